@@ -1,0 +1,249 @@
+"""CPU oracle for the detection path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never does, and it
+shares no code with the HIP library.
+
+Thin ctypes wrapper over ``oracle.cpp`` (plain C++17), plus two helpers that
+chain the steps in the paper's order:
+
+* ``frame(field, ...)``  -- Sec. 3.1 and 3.2.1-3.2.2 on one field
+* ``Sequence``           -- keeps the past frame and applies Sec. 3.2.3-3.2.4
+
+Each function's docstring names the section it follows; the readings of the
+paper that the oracle fixes are stated in ``oracle.cpp``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+MAXLINK = 0x77777777
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile oracle.cpp into liboracle.so beside it (g++, C++17, OpenMP)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-Wall",
+           _SRC, "-o", _LIB + ".tmp"]
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i32, f32, i64 = ctypes.c_int32, ctypes.c_float, ctypes.c_int64
+    lib.or_label.restype = i32
+    lib.or_label.argtypes = [_f32p, i32, i32, f32, i32, i32, _i32p]
+    lib.or_centroids.restype = None
+    lib.or_centroids.argtypes = [_i32p, i32, i32, i32, i32, _i32p, _i32p, _i32p, _i32p,
+                                 _f64p, _f64p, _i32p]
+    lib.or_owner.restype = None
+    lib.or_owner.argtypes = [i32, i32, i32, _i32p, _i32p, _i32p, i32]
+    lib.or_colour_at.restype = i32
+    lib.or_colour_at.argtypes = [i64, i64, i32, i32, i32, _i32p, _i32p]
+    lib.or_edges.restype = i32
+    lib.or_edges.argtypes = [i32, i32, i32, _i32p, _i32p, _i32p, _i32p, i32]
+    lib.or_edges_window.restype = i32
+    lib.or_edges_window.argtypes = [i32, i32, i32, _i32p, _i32p, i32, i32, i32, i32,
+                                    _i32p, i32, i32]
+    lib.or_match.restype = None
+    lib.or_match.argtypes = [i32, i32, i32, _i32p, _i32p, i32, _i32p, _i32p, _i32p, _i32p]
+    lib.or_diff.restype = i32
+    lib.or_diff.argtypes = [i32, i32, _i32p, _i32p, i32, i32, _i32p, _i32p, _i32p, i32,
+                            _i32p, _i32p]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _c32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# --------------------------------------------------------------------- Sec. 3.1
+def label(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8):
+    """Threshold + cluster labelling (Sec. 3.1).  Returns (labels int32 [ly,lx], K)."""
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    ly, lx = f.shape
+    lab = np.empty((ly, lx), dtype=np.int32)
+    K = _load().or_label(_p(f, _f32p), lx, ly, float(threshold), int(phase), int(conn),
+                         _p(lab, _i32p))
+    return lab, int(K)
+
+
+def centroids(labels: np.ndarray, K: int, conn: int = 8) -> dict:
+    """Sizes and centres of mass (Sec. 3.1), exact Q.8 and float64."""
+    lab = _c32(labels)
+    ly, lx = lab.shape
+    out = {k: np.zeros(K, dtype=np.int32) for k in ("n", "root", "qx", "qy", "amb")}
+    out["fx"] = np.zeros(K, dtype=np.float64)
+    out["fy"] = np.zeros(K, dtype=np.float64)
+    if K:
+        _load().or_centroids(_p(lab, _i32p), lx, ly, int(conn), int(K),
+                             _p(out["n"], _i32p), _p(out["root"], _i32p),
+                             _p(out["qx"], _i32p), _p(out["qy"], _i32p),
+                             _p(out["fx"], _f64p), _p(out["fy"], _f64p),
+                             _p(out["amb"], _i32p))
+    return out
+
+
+# ------------------------------------------------------------------- Sec. 3.2.1
+def owner(lx: int, ly: int, qx, qy, nthreads: int = 0) -> np.ndarray:
+    """Digital Voronoi colouring by brute force over all centres (Sec. 3.2.1)."""
+    qx, qy = _c32(qx), _c32(qy)
+    out = np.empty((ly, lx), dtype=np.int32)
+    _load().or_owner(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), _p(out, _i32p),
+                     int(nthreads))
+    return out
+
+
+def colour_at(X: int, Y: int, lx: int, ly: int, qx, qy) -> int:
+    """Colour of one Q.8 point (Sec. 3.2.1 rule at an arbitrary point)."""
+    qx, qy = _c32(qx), _c32(qy)
+    return int(_load().or_colour_at(int(X), int(Y), lx, ly, len(qx), _p(qx, _i32p),
+                                    _p(qy, _i32p)))
+
+
+# ------------------------------------------------------------------- Sec. 3.2.2
+def edges(lx: int, ly: int, qx, qy, owner_map: np.ndarray) -> np.ndarray:
+    """Delaunay couples from Voronoi-vertex sites (Sec. 3.2.2); int32 [E,2], sorted."""
+    qx, qy = _c32(qx), _c32(qy)
+    om = _c32(owner_map)
+    lib = _load()
+    cap = 1 << 12
+    while True:
+        ab = np.empty((cap, 2), dtype=np.int32)
+        E = lib.or_edges(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), _p(om, _i32p),
+                         _p(ab, _i32p), cap)
+        if E <= cap:
+            return ab[:E].copy()
+        cap = E
+
+
+def edges_window(lx: int, ly: int, qx, qy, x0: int, y0: int, w: int, h: int,
+                 nthreads: int = 0) -> np.ndarray:
+    """Couples emitted by the sites of one window, colours by brute force."""
+    qx, qy = _c32(qx), _c32(qy)
+    lib = _load()
+    cap = 1 << 12
+    while True:
+        ab = np.empty((cap, 2), dtype=np.int32)
+        E = lib.or_edges_window(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), x0, y0, w, h,
+                                _p(ab, _i32p), cap, int(nthreads))
+        if E <= cap:
+            return ab[:E].copy()
+        cap = E
+
+
+# ------------------------------------------------------------------- Sec. 3.2.3
+def match(lx: int, ly: int, pqx, pqy, nqx, nqy):
+    """Kinematic isomorphism Phi_{P->N} and preimage counts (Sec. 3.2.3)."""
+    pqx, pqy, nqx, nqy = _c32(pqx), _c32(pqy), _c32(nqx), _c32(nqy)
+    phi = np.empty(len(pqx), dtype=np.int32)
+    cnt = np.empty(len(nqx), dtype=np.int32)
+    _load().or_match(lx, ly, len(pqx), _p(pqx, _i32p), _p(pqy, _i32p), len(nqx),
+                     _p(nqx, _i32p), _p(nqy, _i32p), _p(phi, _i32p), _p(cnt, _i32p))
+    return phi, cnt
+
+
+def diff(KP: int, past_edges, phi, KN: int, now_edges, cnt):
+    """Translation, exclusion and breaking / arising couples (Sec. 3.2.3-3.2.4).
+
+    Returns (flips int32 [F,6] = (a, b, pa, pb, kind, flags), local_trigger [KP],
+    (excluded_past, excluded_now, global_trigger)).
+    """
+    pe = _c32(np.asarray(past_edges).reshape(-1, 2))
+    ne = _c32(np.asarray(now_edges).reshape(-1, 2))
+    phi, cnt = _c32(phi), _c32(cnt)
+    lt = np.zeros(max(KP, 1), dtype=np.int32)
+    counts = np.zeros(3, dtype=np.int32)
+    lib = _load()
+    cap = 256
+    while True:
+        fl = np.empty((cap, 6), dtype=np.int32)
+        F = lib.or_diff(KP, len(pe), _p(pe, _i32p), _p(phi, _i32p), KN, len(ne),
+                        _p(ne, _i32p), _p(cnt, _i32p), _p(fl, _i32p), cap, _p(lt, _i32p),
+                        _p(counts, _i32p))
+        if F <= cap:
+            return fl[:F].copy(), lt[:KP].copy(), tuple(int(c) for c in counts)
+        cap = F
+
+
+# -------------------------------------------------------------- whole frames
+@dataclass
+class FrameResult:
+    labels: np.ndarray
+    K: int
+    comps: dict
+    owner: np.ndarray
+    edges: np.ndarray
+
+
+def frame(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8,
+          nthreads: int = 0) -> FrameResult:
+    """Sec. 3.1 then Sec. 3.2.1-3.2.2 on one field."""
+    lab, K = label(field, threshold, phase, conn)
+    comps = centroids(lab, K, conn)
+    ly, lx = lab.shape
+    om = owner(lx, ly, comps["qx"], comps["qy"], nthreads)
+    ab = edges(lx, ly, comps["qx"], comps["qy"], om)
+    return FrameResult(lab, K, comps, om, ab)
+
+
+@dataclass
+class DiffResult:
+    flips: np.ndarray
+    phi: np.ndarray
+    cnt: np.ndarray
+    local_trigger: np.ndarray
+    excluded_past: int
+    excluded_now: int
+    global_trigger: int
+
+
+class Sequence:
+    """Frame-to-frame driver: the past triangulation is kept between calls."""
+
+    def __init__(self, threshold: float, phase: int = 0, conn: int = 8, nthreads: int = 0):
+        self.threshold, self.phase, self.conn, self.nthreads = threshold, phase, conn, nthreads
+        self.past: FrameResult | None = None
+
+    def push(self, field: np.ndarray):
+        now = frame(field, self.threshold, self.phase, self.conn, self.nthreads)
+        res = compare(self.past, now)
+        self.past = now
+        return now, res
+
+
+def compare(past: FrameResult | None, now: FrameResult) -> DiffResult:
+    """Diff of two frames; with no past frame there is nothing to compare."""
+    if past is None:
+        z = np.zeros(0, dtype=np.int32)
+        return DiffResult(np.zeros((0, 6), np.int32), z, np.zeros(now.K, np.int32), z, 0, 0, 0)
+    ly, lx = now.labels.shape
+    phi, cnt = match(lx, ly, past.comps["qx"], past.comps["qy"], now.comps["qx"],
+                     now.comps["qy"])
+    fl, lt, (exP, exN, g) = diff(past.K, past.edges, phi, now.K, now.edges, cnt)
+    return DiffResult(fl, phi, cnt, lt, exP, exN, g)

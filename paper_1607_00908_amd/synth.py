@@ -1,0 +1,260 @@
+"""Seeded synthetic lattice fields that stand in for the paper's simulation data.
+
+The paper's emulsion fields (lattice-Boltzmann droplets in a 2048x1024 channel,
+Sec. 4) and its random-field sample program (Sec. 1) are not available, so the
+workloads here are generated from a seed.  This module holds input generation
+only: it contains none of the detection method's arithmetic (no thresholding,
+labelling, centroids, tessellation or diffing).  Both the HIP path and the CPU
+oracle consume the same float32 bytes produced here.
+
+Generators
+----------
+* ``DiskSim``   -- polydisperse disks with a tanh interface profile, moved each
+  frame by Gaussian jitter plus simple shear and then relaxed so that no two
+  disks come within ``gap`` lattice units (so they never touch under 8-neighbour
+  connectivity).  Stand-in for the droplet emulsion of Sec. 4.
+* ``GRFSim``    -- periodic Gaussian random field (white noise smoothed by a
+  Gaussian kernel via FFT, standardised), evolved as AR(1).  Thresholding it
+  gives irregular "bubbles" like the random-field sample of Sec. 1.
+* ``tiny_random_field`` -- uniform noise for fuzzing small lattices.
+
+All arithmetic is float64; fields are cast to float32 exactly once.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field as dc_field
+
+import numpy as np
+
+__all__ = [
+    "DiskSim",
+    "GRFSim",
+    "tiny_random_field",
+    "disk_field",
+    "workload",
+    "WORKLOADS",
+]
+
+
+def _wrap_delta(d: np.ndarray, L: float) -> np.ndarray:
+    """Minimum-image displacement on a ring of length L (float64)."""
+    return d - L * np.round(d / L)
+
+
+def disk_field(lx: int, ly: int, centers: np.ndarray, radii: np.ndarray,
+               width: float = 2.0, reach: float = 10.0) -> np.ndarray:
+    """rho(s) = max_i 0.5*(1 - tanh((|s - c_i|_periodic - r_i)/width)).
+
+    Evaluated only within ``r_i + reach`` of each centre (beyond that the
+    profile is below 5e-5 and is taken as 0).  Returns float32 [ly, lx].
+    """
+    rho = np.zeros((ly, lx), dtype=np.float64)
+    if len(radii) == 0:
+        return rho.astype(np.float32)
+    rmax = float(np.max(radii)) + reach
+    span = int(math.ceil(rmax)) + 1
+    off = np.arange(-span, span + 1)
+    P = off.size
+    cx = centers[:, 0]
+    cy = centers[:, 1]
+    bx = np.floor(cx).astype(np.int64)
+    by = np.floor(cy).astype(np.int64)
+    dx = (bx[:, None] + off[None, :]) - cx[:, None]          # [K, P]
+    dy = (by[:, None] + off[None, :]) - cy[:, None]          # [K, P]
+    dist = np.sqrt(dy[:, :, None] ** 2 + dx[:, None, :] ** 2)  # [K, P(y), P(x)]
+    val = 0.5 * (1.0 - np.tanh((dist - radii[:, None, None]) / width))
+    val[dist > (radii[:, None, None] + reach)] = 0.0
+    if P <= lx and P <= ly:
+        # each patch touches P distinct rows and columns: max-combine in place
+        for i in range(len(radii)):
+            x0 = int(bx[i]) - span
+            y0 = int(by[i]) - span
+            if 0 <= x0 and x0 + P <= lx and 0 <= y0 and y0 + P <= ly:
+                sub = rho[y0:y0 + P, x0:x0 + P]
+                np.maximum(sub, val[i], out=sub)
+            else:
+                iy = np.mod(np.arange(y0, y0 + P), ly)
+                ix = np.mod(np.arange(x0, x0 + P), lx)
+                blk = np.ix_(iy, ix)
+                rho[blk] = np.maximum(rho[blk], val[i])
+        return rho.astype(np.float32)
+    # tiny lattice: a patch wraps onto itself; combine by sorting (site, value)
+    sx = np.mod(bx[:, None, None] + off[None, None, :], lx) + 0 * off[None, :, None]
+    sy = np.mod(by[:, None, None] + off[None, :, None], ly) + 0 * off[None, None, :]
+    flat = (sy * lx + sx).ravel()
+    v = val.ravel()
+    order = np.lexsort((v, flat))
+    fs = flat[order]
+    vs = v[order]
+    last = np.ones(fs.shape, dtype=bool)
+    last[:-1] = fs[1:] != fs[:-1]
+    out = rho.ravel()
+    out[fs[last]] = vs[last]
+    return out.reshape(ly, lx).astype(np.float32)
+
+
+@dataclass
+class DiskSim:
+    """Polydisperse disks under jitter + simple shear with overlap relaxation."""
+
+    lx: int
+    ly: int
+    n_disks: int
+    r_min: float
+    r_max: float
+    sigma: float          # per-axis Gaussian jitter per frame (lattice units)
+    shear: float          # dx = shear * (y - ly/2) per frame
+    seed: int
+    gap: float = 2.0      # minimum surface-to-surface distance kept between disks
+    width: float = 2.0    # tanh interface width
+    relax_iters: int = 200
+    centers: np.ndarray = dc_field(init=False, repr=False)
+    radii: np.ndarray = dc_field(init=False, repr=False)
+    rng: np.random.Generator = dc_field(init=False, repr=False)
+
+    def __post_init__(self):
+        self.rng = np.random.default_rng(self.seed)
+        self.radii = self.rng.uniform(self.r_min, self.r_max, self.n_disks)
+        self.centers = np.stack([
+            self.rng.uniform(0, self.lx, self.n_disks),
+            self.rng.uniform(0, self.ly, self.n_disks)], axis=1)
+        self._relax()
+
+    def _relax(self):
+        """Jacobi relaxation: push every overlapping pair apart symmetrically."""
+        from scipy.spatial import cKDTree
+        c = self.centers
+        r = self.radii
+        reach = 2.0 * float(np.max(r)) + self.gap if len(r) else 0.0
+        box = np.array([self.lx, self.ly], dtype=np.float64)
+        for _ in range(self.relax_iters):
+            c[:, 0] %= self.lx
+            c[:, 1] %= self.ly
+            tree = cKDTree(c, boxsize=box)
+            pairs = tree.query_pairs(reach, output_type="ndarray")
+            if pairs.size == 0:
+                break
+            i, j = pairs[:, 0], pairs[:, 1]
+            dx = _wrap_delta(c[i, 0] - c[j, 0], self.lx)
+            dy = _wrap_delta(c[i, 1] - c[j, 1], self.ly)
+            d = np.sqrt(dx * dx + dy * dy)
+            over = r[i] + r[j] + self.gap - d
+            m = over > 0
+            if not np.any(m):
+                break
+            i, j, dx, dy, d, over = i[m], j[m], dx[m], dy[m], d[m], over[m]
+            # small margin so that relaxed pairs do not sit exactly on the limit
+            push = 0.5 * (over + 1e-3)
+            dsafe = np.where(d > 1e-9, d, 1.0)
+            ux = np.where(d > 1e-9, dx / dsafe, 1.0)
+            uy = np.where(d > 1e-9, dy / dsafe, 0.0)
+            mv = np.zeros_like(c)
+            np.add.at(mv[:, 0], i, push * ux)
+            np.add.at(mv[:, 1], i, push * uy)
+            np.add.at(mv[:, 0], j, -push * ux)
+            np.add.at(mv[:, 1], j, -push * uy)
+            c += mv
+        c[:, 0] %= self.lx
+        c[:, 1] %= self.ly
+        self.centers = c
+
+    def field(self) -> np.ndarray:
+        return disk_field(self.lx, self.ly, self.centers, self.radii, self.width)
+
+    def step(self):
+        c = self.centers
+        c += self.rng.normal(0.0, self.sigma, c.shape)
+        c[:, 0] += self.shear * (c[:, 1] - self.ly / 2.0)
+        c[:, 0] %= self.lx
+        c[:, 1] %= self.ly
+        self.centers = c
+        self._relax()
+
+    def frames(self, n: int):
+        """Yield n float32 fields; frame 0 is the initial placement."""
+        for t in range(n):
+            if t:
+                self.step()
+            yield self.field()
+
+
+def _smooth_noise(rng: np.random.Generator, lx: int, ly: int, sigma: float,
+                  workers: int) -> np.ndarray:
+    import scipy.fft as sfft
+    g = rng.standard_normal((ly, lx))
+    fy = np.fft.fftfreq(ly)[:, None]
+    fx = np.fft.rfftfreq(lx)[None, :]
+    kern = np.exp(-2.0 * (math.pi ** 2) * sigma * sigma * (fx * fx + fy * fy))
+    s = sfft.irfft2(sfft.rfft2(g, workers=workers) * kern, s=(ly, lx), workers=workers)
+    s -= s.mean()
+    s /= s.std()
+    return s
+
+
+@dataclass
+class GRFSim:
+    """Periodic Gaussian random field evolved as AR(1): f' = rho f + sqrt(1-rho^2) g."""
+
+    lx: int
+    ly: int
+    sigma: float
+    rho: float
+    seed: int
+    workers: int = -1
+    f: np.ndarray = dc_field(init=False, repr=False)
+    rng: np.random.Generator = dc_field(init=False, repr=False)
+
+    def __post_init__(self):
+        self.rng = np.random.default_rng(self.seed)
+        self.f = _smooth_noise(self.rng, self.lx, self.ly, self.sigma, self.workers)
+
+    def field(self) -> np.ndarray:
+        return self.f.astype(np.float32)
+
+    def step(self):
+        g = _smooth_noise(self.rng, self.lx, self.ly, self.sigma, self.workers)
+        self.f = self.rho * self.f + math.sqrt(1.0 - self.rho * self.rho) * g
+
+    def frames(self, n: int):
+        for t in range(n):
+            if t:
+                self.step()
+            yield self.field()
+
+
+def tiny_random_field(lx: int, ly: int, seed: int) -> np.ndarray:
+    """Uniform [0,1) float32 noise; thresholding it at p gives site percolation."""
+    return np.random.default_rng(seed).random((ly, lx)).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.  Each entry: constructor, frame count, threshold, phase
+# (0: inside means rho > threshold, droplets; 1: rho < threshold, bubbles).
+# ---------------------------------------------------------------------------
+WORKLOADS = {
+    # 256^2, 64 disks r~U(8,12), jitter 0.3, shear 1e-3, 10 frames
+    "disks256": dict(kind="disks", lx=256, ly=256, n_disks=64, r_min=8.0, r_max=12.0,
+                     sigma=0.3, shear=1e-3, seed=1, frames=10, threshold=0.5, phase=0),
+    # 1024^2, 1000 disks r~U(10,16), jitter 0.2, shear 5e-4, 100 frames
+    "disks1024": dict(kind="disks", lx=1024, ly=1024, n_disks=1000, r_min=10.0, r_max=16.0,
+                      sigma=0.2, shear=5e-4, seed=2, frames=100, threshold=0.5, phase=0),
+    # 4096^2 Gaussian random field, smoothing sigma 6, AR(1) rho 0.98, 50 frames,
+    # thresholded at +1 std
+    "grf4096": dict(kind="grf", lx=4096, ly=4096, sigma=6.0, rho=0.98, seed=3,
+                    frames=50, threshold=1.0, phase=0),
+}
+
+
+def workload(name: str, **override):
+    """Return (simulator, spec) for a named workload; ``override`` edits the spec."""
+    spec = dict(WORKLOADS[name])
+    spec.update(override)
+    if spec["kind"] == "disks":
+        sim = DiskSim(spec["lx"], spec["ly"], spec["n_disks"], spec["r_min"], spec["r_max"],
+                      spec["sigma"], spec["shear"], spec["seed"])
+    elif spec["kind"] == "grf":
+        sim = GRFSim(spec["lx"], spec["ly"], spec["sigma"], spec["rho"], spec["seed"])
+    else:
+        raise ValueError(spec["kind"])
+    return sim, spec
