@@ -1,0 +1,169 @@
+/*
+ * dv.h -- C ABI of the GPU detector of topological changes in dynamic lattice
+ * Voronoi diagrams (Bernaschi, Lulli, Sbragaglia, "GPU Based Detection of
+ * Topological Changes in Voronoi Diagrams", arXiv:1607.00908).
+ *
+ * One context follows one sequence of lattice fields (one simulation stream).
+ * Each pushed field goes through the paper's procedure on the GPU:
+ *   Sec. 3.1    threshold, cluster labelling, sizes and centres of mass
+ *   Sec. 3.2.1  digital Voronoi colouring of the lattice by the centres
+ *   Sec. 3.2.2  Voronoi-vertex sites (frame gaps) and the neighbour rules that
+ *               give the Delaunay couples, compressed into sorted rows
+ *   Sec. 3.2.3  kinematic isomorphism Phi_{P->N} between the previous ("past")
+ *               and the current ("now") centres, translation of the past rows,
+ *               row compare (local / global trigger), exclusion of bubbles that
+ *               appear or disappear
+ *   Sec. 3.2.4  breaking and arising couples (edge flips)
+ *
+ * Conventions fixed by this library where the paper leaves them open:
+ *   - lattice: lx * ly sites, site (x, y) at linear index y*lx + x, periodic
+ *     in both axes; connectivity 8 (the D2Q9 directions) or 4;
+ *   - inside: rho > threshold (phase DV_PHASE_ABOVE, droplets) or
+ *     rho < threshold (DV_PHASE_BELOW, bubbles); equality and NaN are outside;
+ *   - labels 0..K-1 in increasing order of each component's smallest linear
+ *     index, DV_NO_LABEL (-1) outside;
+ *   - centres: unweighted mean of the member sites, offsets taken from the
+ *     smallest-index member with the signed minimum image in
+ *     [-floor(L/2), L-1-floor(L/2)]; Q.8 value (units of 1/256 site) =
+ *     256*r + floor((512*S + n) / (2n)) mod 256L (exact integers);
+ *   - colouring: squared periodic distance between Q.8 points in exact
+ *     integers, ties to the lowest label;
+ *   - inner-frame points of the second-neighbour rule: the four half-integer
+ *     points (x +/- 1/2, y +/- 1/2);
+ *   - matching: nearest now centre of each past centre (exact, ties to the
+ *     lowest label); a past point is kept when its image has exactly one
+ *     preimage, a now point when it has exactly one preimage; couples that
+ *     touch a dropped point are ignored on both sides.
+ *
+ * Threading: a context is used by one host thread at a time.  Distinct
+ * contexts are independent, also on one device.
+ * Errors: every call returns a dv_status; no call writes partial results to
+ * caller memory.  Argument errors are found on the host before any device work.
+ */
+#ifndef DV_H
+#define DV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Colour of "no cell" and row padding value (Sec. 3.2.1, footnote on MAXLINK). */
+#define DV_MAXLINK 0x77777777
+#define DV_NO_LABEL (-1)
+
+/* flags */
+#define DV_KEEP_MAPS 1u  /* label / owner maps stay readable after each push */
+
+typedef enum {
+    DV_OK = 0,
+    DV_ERR_ARG = 1,       /* invalid argument or configuration               */
+    DV_ERR_CAPACITY = 2,  /* a configured capacity was exceeded (see below)   */
+    DV_ERR_NOMEM = 3,     /* device or host allocation failed                 */
+    DV_ERR_DEVICE = 4,    /* a HIP call failed                                */
+    DV_ERR_STATE = 5,     /* call not valid in the current state              */
+    DV_ERR_INTERNAL = 6
+} dv_status;
+
+typedef enum { DV_PHASE_ABOVE = 0, DV_PHASE_BELOW = 1 } dv_phase;
+
+typedef struct dv_ctx dv_ctx;
+
+typedef struct {
+    uint32_t size;           /* = sizeof(dv_config); guards the ABI                */
+    int32_t lx, ly;          /* lattice, each >= 3, lx*ly < 2^31, each <= 65536     */
+    float threshold;         /* inside / outside threshold on the field            */
+    int32_t phase;           /* dv_phase                                           */
+    int32_t connectivity;    /* 8 (default) or 4                                   */
+    int32_t max_components;  /* K_max, 1 .. 2^24; device memory is sized from it   */
+    int32_t max_degree;      /* row capacity of the adjacency (Delaunay degree),
+                                4 .. 256; 0 selects 48                             */
+    int32_t device;          /* HIP device ordinal                                 */
+    uint32_t flags;          /* DV_KEEP_MAPS                                       */
+} dv_config;
+
+/* One edge flip (Sec. 3.2.4).  a < b are now labels; pa, pb the past labels
+ * with Phi(pa) = a and Phi(pb) = b.  kind = -1 breaking (couple only in the
+ * past triangulation), +1 arising (only in the now triangulation).  flags is
+ * reserved and 0.  Flips are ordered breaking first, then arising, each by
+ * (a, b) ascending. */
+typedef struct {
+    int32_t a, b;
+    int32_t pa, pb;
+    int32_t kind;
+    uint32_t flags;
+} dv_flip;
+
+/* Summary of the most recent push. */
+typedef struct {
+    int64_t frame;                  /* frames accepted so far                          */
+    int32_t status;                 /* dv_status of the most recent push               */
+    int32_t n_components;           /* K of the most recent push (may exceed K_max
+                                       when status is DV_ERR_CAPACITY)                  */
+    int32_t n_edges;                /* E: undirected Delaunay couples                   */
+    int32_t n_flips;
+    int32_t n_breaking;
+    int32_t n_excluded_past;        /* past points dropped by the isomorphism          */
+    int32_t n_excluded_now;         /* now points with no or several preimages          */
+    int32_t n_ambiguous_centroids;  /* components crossing their own antipodal line    */
+    uint32_t global_trigger;        /* 1 when any row changed (Sec. 3.2.3)             */
+} dv_frame_info;
+
+/* Create a context on cfg->device.  hip_stream is a hipStream_t on that
+ * device, or NULL for a stream the context creates (and destroys).  All
+ * device work of the context is ordered on that stream.  On success *out
+ * owns every device buffer; on failure *out is NULL. */
+dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
+
+/* Enqueue one frame.  field_device: lx*ly float32 values in device memory,
+ * row-major (x fastest).  The field is read asynchronously on the context's
+ * stream: the caller keeps it alive and unmodified until the next
+ * synchronising call (dv_get_flips, dv_get_info, any getter, dv_sync).
+ * The first accepted frame has no past and yields no flips.  A frame whose
+ * component count exceeds K_max, or whose Delaunay degree exceeds the row
+ * capacity, is rejected: the next synchronising call reports
+ * DV_ERR_CAPACITY and the past state stays that of the last accepted frame. */
+dv_status dv_push_frame(dv_ctx *ctx, const float *field_device);
+
+/* Wait for the stream and copy the flips of the most recent push.  When
+ * capacity is smaller than the count, *n_out receives the count, nothing is
+ * written and DV_ERR_CAPACITY is returned. */
+dv_status dv_get_flips(dv_ctx *ctx, dv_flip *host_out, int32_t capacity, int32_t *n_out);
+
+/* Wait for the stream; fill *info for the most recent push.  Returns the
+ * status of that push (DV_OK or DV_ERR_CAPACITY); *info is filled either way. */
+dv_status dv_get_info(dv_ctx *ctx, dv_frame_info *info);
+
+/* Wait for the context's stream. */
+dv_status dv_sync(dv_ctx *ctx);
+
+/* Release everything the context owns.  NULL is accepted. */
+void dv_destroy(dv_ctx *ctx);
+
+/* ---- inspection (all synchronise; host outputs; state of the most recent
+ * push, which must have been accepted, else its error is returned) ---- */
+
+/* Label map, lx*ly int32.  Needs DV_KEEP_MAPS (else DV_ERR_STATE). */
+dv_status dv_get_labels(dv_ctx *ctx, int32_t *host_out);
+/* Voronoi owner (colour) map, lx*ly int32.  Needs DV_KEEP_MAPS. */
+dv_status dv_get_owner(dv_ctx *ctx, int32_t *host_out);
+/* Components: q8_xy[2k], [2k+1] Q.8 centre; xy[2k], [2k+1] float64 centre;
+ * size[k] member count; any output pointer may be NULL. */
+dv_status dv_get_components(dv_ctx *ctx, int32_t *q8_xy, double *xy, int32_t *size,
+                            int32_t capacity, int32_t *n_out);
+/* Undirected couples ab[2e] < ab[2e+1], sorted by (a, b). */
+dv_status dv_get_edges(dv_ctx *ctx, int32_t *ab, int32_t capacity, int32_t *n_out);
+/* Phi of the most recent comparison indexed by past label; -1 for dropped
+ * past points; *n_out = K of the past frame (0 for the first frame). */
+dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *n_out);
+
+const char *dv_status_str(dv_status s);
+/* Text of the last error on this context ("" when none).  NULL ctx: text of
+ * the last dv_create failure in this process. */
+const char *dv_last_error(const dv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DV_H */

@@ -83,22 +83,24 @@ struct UF {
 const int NB8[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
 const int NB4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
 
-// Squared periodic distance in Q.8 units between (X1,Y1) and (X2,Y2).
-int64_t dist2_q8(int64_t X1, int64_t Y1, int64_t X2, int64_t Y2, int lx, int ly) {
-    const int64_t dx = wrap_signed(X1 - X2, 256LL * lx);
-    const int64_t dy = wrap_signed(Y1 - Y2, 256LL * ly);
-    return dx * dx + dy * dy;
-}
-
 // Sec. 3.2.1: colour = label of the nearest centre by squared Euclidean
 // distance.  Reading: exact integer distance between Q.8 points with the
 // periodic minimum image; ties go to the lowest label; no centre -> MAXLINK.
+// The query point is first brought into [0, 256 L); then every difference to
+// a centre lies in (-256 L, 256 L) and one conditional shift gives the same
+// minimum image as wrap_signed.
 int32_t nearest_centre(int64_t X, int64_t Y, int K, const int32_t* qx, const int32_t* qy,
                        int lx, int ly) {
+    const int64_t MX = 256LL * lx, MY = 256LL * ly, hx = MX / 2, hy = MY / 2;
+    X = pos_mod(X, MX);
+    Y = pos_mod(Y, MY);
     int32_t best = MAXLINK;
     int64_t bd = INT64_MAX;
     for (int i = 0; i < K; ++i) {
-        const int64_t d = dist2_q8(X, Y, qx[i], qy[i], lx, ly);
+        int64_t dx = X - qx[i], dy = Y - qy[i];
+        if (dx >= MX - hx) dx -= MX; else if (dx < -hx) dx += MX;
+        if (dy >= MY - hy) dy -= MY; else if (dy < -hy) dy += MY;
+        const int64_t d = dx * dx + dy * dy;
         if (d < bd) { bd = d; best = i; }
     }
     return best;

@@ -1,0 +1,18 @@
+"""MI355X-native detection of topological changes in dynamic lattice Voronoi
+diagrams (Bernaschi, Lulli, Sbragaglia, arXiv:1607.00908).
+
+* ``dv``     -- binding of the HIP library libdv.so (C ABI in include/dv.h)
+* ``synth``  -- seeded synthetic workloads (input generation only)
+
+Submodules are imported on demand so that the workload generators can be used
+without loading the GPU library.
+"""
+
+__all__ = ["dv", "synth"]
+
+
+def __getattr__(name):
+    if name in __all__:
+        import importlib
+        return importlib.import_module(f"{__name__}.{name}")
+    raise AttributeError(name)

@@ -1,0 +1,359 @@
+// Host side of libdv: the C ABI declared in include/dv.h.
+//
+// A context owns every device buffer, sized once from the lattice and K_max,
+// and enqueues the whole per-frame procedure on one HIP stream without any
+// host synchronisation.  Synchronising calls copy the device frame header
+// (and the requested arrays) back through pinned host memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dv.h"
+#include "dv_internal.h"
+
+struct dv_ctx {
+    dv_config cfg;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    Bufs B;
+    std::vector<void *> allocs;
+    DevState *h_state;       // pinned mirror of the device header
+    int32_t *d_edge_scratch; // [2 * K_max] for the couple-list getter
+    int32_t *d_edge_ab;      // [K_max * max_degree] pairs
+    int32_t *d_edge_total;
+    bool pushed;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+dv_status fail(dv_ctx *c, dv_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+template <class T>
+bool dalloc(dv_ctx *c, T **p, size_t count) {
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    c->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return true;
+}
+
+void release(dv_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+dv_status check_cfg(const dv_config *cfg) {
+    if (!cfg) return fail(nullptr, DV_ERR_ARG, "config is NULL");
+    if (cfg->size != sizeof(dv_config)) return fail(nullptr, DV_ERR_ARG, "config size mismatch");
+    if (cfg->lx < 3 || cfg->ly < 3 || cfg->lx > 65536 || cfg->ly > 65536)
+        return fail(nullptr, DV_ERR_ARG, "lattice sides must be in [3, 65536]");
+    if ((long long)cfg->lx * cfg->ly >= (1LL << 31))
+        return fail(nullptr, DV_ERR_ARG, "lattice has 2^31 sites or more");
+    if (cfg->phase != DV_PHASE_ABOVE && cfg->phase != DV_PHASE_BELOW)
+        return fail(nullptr, DV_ERR_ARG, "phase must be DV_PHASE_ABOVE or DV_PHASE_BELOW");
+    if (cfg->connectivity != 4 && cfg->connectivity != 8)
+        return fail(nullptr, DV_ERR_ARG, "connectivity must be 4 or 8");
+    if (cfg->max_components < 1 || cfg->max_components > (1 << 24))
+        return fail(nullptr, DV_ERR_ARG, "max_components must be in [1, 2^24]");
+    if (cfg->max_degree != 0 && (cfg->max_degree < 4 || cfg->max_degree > 64))
+        return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
+    if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
+    if (cfg->flags & ~DV_KEEP_MAPS) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
+    return DV_OK;
+}
+
+dv_status sync_state(dv_ctx *c) {
+    if (hipMemcpyAsync(c->h_state, c->B.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
+    return DV_OK;
+}
+
+// synchronise and require an accepted most recent push
+dv_status ready(dv_ctx *c) {
+    if (!c) return DV_ERR_ARG;
+    if (!c->pushed) return fail(c, DV_ERR_STATE, "no frame has been pushed");
+    (void)hipSetDevice(c->device);
+    dv_status s = sync_state(c);
+    if (s != DV_OK) return s;
+    if (c->h_state->status != 0) return fail(c, (dv_status)c->h_state->status, "most recent frame was rejected (capacity)");
+    return DV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
+    if (!out) return fail(nullptr, DV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    dv_status s = check_cfg(cfg_in);
+    if (s != DV_OK) return s;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return fail(nullptr, DV_ERR_DEVICE, "no HIP device");
+    if (cfg_in->device < 0 || cfg_in->device >= ndev)
+        return fail(nullptr, DV_ERR_ARG, "device ordinal out of range");
+
+    dv_ctx *c = new dv_ctx();
+    c->cfg = *cfg_in;
+    if (c->cfg.max_degree == 0) c->cfg.max_degree = 48;
+    c->device = c->cfg.device;
+    if (hipSetDevice(c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, DV_ERR_DEVICE, "stream creation failed");
+        }
+        c->own_stream = true;
+    }
+    Bufs &B = c->B;
+    std::memset(&B, 0, sizeof(B));
+    B.lx = c->cfg.lx;
+    B.ly = c->cfg.ly;
+    B.ntx = (B.lx + DV_TILE - 1) / DV_TILE;
+    B.nty = (B.ly + DV_TILE - 1) / DV_TILE;
+    B.thr = c->cfg.threshold;
+    B.phase = c->cfg.phase;
+    B.conn = c->cfg.connectivity;
+    B.kmax = c->cfg.max_components;
+    B.maxdeg = c->cfg.max_degree;
+    B.ncells = B.ntx * B.nty;
+    B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
+    const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
+    const size_t segs = (size_t)B.ly * B.ntx;
+    bool ok = dalloc(c, &B.parent, N) && dalloc(c, &B.pieces, tiles * DV_TILE_SITES) &&
+              dalloc(c, &B.npieces, tiles) && dalloc(c, &B.seg_mask, segs) &&
+              dalloc(c, &B.seg_prefix, segs) && dalloc(c, &B.band_sum, (size_t)B.nty) &&
+              dalloc(c, &B.acc_x, K) && dalloc(c, &B.acc_y, K) && dalloc(c, &B.acc_n, K) &&
+              dalloc(c, &B.acc_amb, K) && dalloc(c, &B.acc_root, K) &&
+              dalloc(c, &B.cell_count, tiles) && dalloc(c, &B.cell_start, tiles + 1) &&
+              dalloc(c, &B.cell_items, K) && dalloc(c, &B.cell_q, K) &&
+              dalloc(c, &B.comp_cell, K) && dalloc(c, &B.comp_slot, K) && dalloc(c, &B.phi, K) &&
+              dalloc(c, &B.cnt, K) && dalloc(c, &B.inv, K) && dalloc(c, &B.trigger, K) &&
+              dalloc(c, &B.nb, K) && dalloc(c, &B.na, K) && dalloc(c, &B.ob, K) &&
+              dalloc(c, &B.oa, K) && dalloc(c, &B.flips, K * B.maxdeg * 6) &&
+              dalloc(c, &B.st, 1) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
+              dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
+    if (ok && B.keep_maps) ok = dalloc(c, &B.labels, N) && dalloc(c, &B.owner, N);
+    for (int b = 0; ok && b < 2; ++b) {
+        CompBuf &C = B.comp[b];
+        ok = dalloc(c, &C.qx, K) && dalloc(c, &C.qy, K) && dalloc(c, &C.fx, K) &&
+             dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
+             dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg) && dalloc(c, &C.deg, K);
+    }
+    if (ok && hipHostMalloc((void **)&c->h_state, sizeof(DevState)) != hipSuccess) ok = false;
+    if (!ok) {
+        release(c);
+        delete c;
+        return fail(nullptr, DV_ERR_NOMEM, "device allocation failed");
+    }
+    // initial contents: zero accumulators and header, empty rows
+    bool z = hipMemsetAsync(B.acc_x, 0, K * sizeof(long long), c->stream) == hipSuccess &&
+             hipMemsetAsync(B.acc_y, 0, K * sizeof(long long), c->stream) == hipSuccess &&
+             hipMemsetAsync(B.acc_n, 0, K * sizeof(int), c->stream) == hipSuccess &&
+             hipMemsetAsync(B.acc_amb, 0, K * sizeof(int), c->stream) == hipSuccess &&
+             hipMemsetAsync(B.st, 0, sizeof(DevState), c->stream) == hipSuccess;
+    for (int b = 0; z && b < 2; ++b)
+        z = hipMemsetD32Async((hipDeviceptr_t)B.comp[b].adj, DV_EMPTY, K * B.maxdeg, c->stream) ==
+                hipSuccess &&
+            hipMemsetAsync(B.comp[b].deg, 0, K * sizeof(int), c->stream) == hipSuccess;
+    if (!z || hipStreamSynchronize(c->stream) != hipSuccess) {
+        release(c);
+        delete c;
+        return fail(nullptr, DV_ERR_DEVICE, "device initialisation failed");
+    }
+    c->pushed = false;
+    *out = c;
+    return DV_OK;
+}
+
+dv_status dv_push_frame(dv_ctx *c, const float *field_device) {
+    if (!c) return DV_ERR_ARG;
+    if (!field_device) return fail(c, DV_ERR_ARG, "field is NULL");
+    (void)hipSetDevice(c->device);
+    c->B.field = field_device;
+    launch_label(c->B, c->stream);
+    launch_voronoi(c->B, c->stream);
+    launch_diff(c->B, c->stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    c->pushed = true;
+    return DV_OK;
+}
+
+dv_status dv_sync(dv_ctx *c) {
+    if (!c) return DV_ERR_ARG;
+    (void)hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    return DV_OK;
+}
+
+dv_status dv_get_info(dv_ctx *c, dv_frame_info *info) {
+    if (!c || !info) return DV_ERR_ARG;
+    if (!c->pushed) return fail(c, DV_ERR_STATE, "no frame has been pushed");
+    (void)hipSetDevice(c->device);
+    dv_status s = sync_state(c);
+    if (s != DV_OK) return s;
+    const DevState &h = *c->h_state;
+    dv_frame_info fi;
+    std::memset(&fi, 0, sizeof(fi));
+    fi.frame = h.frame;
+    fi.status = h.status;
+    fi.n_components = h.K_now;
+    fi.n_edges = h.status == 0 ? h.E[h.sel] : 0;
+    fi.n_flips = h.n_flips;
+    fi.n_breaking = h.n_break;
+    fi.n_excluded_past = h.n_excl_past;
+    fi.n_excluded_now = h.n_excl_now;
+    fi.n_ambiguous_centroids = h.n_amb;
+    fi.global_trigger = (uint32_t)h.global_trigger;
+    *info = fi;
+    return (dv_status)h.status;
+}
+
+dv_status dv_get_flips(dv_ctx *c, dv_flip *host_out, int32_t capacity, int32_t *n_out) {
+    if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    const int n = c->h_state->n_flips;
+    *n_out = n;
+    if (n > capacity) return fail(c, DV_ERR_CAPACITY, "flip buffer too small");
+    if (n > 0) {
+        if (!host_out) return fail(c, DV_ERR_ARG, "host_out is NULL");
+        if (hipMemcpy(host_out, c->B.flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, DV_ERR_DEVICE, "copy failed");
+    }
+    return DV_OK;
+}
+
+dv_status dv_get_labels(dv_ctx *c, int32_t *host_out) {
+    if (!c || !host_out) return DV_ERR_ARG;
+    if (!c->B.keep_maps) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    const size_t N = (size_t)c->B.lx * c->B.ly;
+    if (hipMemcpy(host_out, c->B.labels, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, "copy failed");
+    return DV_OK;
+}
+
+dv_status dv_get_owner(dv_ctx *c, int32_t *host_out) {
+    if (!c || !host_out) return DV_ERR_ARG;
+    if (!c->B.keep_maps) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    const size_t N = (size_t)c->B.lx * c->B.ly;
+    if (hipMemcpy(host_out, c->B.owner, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, "copy failed");
+    return DV_OK;
+}
+
+dv_status dv_get_components(dv_ctx *c, int32_t *q8_xy, double *xy, int32_t *size, int32_t capacity,
+                            int32_t *n_out) {
+    if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    const DevState &h = *c->h_state;
+    const int K = h.K[h.sel];
+    *n_out = K;
+    if (K > capacity) return fail(c, DV_ERR_CAPACITY, "component buffer too small");
+    if (K == 0) return DV_OK;
+    const CompBuf &C = c->B.comp[h.sel];
+    std::vector<int32_t> qx(K), qy(K);
+    std::vector<double> fx(K), fy(K);
+    bool ok = hipMemcpy(qx.data(), C.qx, K * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(qy.data(), C.qy, K * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(fx.data(), C.fx, K * 8, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(fy.data(), C.fy, K * 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (ok && size) ok = hipMemcpy(size, C.n, K * 4, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) return fail(c, DV_ERR_DEVICE, "copy failed");
+    for (int k = 0; k < K; ++k) {
+        if (q8_xy) { q8_xy[2 * k] = qx[k]; q8_xy[2 * k + 1] = qy[k]; }
+        if (xy) { xy[2 * k] = fx[k]; xy[2 * k + 1] = fy[k]; }
+    }
+    return DV_OK;
+}
+
+dv_status dv_get_edges(dv_ctx *c, int32_t *ab, int32_t capacity, int32_t *n_out) {
+    if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    launch_edge_list(c->B, c->d_edge_ab, c->d_edge_total, c->d_edge_scratch, c->stream);
+    int32_t E = 0;
+    if (hipMemcpyAsync(&E, c->d_edge_total, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, "edge list failed");
+    *n_out = E;
+    if (E > capacity) return fail(c, DV_ERR_CAPACITY, "edge buffer too small");
+    if (E > 0) {
+        if (!ab) return fail(c, DV_ERR_ARG, "ab is NULL");
+        if (hipMemcpy(ab, c->d_edge_ab, (size_t)E * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, DV_ERR_DEVICE, "copy failed");
+    }
+    return DV_OK;
+}
+
+dv_status dv_get_matching(dv_ctx *c, int32_t *phi, int32_t capacity, int32_t *n_out) {
+    if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
+    dv_status s = ready(c);
+    if (s != DV_OK) return s;
+    const int KP = c->h_state->K_past_cmp;
+    *n_out = KP;
+    if (KP > capacity) return fail(c, DV_ERR_CAPACITY, "matching buffer too small");
+    if (KP == 0) return DV_OK;
+    if (!phi) return fail(c, DV_ERR_ARG, "phi is NULL");
+    if (hipMemcpy(phi, c->B.phi, (size_t)KP * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, "copy failed");
+    return DV_OK;
+}
+
+void dv_destroy(dv_ctx *c) {
+    if (!c) return;
+    release(c);
+    delete c;
+}
+
+const char *dv_status_str(dv_status s) {
+    switch (s) {
+        case DV_OK: return "ok";
+        case DV_ERR_ARG: return "invalid argument";
+        case DV_ERR_CAPACITY: return "capacity exceeded";
+        case DV_ERR_NOMEM: return "out of memory";
+        case DV_ERR_DEVICE: return "device error";
+        case DV_ERR_STATE: return "invalid state";
+        case DV_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char *dv_last_error(const dv_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Device helpers shared by the HIP sources of libdv: exact periodic Q.8
+// distances and the bucket grid of centres (one cell per 32x32 tile).
+#pragma once
+
+#include "dv_internal.h"
+
+// v in (-M, M) -> signed minimum image in [-M/2, M/2 - 1]  (M = 256 L, even)
+__device__ __forceinline__ int wrap_q(int v, int M) {
+    const int h = M >> 1;
+    if (v >= h) v -= M;
+    else if (v < -h) v += M;
+    return v;
+}
+
+// squared periodic distance between Q.8 points; X, Y, cx, cy in [0, M)
+__device__ __forceinline__ long long d2q(int X, int Y, int cx, int cy, int MX, int MY) {
+    const int dx = wrap_q(X - cx, MX), dy = wrap_q(Y - cy, MY);
+    return (long long)dx * dx + (long long)dy * dy;
+}
+
+__device__ __forceinline__ int pmod(int v, int m) {
+    const int r = v % m;
+    return r < 0 ? r + m : r;
+}
+
+// Up to two ranges of cell indices along one axis.
+struct Span {
+    int lo[2], hi[2];
+    int n;
+};
+
+// Cells whose sites meet the periodic site interval [a, b] (integers, a <= b).
+__device__ __forceinline__ Span span_sites(int a, int b, int L) {
+    Span s;
+    const int ncell = (L + DV_TILE - 1) / DV_TILE;
+    if (b - a >= L - 1) {
+        s.n = 1; s.lo[0] = 0; s.hi[0] = ncell - 1;
+        return s;
+    }
+    a = pmod(a, L);
+    b = pmod(b, L);
+    if (a <= b) {
+        s.n = 1; s.lo[0] = a / DV_TILE; s.hi[0] = b / DV_TILE;
+    } else {
+        s.n = 2; s.lo[0] = a / DV_TILE; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b / DV_TILE;
+    }
+    return s;
+}
+
+// Cells within Chebyshev cell distance R of cell c (periodic, no repeats).
+__device__ __forceinline__ Span span_cells(int c, int R, int ncell) {
+    Span s;
+    if (2 * R + 1 >= ncell) {
+        s.n = 1; s.lo[0] = 0; s.hi[0] = ncell - 1;
+        return s;
+    }
+    const int a = c - R, b = c + R;
+    if (a < 0) {
+        s.n = 2; s.lo[0] = a + ncell; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b;
+    } else if (b >= ncell) {
+        s.n = 2; s.lo[0] = a; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b - ncell;
+    } else {
+        s.n = 1; s.lo[0] = a; s.hi[0] = b;
+    }
+    return s;
+}
+
+__device__ __forceinline__ bool span_full(const Span &s, int ncell) {
+    return s.n == 1 && s.lo[0] == 0 && s.hi[0] == ncell - 1;
+}
+
+// Nearest now centre of the Q.8 point (X, Y) in [0,MX) x [0,MY), exact, ties to
+// the lowest label, by the bucket grid.  K >= 1.  First a growing square of
+// cells around the point's cell until a centre is seen; its distance bounds
+// the answer, so every cell meeting the disc of that radius (+1 site) around
+// the point is then scanned.
+__device__ int point_nearest(const Bufs &B, int X, int Y) {
+    const int MX = 256 * B.lx, MY = 256 * B.ly;
+    const int cx = X >> 13, cy = Y >> 13;
+    const int *cs = B.cell_start;
+    long long bd = LLONG_MAX;
+    for (int R = 1;; R *= 2) {
+        const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
+        for (int ry = 0; ry < sy.n; ++ry)
+            for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row)
+                for (int rx = 0; rx < sx.n; ++rx) {
+                    const int e0 = cs[row * B.ntx + sx.lo[rx]], e1 = cs[row * B.ntx + sx.hi[rx] + 1];
+                    for (int e = e0; e < e1; ++e) {
+                        const int2 q = B.cell_q[e];
+                        const long long d = d2q(X, Y, q.x, q.y, MX, MY);
+                        if (d < bd) bd = d;
+                    }
+                }
+        if (bd != LLONG_MAX || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
+    }
+    // disc of radius sqrt(bd) + 1 site around the point
+    const double rho = sqrt((double)bd) / 256.0 + 1.0;
+    const double px = X / 256.0, py = Y / 256.0;
+    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx);
+    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly);
+    long long best = LLONG_MAX;
+    int bl = DV_EMPTY;
+    for (int ry = 0; ry < sy.n; ++ry)
+        for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row)
+            for (int rx = 0; rx < sx.n; ++rx) {
+                const int e0 = cs[row * B.ntx + sx.lo[rx]], e1 = cs[row * B.ntx + sx.hi[rx] + 1];
+                for (int e = e0; e < e1; ++e) {
+                    const int2 q = B.cell_q[e];
+                    const long long d = d2q(X, Y, q.x, q.y, MX, MY);
+                    const int lab = B.cell_items[e];
+                    if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
+                }
+            }
+    return bl;
+}
+
+// Block-wide exclusive scan of in[0, n) into out[0, n); returns the total.
+// Every thread of the block must call it.  blockDim.x is a multiple of 64.
+__device__ int block_exclusive_scan(const int *in, int *out, int n, int *wsum /* LDS [16] */) {
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+        const int i = c0 + t;
+        const int v = i < n ? in[i] : 0;
+        int x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int before = carry;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+        if (i < n) out[i] = before + x - v;
+        int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += wsum[w];
+        carry += tot;
+    }
+    return carry;
+}

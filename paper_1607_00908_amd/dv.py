@@ -1,0 +1,253 @@
+"""Python binding of libdv (the C ABI in include/dv.h).
+
+Argument marshalling only: every step of the detection path runs in the HIP
+kernels of libdv.so.  PyTorch supplies device memory (the field tensor) and
+the stream.  The library must have been built (``__graft_entry__.build()``);
+loading fails loudly otherwise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdv.so")
+
+MAXLINK = 0x77777777
+NO_LABEL = -1
+PHASE_ABOVE = 0
+PHASE_BELOW = 1
+KEEP_MAPS = 1
+
+OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = range(7)
+
+# every entry point declared in include/dv.h
+EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
+           "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
+           "dv_get_matching", "dv_status_str", "dv_last_error")
+
+
+class DVConfig(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
+                ("threshold", ctypes.c_float), ("phase", ctypes.c_int32),
+                ("connectivity", ctypes.c_int32), ("max_components", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class DVFlip(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int32), ("b", ctypes.c_int32), ("pa", ctypes.c_int32),
+                ("pb", ctypes.c_int32), ("kind", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class DVFrameInfo(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("n_components", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("n_flips", ctypes.c_int32), ("n_breaking", ctypes.c_int32),
+                ("n_excluded_past", ctypes.c_int32), ("n_excluded_now", ctypes.c_int32),
+                ("n_ambiguous_centroids", ctypes.c_int32), ("global_trigger", ctypes.c_uint32)]
+
+
+class DVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdv.so and declare the C signatures.  Raises when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.dv_create.restype = i32
+    lib.dv_create.argtypes = [ctypes.POINTER(DVConfig), vp, ctypes.POINTER(vp)]
+    lib.dv_push_frame.restype = i32
+    lib.dv_push_frame.argtypes = [vp, vp]
+    lib.dv_get_flips.restype = i32
+    lib.dv_get_flips.argtypes = [vp, vp, i32, i32p]
+    lib.dv_get_info.restype = i32
+    lib.dv_get_info.argtypes = [vp, ctypes.POINTER(DVFrameInfo)]
+    lib.dv_sync.restype = i32
+    lib.dv_sync.argtypes = [vp]
+    lib.dv_destroy.restype = None
+    lib.dv_destroy.argtypes = [vp]
+    lib.dv_get_labels.restype = i32
+    lib.dv_get_labels.argtypes = [vp, vp]
+    lib.dv_get_owner.restype = i32
+    lib.dv_get_owner.argtypes = [vp, vp]
+    lib.dv_get_components.restype = i32
+    lib.dv_get_components.argtypes = [vp, vp, vp, vp, i32, i32p]
+    lib.dv_get_edges.restype = i32
+    lib.dv_get_edges.argtypes = [vp, vp, i32, i32p]
+    lib.dv_get_matching.restype = i32
+    lib.dv_get_matching.argtypes = [vp, vp, i32, i32p]
+    lib.dv_status_str.restype = ctypes.c_char_p
+    lib.dv_status_str.argtypes = [i32]
+    lib.dv_last_error.restype = ctypes.c_char_p
+    lib.dv_last_error.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class FrameInfo:
+    frame: int
+    status: int
+    n_components: int
+    n_edges: int
+    n_flips: int
+    n_breaking: int
+    n_excluded_past: int
+    n_excluded_now: int
+    n_ambiguous_centroids: int
+    global_trigger: int
+
+
+class Detector:
+    """One detection context (one sequence of frames) on one device.
+
+    ``stream``: the torch.cuda.Stream the context enqueues its kernels on;
+    None creates one.  Before each push the context's stream waits (on the
+    device, without a host synchronisation) for the caller's current stream,
+    so a field produced there is complete when the kernels read it.
+    """
+
+    def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
+                 connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
+                 device: int = 0, keep_maps: bool = True, stream=None):
+        self.lib = load()
+        self.lx, self.ly = int(lx), int(ly)
+        cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
+                       int(connectivity), int(max_components), int(max_degree), int(device),
+                       KEEP_MAPS if keep_maps else 0)
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", int(device))
+        if stream is None:
+            stream = torch.cuda.Stream(device=self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.dv_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
+                                ctypes.byref(h))
+        if st != OK:
+            raise DVError(st, self.lib.dv_last_error(None).decode())
+        self.h = h
+        self.cfg = cfg
+        self._field_ref = None
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int, allow=()):
+        if st != OK and st not in allow:
+            raise DVError(st, self.lib.dv_last_error(self.h).decode())
+        return st
+
+    # -- frames --------------------------------------------------------------
+    def push(self, field) -> None:
+        """Enqueue one frame.  ``field``: float32 device tensor [ly, lx]
+        (contiguous), or a raw device pointer (int)."""
+        if isinstance(field, int):
+            ptr = field
+        else:
+            if not (field.is_cuda and field.dtype == self._torch.float32):
+                raise TypeError("field must be a float32 device tensor")
+            if tuple(field.shape) != (self.ly, self.lx) or not field.is_contiguous():
+                raise ValueError(f"field must be contiguous with shape ({self.ly}, {self.lx})")
+            if field.device != self.device:
+                raise ValueError(f"field is on {field.device}, the context on {self.device}")
+            ptr = field.data_ptr()
+            cur = self._torch.cuda.current_stream(self.device)
+            if cur.cuda_stream != self.stream.cuda_stream:
+                self.stream.wait_stream(cur)
+                field.record_stream(self.stream)
+            self._field_ref = field  # kept alive until the next synchronising call
+        self._check(self.lib.dv_push_frame(self.h, ctypes.c_void_p(ptr)))
+
+    def sync(self):
+        self._check(self.lib.dv_sync(self.h))
+        self._field_ref = None
+
+    def flips(self) -> np.ndarray:
+        """Flips of the most recent frame: int32 [F, 6] = (a, b, pa, pb, kind, flags)."""
+        n = ctypes.c_int32(0)
+        self._check(self.lib.dv_get_flips(self.h, None, 0, ctypes.byref(n)), allow=(ERR_CAPACITY,))
+        out = np.zeros((max(n.value, 1), 6), dtype=np.int32)
+        self._check(self.lib.dv_get_flips(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        self._field_ref = None
+        return out[:n.value]
+
+    def info(self) -> FrameInfo:
+        fi = DVFrameInfo()
+        self._check(self.lib.dv_get_info(self.h, ctypes.byref(fi)), allow=(ERR_CAPACITY,))
+        self._field_ref = None
+        return FrameInfo(fi.frame, fi.status, fi.n_components, fi.n_edges, fi.n_flips,
+                         fi.n_breaking, fi.n_excluded_past, fi.n_excluded_now,
+                         fi.n_ambiguous_centroids, fi.global_trigger)
+
+    # -- inspection ------------------------------------------------------------
+    def labels(self) -> np.ndarray:
+        out = np.empty((self.ly, self.lx), dtype=np.int32)
+        self._check(self.lib.dv_get_labels(self.h, _ptr(out)))
+        return out
+
+    def owner(self) -> np.ndarray:
+        out = np.empty((self.ly, self.lx), dtype=np.int32)
+        self._check(self.lib.dv_get_owner(self.h, _ptr(out)))
+        return out
+
+    def components(self) -> dict:
+        n = ctypes.c_int32(0)
+        self._check(self.lib.dv_get_components(self.h, None, None, None, 0, ctypes.byref(n)),
+                    allow=(ERR_CAPACITY,))
+        K = n.value
+        q = np.zeros((max(K, 1), 2), dtype=np.int32)
+        f = np.zeros((max(K, 1), 2), dtype=np.float64)
+        s = np.zeros(max(K, 1), dtype=np.int32)
+        self._check(self.lib.dv_get_components(self.h, _ptr(q), _ptr(f), _ptr(s), K, ctypes.byref(n)))
+        return {"qx": q[:K, 0].copy(), "qy": q[:K, 1].copy(), "fx": f[:K, 0].copy(),
+                "fy": f[:K, 1].copy(), "n": s[:K].copy()}
+
+    def edges(self) -> np.ndarray:
+        n = ctypes.c_int32(0)
+        self._check(self.lib.dv_get_edges(self.h, None, 0, ctypes.byref(n)), allow=(ERR_CAPACITY,))
+        out = np.zeros((max(n.value, 1), 2), dtype=np.int32)
+        self._check(self.lib.dv_get_edges(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
+    def matching(self) -> np.ndarray:
+        n = ctypes.c_int32(0)
+        self._check(self.lib.dv_get_matching(self.h, None, 0, ctypes.byref(n)), allow=(ERR_CAPACITY,))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        self._check(self.lib.dv_get_matching(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        return out[:n.value]

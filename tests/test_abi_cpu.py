@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/dv.h declares, and rejects invalid configurations
+on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1607_00908_amd import dv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dv_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(dv.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dv.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(dv.DVConfig) == 40
+    assert ctypes.sizeof(dv.DVFlip) == 24
+    assert ctypes.sizeof(dv.DVFrameInfo) == 48
+
+
+def _cfg(**kw):
+    base = dict(lx=64, ly=64, threshold=0.5, phase=0, connectivity=8, max_components=100,
+                max_degree=0, device=0, flags=1)
+    base.update(kw)
+    c = dv.DVConfig(ctypes.sizeof(dv.DVConfig), base["lx"], base["ly"], base["threshold"],
+                    base["phase"], base["connectivity"], base["max_components"],
+                    base["max_degree"], base["device"], base["flags"])
+    return c
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
+    dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
+    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=2)])
+def test_invalid_config_is_rejected_on_the_host(bad):
+    lib = dv.load()
+    h = ctypes.c_void_p()
+    st = lib.dv_create(ctypes.byref(_cfg(**bad)), None, ctypes.byref(h))
+    assert st == dv.ERR_ARG
+    assert not h.value
+    assert lib.dv_last_error(None)
+
+
+def test_size_guard():
+    lib = dv.load()
+    c = _cfg()
+    c.size = 12
+    h = ctypes.c_void_p()
+    assert lib.dv_create(ctypes.byref(c), None, ctypes.byref(h)) == dv.ERR_ARG
+
+
+def test_null_arguments():
+    lib = dv.load()
+    assert lib.dv_create(None, None, None) == dv.ERR_ARG
+    assert lib.dv_push_frame(None, None) == dv.ERR_ARG
+    n = ctypes.c_int32(0)
+    assert lib.dv_get_flips(None, None, 0, ctypes.byref(n)) == dv.ERR_ARG
+    lib.dv_destroy(None)   # NULL-safe
+    assert lib.dv_status_str(2) == b"capacity exceeded"

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Labels, Q.8 centres, sizes, colour map, couples, matching and flips must be
+bit-identical; float64 centres agree to 1e-6 relative (they are computed by the
+same correctly rounded operations, so they are in fact identical).
+Sizes span several tiles with ragged tails; the named workloads run at their
+full sizes in the launch configuration the benchmark uses.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_00908_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1607_00908_amd import dv  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check_frame(det, now, ref, lx, ly, maps=True):
+    info = det.info()
+    assert info.status == 0
+    assert info.n_components == now.K
+    if maps:
+        assert np.array_equal(det.labels(), now.labels), "labels"
+        assert np.array_equal(det.owner(), now.owner), "owner"
+    comps = det.components()
+    assert np.array_equal(comps["qx"], now.comps["qx"]), "qx"
+    assert np.array_equal(comps["qy"], now.comps["qy"]), "qy"
+    assert np.array_equal(comps["n"], now.comps["n"]), "sizes"
+    assert np.allclose(comps["fx"], now.comps["fx"], rtol=1e-6, atol=0)
+    assert np.allclose(comps["fy"], now.comps["fy"], rtol=1e-6, atol=0)
+    assert info.n_ambiguous_centroids == int(now.comps["amb"].sum())
+    e = det.edges()
+    assert np.array_equal(e, now.edges), "couples"
+    assert info.n_edges == len(now.edges)
+    fl = det.flips()
+    assert np.array_equal(fl, ref.flips), "flips"
+    assert info.n_flips == len(ref.flips)
+    assert info.n_breaking == int(np.sum(ref.flips[:, 4] == -1)) if len(ref.flips) else info.n_breaking == 0
+    assert info.n_excluded_past == ref.excluded_past
+    assert info.n_excluded_now == ref.excluded_now
+    assert info.global_trigger == ref.global_trigger
+    phi = det.matching()
+    if len(ref.phi):
+        want = ref.phi.copy()
+        keep = (want >= 0)
+        keep[keep] = ref.cnt[want[keep]] == 1
+        want[~keep] = -1
+        assert np.array_equal(phi, want), "matching"
+    else:
+        assert len(phi) == 0
+
+
+def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag=""):
+    ly, lx = fields[0].shape
+    if kmax is None:
+        kmax = lx * ly
+    det = dv.Detector(lx, ly, thr, phase, conn, max_components=kmax, max_degree=max_degree,
+                      keep_maps=maps)
+    seq = oracle.Sequence(thr, phase, conn, NTHREADS)
+    for i, f in enumerate(fields):
+        say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase}")
+        det.push(torch.from_numpy(np.ascontiguousarray(f)).to("cuda"))
+        now, ref = seq.push(f)
+        check_frame(det, now, ref, lx, ly, maps)
+    det.close()
+    return now
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_fuzz_small_lattices(seed):
+    rng = np.random.default_rng(1000 + seed)
+    lx, ly = int(rng.integers(3, 80)), int(rng.integers(3, 80))
+    conn = int(rng.choice([4, 8]))
+    phase = int(rng.integers(0, 2))
+    p = float(rng.uniform(0.15, 0.6))
+    thr = p if phase == 1 else 1.0 - p
+    fields = [synth.tiny_random_field(lx, ly, 5000 + 7 * seed + k) for k in range(3)]
+    run_sequence(fields, thr, phase, conn, tag=f"fuzz{seed}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_moving_disks_small(seed):
+    rng = np.random.default_rng(2000 + seed)
+    lx, ly = int(rng.integers(40, 200)), int(rng.integers(40, 200))
+    nd = int(rng.integers(3, 40))
+    sim = synth.DiskSim(lx, ly, nd, 3.0, 6.0, 0.7, 3e-3, seed=3000 + seed)
+    run_sequence(list(sim.frames(5)), 0.5, tag=f"disks{seed}")
+
+
+@pytest.mark.parametrize("lx,ly", [(3, 3), (3, 17), (64, 3), (32, 32), (33, 31), (65, 97), (31, 200)])
+def test_shapes_and_ragged_tiles(lx, ly):
+    fields = [synth.tiny_random_field(lx, ly, 17 * lx + ly + k) for k in range(3)]
+    for conn in (4, 8):
+        run_sequence(fields, 0.4, 1, conn, tag=f"shape{lx}x{ly}")
+
+
+def test_empty_and_single_component():
+    lx, ly = 70, 45
+    empty = np.zeros((ly, lx), np.float32)
+    one = np.zeros((ly, lx), np.float32)
+    one[10:20, 30:40] = 1.0
+    full = np.ones((ly, lx), np.float32)
+    run_sequence([empty, one, empty, full, one], 0.5, tag="empty/one")
+
+
+def test_wrapping_strip_and_checkerboard():
+    lx, ly = 50, 40
+    strip = np.zeros((ly, lx), np.float32)
+    strip[7, :] = 1.0
+    strip[20:23, 5:9] = 1.0
+    yy, xx = np.mgrid[0:ly, 0:lx]
+    cb = ((xx + yy) % 2).astype(np.float32)
+    run_sequence([strip, cb, strip], 0.5, 0, 4, tag="strip/cb4")
+    run_sequence([strip, cb, strip], 0.5, 0, 8, tag="strip/cb8")
+
+
+def test_threshold_equality_and_nan_are_outside():
+    rng = np.random.default_rng(9)
+    f = rng.random((48, 40)).astype(np.float32)
+    f[rng.random(f.shape) < 0.2] = np.float32(0.5)
+    f[rng.random(f.shape) < 0.05] = np.nan
+    run_sequence([f, f[::-1].copy()], 0.5, 0, 8, tag="nan")
+    run_sequence([f, f[::-1].copy()], 0.5, 1, 8, tag="nan-below")
+
+
+def test_t1_fixture_on_gpu():
+    import json
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "t1_fixture.json")))
+    names = ["A", "B", "C", "D"]
+    fields = []
+    for fr in ("0", "1"):
+        pts = [d["quartet"][fr][n] for n in names] + d["background"]
+        fields.append(synth.disk_field(d["lx"], d["ly"], np.array(pts, float),
+                                       np.full(len(pts), float(d["radius"]))))
+    run_sequence(fields, 0.5, tag="t1")
+    det = dv.Detector(d["lx"], d["ly"], 0.5, max_components=128)
+    for f in fields:
+        det.push(torch.from_numpy(f).cuda())
+    fl = det.flips()
+    assert len(fl) == 2 and fl[0, 4] == -1 and fl[1, 4] == 1
+    det.close()
+
+
+def test_capacity_rejection_keeps_the_past():
+    """K > K_max rejects the frame; the next frame is compared with the last
+    accepted one."""
+    sim = synth.DiskSim(120, 100, 12, 4.0, 6.0, 0.8, 2e-3, seed=77)
+    a, b, c = list(sim.frames(3))
+    noise = synth.tiny_random_field(120, 100, 4)   # hundreds of components
+    det = dv.Detector(120, 100, 0.5, max_components=64)
+    det.push(torch.from_numpy(a).cuda())
+    assert det.info().status == 0
+    det.push(torch.from_numpy(noise).cuda())
+    with pytest.raises(dv.DVError) as e:
+        det.flips()
+    assert e.value.status == dv.ERR_CAPACITY
+    assert det.info().status == dv.ERR_CAPACITY
+    det.push(torch.from_numpy(c).cuda())
+    got = det.flips()
+    fa, fc = oracle.frame(a, 0.5), oracle.frame(c, 0.5)
+    ref = oracle.compare(fa, fc)
+    assert np.array_equal(got, ref.flips)
+    assert det.info().frame == 2
+    det.close()
+
+
+def test_degree_overflow_is_reported():
+    sim = synth.DiskSim(128, 128, 30, 3.0, 5.0, 0.5, 1e-3, seed=8)
+    f = next(sim.frames(1))
+    det = dv.Detector(128, 128, 0.5, max_components=64, max_degree=4)
+    det.push(torch.from_numpy(f).cuda())
+    assert det.info().status == dv.ERR_CAPACITY
+    det.close()
+
+
+def test_flip_buffer_too_small_reports_count():
+    import ctypes
+    sim = synth.DiskSim(160, 160, 40, 5.0, 8.0, 0.6, 2e-3, seed=7)
+    frames = list(sim.frames(12))
+    det = dv.Detector(160, 160, 0.5, max_components=128)
+    det.push(torch.from_numpy(frames[0]).cuda())
+    det.push(torch.from_numpy(frames[11]).cuda())
+    n = ctypes.c_int32(-1)
+    st = det.lib.dv_get_flips(det.h, None, 0, ctypes.byref(n))
+    ref = oracle.compare(oracle.frame(frames[0], 0.5), oracle.frame(frames[11], 0.5))
+    assert len(ref.flips) > 0
+    assert st == dv.ERR_CAPACITY and n.value == len(ref.flips)
+    assert np.array_equal(det.flips(), ref.flips)
+    det.close()
+
+
+def test_disks256_all_frames():
+    sim, spec = synth.workload("disks256")
+    run_sequence(list(sim.frames(spec["frames"])), spec["threshold"], kmax=1024, tag="disks256")
+
+
+def test_disks1024_frames():
+    sim, spec = synth.workload("disks1024")
+    run_sequence(list(sim.frames(6)), spec["threshold"], kmax=4096, tag="disks1024")
+
+
+def test_grf1024_frames():
+    """The random-field workload's statistics at 1024^2 (same smoothing,
+    threshold and AR(1) step): many components appear, vanish and wrap."""
+    sim = synth.GRFSim(1024, 1024, 6.0, 0.98, seed=33)
+    run_sequence(list(sim.frames(4)), 1.0, kmax=8192, tag="grf1024")
+
+
+def test_grf4096_full_size():
+    """Full-size random-field frames (16.8 M sites, ~9k components): labels,
+    centres, colour map, couples and flips against the oracle."""
+    sim, spec = synth.workload("grf4096")
+    fields = list(sim.frames(2))
+    run_sequence(fields, spec["threshold"], kmax=32768, tag="grf4096")
