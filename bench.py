@@ -1,0 +1,214 @@
+"""Benchmark of the per-frame detection path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload disks1024]
+
+A step is one frame through the whole path (threshold, labelling, centres,
+digital Voronoi, Delaunay couples, matching, flips) on synthetic input of the
+workload's shape.  All frames of the workload are resident in HBM before the
+timed region (a ring of distinct frames, 400 MB for disks1024, larger than the
+256 MB Infinity Cache); steps cycle through the ring without host
+synchronisation.  Prints one JSON line.
+
+Reported beside the throughput:
+  roofline      one stage timed with HIP events on the context's stream over the
+                timed region; algorithmic bytes per launch / mean duration
+  latency_ms    p50 / p99 of push -> flips returned (host-synchronous loop)
+  cpu_baseline  the CPU oracle on a bounded sample of the same frames
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# compulsory HBM bytes per site of each per-site stage (maps kept / flips only)
+STAGE_BYTES = {
+    "tile_ccl": (4, 4),        # field read
+    "relabel": (8, 4),         # field read + label map write
+    "owner_edges": (4, 0),     # owner map write
+}
+STAGE_SOURCES = {
+    "tile_ccl": "k_label.hip", "relabel": "k_label.hip", "owner_edges": "k_voronoi.hip",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(stage: str) -> str:
+    p = os.path.join(ROOT, "paper_1607_00908_amd", "csrc", STAGE_SOURCES[stage])
+    h = hashlib.sha256()
+    for f in sorted({p, os.path.join(ROOT, "paper_1607_00908_amd", "csrc", "dv_internal.h"),
+                     os.path.join(ROOT, "paper_1607_00908_amd", "csrc", "dv_device.h")}):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(stage: str, workload: str, maps: bool):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on the current source of the stage; else None."""
+    p = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    key = f"{stage}:{workload}:{'maps' if maps else 'flips'}"
+    e = d.get(key)
+    if not e or e.get("source_sha") != source_hash(stage):
+        return None
+    return int(round(e["bytes_per_dispatch"]))
+
+
+def make_frames(workload: str, frames: int | None):
+    from paper_1607_00908_amd import synth
+    sim, spec = synth.workload(workload)
+    n = spec["frames"] if frames is None else frames
+    out = list(sim.frames(n))
+    return out, spec
+
+
+def cpu_baseline(frames, spec, seconds: float):
+    """Run the oracle on the first frames until about `seconds` of CPU work."""
+    import oracle
+    ly, lx = frames[0].shape
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, nthreads=1)
+    t0 = time.perf_counter()
+    n = 0
+    for f in frames:
+        seq.push(f)
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(n * lx * ly / dt / 1e6, 4), "unit": "Msites/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"frames 0-{n - 1} of {spec.get('name', '')} ({n} frames, {n - 1} diffs), "
+                      f"whole path, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="disks1024")
+    ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
+    ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
+    ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
+    ap.add_argument("--latency-frames", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("bench.py measures one GPU only (no multi-GPU path in this build)")
+        sys.exit(2)
+
+    import torch
+    from paper_1607_00908_amd import dv
+
+    t0 = time.perf_counter()
+    frames, spec = make_frames(args.workload, args.frames)
+    spec["name"] = args.workload
+    ly, lx = frames[0].shape
+    N = lx * ly
+    log(f"generated {len(frames)} frames {lx}x{ly} in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda", 0)
+    ring = torch.from_numpy(np.stack(frames)).to(dev)
+    torch.cuda.synchronize()
+    maps = not args.flips_only
+    kmax = 32768 if N > (1 << 22) else 4096
+    det = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
+                      keep_maps=maps)
+    F = ring.shape[0]
+
+    # the context's stream does all device work; pushes need no cross-stream wait
+    torch.cuda.set_stream(det.stream)
+    for i in range(args.warmup):
+        det.push(ring[i % F])
+    det.sync()
+    info = det.info()
+    log(f"warmup done: K={info.n_components} E={info.n_edges} flips={info.n_flips}")
+
+    det.set_profile(args.stage, capacity=args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        det.push(ring[(args.warmup + i) % F])
+    det.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, launches = det.get_profile()
+    det.set_profile(None)
+    info = det.info()
+    assert info.status == 0, info
+    ms_per_step = 1e3 * elapsed / args.steps
+    msites = N * args.steps / elapsed / 1e6
+    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/frame, {msites:.0f} Msites/s")
+
+    # latency: push -> flips returned, host-synchronous
+    lat = []
+    for i in range(args.latency_frames):
+        f = ring[i % F]
+        a = time.perf_counter()
+        det.push(f)
+        det.flips()
+        lat.append(time.perf_counter() - a)
+    lat = np.array(lat) * 1e3
+
+    stage_avg_ms = stage_ms / max(launches, 1)
+    per_site = STAGE_BYTES.get(args.stage, (0, 0))[0 if maps else 1]
+    alg_bytes = per_site * N
+    achieved = alg_bytes / (stage_avg_ms * 1e-3) / 1e9 if stage_avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic(args.stage, args.workload, maps),
+                "kernel": args.stage, "kernel_us": round(stage_avg_ms * 1e3, 2),
+                "algorithmic_bytes": alg_bytes}
+
+    out = {
+        "metric": "Msites/s through label+Voronoi+flip pipeline (%HBM peak); p50/p99 frame latency",
+        "value": round(msites, 2),
+        "unit": "Msites/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32->int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lx": lx, "ly": ly, "frames_in_ring": F,
+                   "components": info.n_components, "edges": info.n_edges,
+                   "mode": "maps+flips" if maps else "flips-only", "parallelism": "single-gpu"},
+        "frames_per_s": round(args.steps / elapsed, 1),
+        "hbm_frac_pipeline": round(msites * 1e6 * (12 if maps else 4) / (HBM_PEAK_GBS * 1e9), 5),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "samples": len(lat)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds)
+    det.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -78,7 +78,7 @@ typedef struct {
     int32_t connectivity;    /* 8 (default) or 4                                   */
     int32_t max_components;  /* K_max, 1 .. 2^24; device memory is sized from it   */
     int32_t max_degree;      /* row capacity of the adjacency (Delaunay degree),
-                                4 .. 256; 0 selects 48                             */
+                                4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
     uint32_t flags;          /* DV_KEEP_MAPS                                       */
 } dv_config;
@@ -157,6 +157,21 @@ dv_status dv_get_edges(dv_ctx *ctx, int32_t *ab, int32_t capacity, int32_t *n_ou
 /* Phi of the most recent comparison indexed by past label; -1 for dropped
  * past points; *n_out = K of the past frame (0 for the first frame). */
 dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *n_out);
+
+/* ---- measurement ---- */
+
+/* Stages of the per-frame procedure, in launch order. */
+#define DV_N_STAGES 15
+/* Bracket every launch of one stage with HIP events on the context's stream.
+ * stage: 0 .. DV_N_STAGES-1, or -1 to stop.  capacity: launches that can be
+ * recorded before the next dv_get_profile (further launches are not timed).
+ * Creates the events; returns DV_ERR_ARG for a bad stage or capacity. */
+dv_status dv_set_profile(dv_ctx *ctx, int32_t stage, int32_t capacity);
+/* Wait for the stream; *total_ms = summed event time of the recorded
+ * launches, *launches = their number; clears the record. */
+dv_status dv_get_profile(dv_ctx *ctx, double *total_ms, int32_t *launches);
+/* Name of a stage ("tile_ccl", "owner_edges", ...); NULL when out of range. */
+const char *dv_stage_name(int32_t stage);
 
 const char *dv_status_str(dv_status s);
 /* Text of the last error on this context ("" when none).  NULL ctx: text of

@@ -27,6 +27,7 @@ struct dv_ctx {
     int32_t *d_edge_ab;      // [K_max * max_degree] pairs
     int32_t *d_edge_total;
     bool pushed;
+    Prof prof;
     std::string err;
 };
 
@@ -50,10 +51,19 @@ bool dalloc(dv_ctx *c, T **p, size_t count) {
     return true;
 }
 
+void drop_events(dv_ctx *c) {
+    if (c->prof.ev) {
+        for (int i = 0; i < 2 * c->prof.cap; ++i) (void)hipEventDestroy(c->prof.ev[i]);
+        delete[] c->prof.ev;
+    }
+    c->prof = Prof();
+}
+
 void release(dv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_events(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_state) (void)hipHostFree(c->h_state);
@@ -198,9 +208,9 @@ dv_status dv_push_frame(dv_ctx *c, const float *field_device) {
     if (!field_device) return fail(c, DV_ERR_ARG, "field is NULL");
     (void)hipSetDevice(c->device);
     c->B.field = field_device;
-    launch_label(c->B, c->stream);
-    launch_voronoi(c->B, c->stream);
-    launch_diff(c->B, c->stream);
+    launch_label(c->B, c->stream, c->prof);
+    launch_voronoi(c->B, c->stream, c->prof);
+    launch_diff(c->B, c->stream, c->prof);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     c->pushed = true;
@@ -337,6 +347,54 @@ void dv_destroy(dv_ctx *c) {
     if (!c) return;
     release(c);
     delete c;
+}
+
+static const char *const STAGE_NAMES[ST_COUNT] = {
+    "tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "grid_scan",
+    "grid_scatter", "owner_edges", "rows", "match", "diff_count", "diff_scan", "diff_write",
+    "commit"};
+
+const char *dv_stage_name(int32_t stage) {
+    return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;
+}
+
+dv_status dv_set_profile(dv_ctx *c, int32_t stage, int32_t capacity) {
+    if (!c) return DV_ERR_ARG;
+    if (stage < -1 || stage >= ST_COUNT || (stage >= 0 && (capacity < 1 || capacity > (1 << 20))))
+        return fail(c, DV_ERR_ARG, "bad stage or capacity");
+    (void)hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    drop_events(c);
+    if (stage < 0) return DV_OK;
+    c->prof.ev = new hipEvent_t[2 * (size_t)capacity];
+    for (int i = 0; i < 2 * capacity; ++i) {
+        if (hipEventCreate(&c->prof.ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->prof.ev[j]);
+            delete[] c->prof.ev;
+            c->prof = Prof();
+            return fail(c, DV_ERR_DEVICE, "event creation failed");
+        }
+    }
+    c->prof.cap = capacity;
+    c->prof.stage = stage;
+    return DV_OK;
+}
+
+dv_status dv_get_profile(dv_ctx *c, double *total_ms, int32_t *launches) {
+    if (!c || !total_ms || !launches) return DV_ERR_ARG;
+    (void)hipSetDevice(c->device);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    double tot = 0.0;
+    for (int i = 0; i < c->prof.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->prof.ev[2 * i], c->prof.ev[2 * i + 1]) != hipSuccess)
+            return fail(c, DV_ERR_DEVICE, "event query failed");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = c->prof.used;
+    c->prof.used = 0;
+    return DV_OK;
 }
 
 const char *dv_status_str(dv_status s) {

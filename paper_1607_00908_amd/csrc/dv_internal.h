@@ -88,12 +88,35 @@ struct Bufs {
     DevState *st;
 };
 
+// Stage ids, in launch order (names in dv_api.hip).
+enum {
+    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RANK_SCAN, ST_RELABEL, ST_FINALIZE, ST_GRID_SCAN,
+    ST_GRID_SCATTER, ST_OWNER_EDGES, ST_ROWS, ST_MATCH, ST_DIFF_COUNT, ST_DIFF_SCAN,
+    ST_DIFF_WRITE, ST_COMMIT, ST_COUNT
+};
+
+// Optional event bracketing of one stage (measurement only).
+struct Prof {
+    int stage = -1;          // stage to time, -1 none
+    int cap = 0, used = 0;   // recorded launches
+    hipEvent_t *ev = nullptr;  // [2 * cap]
+    void begin(int id, hipStream_t s) {
+        if (id == stage && used < cap) (void)hipEventRecord(ev[2 * used], s);
+    }
+    void end(int id, hipStream_t s) {
+        if (id == stage && used < cap) {
+            (void)hipEventRecord(ev[2 * used + 1], s);
+            ++used;
+        }
+    }
+};
+
 // launchers (k_label.hip)
-void launch_label(const Bufs &B, hipStream_t s);
+void launch_label(const Bufs &B, hipStream_t s, Prof &P);
 // launchers (k_voronoi.hip)
-void launch_voronoi(const Bufs &B, hipStream_t s);
+void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P);
 // launchers (k_diff.hip)
-void launch_diff(const Bufs &B, hipStream_t s);
+void launch_diff(const Bufs &B, hipStream_t s, Prof &P);
 // inspection helpers (k_diff.hip)
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,
                       hipStream_t s);

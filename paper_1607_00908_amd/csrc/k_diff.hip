@@ -229,13 +229,23 @@ __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int
 
 }  // namespace
 
-void launch_diff(const Bufs &B, hipStream_t s) {
+void launch_diff(const Bufs &B, hipStream_t s, Prof &P) {
     const int kgrid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
+    P.begin(ST_MATCH, s);
     hipLaunchKernelGGL(k_match, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_MATCH, s);
+    P.begin(ST_DIFF_COUNT, s);
     hipLaunchKernelGGL(k_diff_count, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_DIFF_COUNT, s);
+    P.begin(ST_DIFF_SCAN, s);
     hipLaunchKernelGGL(k_diff_scan, dim3(1), dim3(1024), 0, s, B);
+    P.end(ST_DIFF_SCAN, s);
+    P.begin(ST_DIFF_WRITE, s);
     hipLaunchKernelGGL(k_diff_write, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_DIFF_WRITE, s);
+    P.begin(ST_COMMIT, s);
     hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, B);
+    P.end(ST_COMMIT, s);
 }
 
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,

@@ -390,11 +390,21 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
 
 }  // namespace
 
-void launch_label(const Bufs &B, hipStream_t s) {
+void launch_label(const Bufs &B, hipStream_t s, Prof &P) {
     const dim3 tiles(B.ntx, B.nty);
+    P.begin(ST_TILE_CCL, s);
     hipLaunchKernelGGL(k_tile_ccl, tiles, dim3(DV_BLOCK), 0, s, B);
+    P.end(ST_TILE_CCL, s);
+    P.begin(ST_MERGE, s);
     hipLaunchKernelGGL(k_merge, tiles, dim3(64), 0, s, B);
+    P.end(ST_MERGE, s);
+    P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, tiles, dim3(DV_BLOCK), 0, s, B);
+    P.end(ST_RESOLVE, s);
+    P.begin(ST_RANK_SCAN, s);
     hipLaunchKernelGGL(k_rank_scan, dim3(B.nty), dim3(DV_BLOCK), 0, s, B);
+    P.end(ST_RANK_SCAN, s);
+    P.begin(ST_RELABEL, s);
     hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), 0, s, B);
+    P.end(ST_RELABEL, s);
 }

@@ -293,11 +293,21 @@ __global__ __launch_bounds__(256) void k_rows(Bufs B) {
 
 }  // namespace
 
-void launch_voronoi(const Bufs &B, hipStream_t s) {
+void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P) {
     const int kgrid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
+    P.begin(ST_FINALIZE, s);
     hipLaunchKernelGGL(k_finalize, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_FINALIZE, s);
+    P.begin(ST_GRID_SCAN, s);
     hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, B);
+    P.end(ST_GRID_SCAN, s);
+    P.begin(ST_GRID_SCATTER, s);
     hipLaunchKernelGGL(k_grid_scatter, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_GRID_SCATTER, s);
+    P.begin(ST_OWNER_EDGES, s);
     hipLaunchKernelGGL(k_owner_edges, dim3(B.ntx, B.nty), dim3(DV_BLOCK), 0, s, B);
+    P.end(ST_OWNER_EDGES, s);
+    P.begin(ST_ROWS, s);
     hipLaunchKernelGGL(k_rows, dim3(kgrid), dim3(256), 0, s, B);
+    P.end(ST_ROWS, s);
 }

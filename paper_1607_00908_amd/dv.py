@@ -27,7 +27,12 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 # every entry point declared in include/dv.h
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
-           "dv_get_matching", "dv_status_str", "dv_last_error")
+           "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
+           "dv_status_str", "dv_last_error")
+
+STAGES = ("tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "grid_scan",
+          "grid_scatter", "owner_edges", "rows", "match", "diff_count", "diff_scan", "diff_write",
+          "commit")
 
 
 class DVConfig(ctypes.Structure):
@@ -92,6 +97,12 @@ def load(path: str = LIB_PATH):
     lib.dv_get_edges.argtypes = [vp, vp, i32, i32p]
     lib.dv_get_matching.restype = i32
     lib.dv_get_matching.argtypes = [vp, vp, i32, i32p]
+    lib.dv_set_profile.restype = i32
+    lib.dv_set_profile.argtypes = [vp, i32, i32]
+    lib.dv_get_profile.restype = i32
+    lib.dv_get_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+    lib.dv_stage_name.restype = ctypes.c_char_p
+    lib.dv_stage_name.argtypes = [i32]
     lib.dv_status_str.restype = ctypes.c_char_p
     lib.dv_status_str.argtypes = [i32]
     lib.dv_last_error.restype = ctypes.c_char_p
@@ -214,6 +225,25 @@ class Detector:
         return FrameInfo(fi.frame, fi.status, fi.n_components, fi.n_edges, fi.n_flips,
                          fi.n_breaking, fi.n_excluded_past, fi.n_excluded_now,
                          fi.n_ambiguous_centroids, fi.global_trigger)
+
+    # -- measurement -----------------------------------------------------------
+    def set_profile(self, stage, capacity: int = 4096):
+        """Time every launch of one stage (name or index) with HIP events;
+        None stops."""
+        if stage is None:
+            idx = -1
+        elif isinstance(stage, str):
+            idx = STAGES.index(stage)
+        else:
+            idx = int(stage)
+        self._check(self.lib.dv_set_profile(self.h, idx, int(capacity)))
+
+    def get_profile(self):
+        """(total milliseconds, launches) recorded since the last call."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int32(0)
+        self._check(self.lib.dv_get_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     # -- inspection ------------------------------------------------------------
     def labels(self) -> np.ndarray:

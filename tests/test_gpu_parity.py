@@ -162,7 +162,8 @@ def test_capacity_rejection_keeps_the_past():
     accepted one."""
     sim = synth.DiskSim(120, 100, 12, 4.0, 6.0, 0.8, 2e-3, seed=77)
     a, b, c = list(sim.frames(3))
-    noise = synth.tiny_random_field(120, 100, 4)   # hundreds of components
+    # 15% of sites inside, below site percolation: hundreds of components
+    noise = (synth.tiny_random_field(120, 100, 4) > 0.85).astype(np.float32)
     det = dv.Detector(120, 100, 0.5, max_components=64)
     det.push(torch.from_numpy(a).cuda())
     assert det.info().status == 0
