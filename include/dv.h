@@ -161,7 +161,7 @@ dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *
 /* ---- measurement ---- */
 
 /* Stages of the per-frame procedure, in launch order. */
-#define DV_N_STAGES 15
+#define DV_N_STAGES 8
 /* Bracket every launch of one stage with HIP events on the context's stream.
  * stage: 0 .. DV_N_STAGES-1, or -1 to stop.  capacity: launches that can be
  * recorded before the next dv_get_profile (further launches are not timed).

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dv.h"
+#include "dv.h"
 #include "dv_internal.h"
 
 struct dv_ctx {
@@ -127,6 +127,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     dv_ctx *c = new dv_ctx();
     c->cfg = *cfg_in;
     if (c->cfg.max_degree == 0) c->cfg.max_degree = 48;
+    // row slots are read four at a time
+    c->cfg.max_degree = (c->cfg.max_degree + 3) & ~3;
     c->device = c->cfg.device;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
@@ -168,6 +170,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
               dalloc(c, &B.cnt, K) && dalloc(c, &B.inv, K) && dalloc(c, &B.trigger, K) &&
               dalloc(c, &B.nb, K) && dalloc(c, &B.na, K) && dalloc(c, &B.ob, K) &&
               dalloc(c, &B.oa, K) && dalloc(c, &B.flips, K * B.maxdeg * 6) &&
+              dalloc(c, &B.stage, K * B.maxdeg * 12) &&
               dalloc(c, &B.st, 1) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
               dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
     if (ok && B.keep_maps) ok = dalloc(c, &B.labels, N) && dalloc(c, &B.owner, N);
@@ -175,7 +178,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
         CompBuf &C = B.comp[b];
         ok = dalloc(c, &C.qx, K) && dalloc(c, &C.qy, K) && dalloc(c, &C.fx, K) &&
              dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
-             dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg) && dalloc(c, &C.deg, K);
+             dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
     }
     if (ok && hipHostMalloc((void **)&c->h_state, sizeof(DevState)) != hipSuccess) ok = false;
     if (!ok) {
@@ -191,8 +194,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
              hipMemsetAsync(B.st, 0, sizeof(DevState), c->stream) == hipSuccess;
     for (int b = 0; z && b < 2; ++b)
         z = hipMemsetD32Async((hipDeviceptr_t)B.comp[b].adj, DV_EMPTY, K * B.maxdeg, c->stream) ==
-                hipSuccess &&
-            hipMemsetAsync(B.comp[b].deg, 0, K * sizeof(int), c->stream) == hipSuccess;
+            hipSuccess;
     if (!z || hipStreamSynchronize(c->stream) != hipSuccess) {
         release(c);
         delete c;
@@ -350,9 +352,7 @@ void dv_destroy(dv_ctx *c) {
 }
 
 static const char *const STAGE_NAMES[ST_COUNT] = {
-    "tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "grid_scan",
-    "grid_scatter", "owner_edges", "rows", "match", "diff_count", "diff_scan", "diff_write",
-    "commit"};
+    "tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "owner_edges", "diff"};
 
 const char *dv_stage_name(int32_t stage) {
     return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;

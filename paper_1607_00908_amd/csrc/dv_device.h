@@ -23,10 +23,13 @@ __device__ __forceinline__ int pmod(int v, int m) {
     return r < 0 ? r + m : r;
 }
 
-// Up to two ranges of cell indices along one axis.
+// Up to two ranges of cell indices along one axis (accessors select between
+// two scalars, so a Span never lives in scratch memory).
 struct Span {
-    int lo[2], hi[2];
+    int lo0, hi0, lo1, hi1;
     int n;
+    __device__ __forceinline__ int lo(int i) const { return i ? lo1 : lo0; }
+    __device__ __forceinline__ int hi(int i) const { return i ? hi1 : hi0; }
 };
 
 // Cells whose sites meet the periodic site interval [a, b] (integers, a <= b).
@@ -34,15 +37,15 @@ __device__ __forceinline__ Span span_sites(int a, int b, int L) {
     Span s;
     const int ncell = (L + DV_TILE - 1) / DV_TILE;
     if (b - a >= L - 1) {
-        s.n = 1; s.lo[0] = 0; s.hi[0] = ncell - 1;
+        s.n = 1; s.lo0 = 0; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = -1;
         return s;
     }
     a = pmod(a, L);
     b = pmod(b, L);
     if (a <= b) {
-        s.n = 1; s.lo[0] = a / DV_TILE; s.hi[0] = b / DV_TILE;
+        s.n = 1; s.lo0 = a / DV_TILE; s.hi0 = b / DV_TILE; s.lo1 = 0; s.hi1 = -1;
     } else {
-        s.n = 2; s.lo[0] = a / DV_TILE; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b / DV_TILE;
+        s.n = 2; s.lo0 = a / DV_TILE; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = b / DV_TILE;
     }
     return s;
 }
@@ -51,22 +54,22 @@ __device__ __forceinline__ Span span_sites(int a, int b, int L) {
 __device__ __forceinline__ Span span_cells(int c, int R, int ncell) {
     Span s;
     if (2 * R + 1 >= ncell) {
-        s.n = 1; s.lo[0] = 0; s.hi[0] = ncell - 1;
+        s.n = 1; s.lo0 = 0; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = -1;
         return s;
     }
     const int a = c - R, b = c + R;
     if (a < 0) {
-        s.n = 2; s.lo[0] = a + ncell; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b;
+        s.n = 2; s.lo0 = a + ncell; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = b;
     } else if (b >= ncell) {
-        s.n = 2; s.lo[0] = a; s.hi[0] = ncell - 1; s.lo[1] = 0; s.hi[1] = b - ncell;
+        s.n = 2; s.lo0 = a; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = b - ncell;
     } else {
-        s.n = 1; s.lo[0] = a; s.hi[0] = b;
+        s.n = 1; s.lo0 = a; s.hi0 = b; s.lo1 = 0; s.hi1 = -1;
     }
     return s;
 }
 
 __device__ __forceinline__ bool span_full(const Span &s, int ncell) {
-    return s.n == 1 && s.lo[0] == 0 && s.hi[0] == ncell - 1;
+    return s.n == 1 && s.lo0 == 0 && s.hi0 == ncell - 1;
 }
 
 // Nearest now centre of the Q.8 point (X, Y) in [0,MX) x [0,MY), exact, ties to
@@ -82,9 +85,9 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
     for (int R = 1;; R *= 2) {
         const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
         for (int ry = 0; ry < sy.n; ++ry)
-            for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row)
+            for (int row = sy.lo(ry); row <= sy.hi(ry); ++row)
                 for (int rx = 0; rx < sx.n; ++rx) {
-                    const int e0 = cs[row * B.ntx + sx.lo[rx]], e1 = cs[row * B.ntx + sx.hi[rx] + 1];
+                    const int e0 = cs[row * B.ntx + sx.lo(rx)], e1 = cs[row * B.ntx + sx.hi(rx) + 1];
                     for (int e = e0; e < e1; ++e) {
                         const int2 q = B.cell_q[e];
                         const long long d = d2q(X, Y, q.x, q.y, MX, MY);
@@ -101,9 +104,9 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
     long long best = LLONG_MAX;
     int bl = DV_EMPTY;
     for (int ry = 0; ry < sy.n; ++ry)
-        for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row)
+        for (int row = sy.lo(ry); row <= sy.hi(ry); ++row)
             for (int rx = 0; rx < sx.n; ++rx) {
-                const int e0 = cs[row * B.ntx + sx.lo[rx]], e1 = cs[row * B.ntx + sx.hi[rx] + 1];
+                const int e0 = cs[row * B.ntx + sx.lo(rx)], e1 = cs[row * B.ntx + sx.hi(rx) + 1];
                 for (int e = e0; e < e1; ++e) {
                     const int2 q = B.cell_q[e];
                     const long long d = d2q(X, Y, q.x, q.y, MX, MY);
@@ -111,6 +114,63 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
                     if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
                 }
             }
+    return bl;
+}
+
+// Lexicographic (distance, label) minimum across the 64 lanes of a wave.
+__device__ __forceinline__ void wave_min_dl(long long &d, int &lab) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long d2 = __shfl_xor(d, o, 64);
+        const int l2 = __shfl_xor(lab, o, 64);
+        if (d2 < d || (d2 == d && l2 < lab)) { d = d2; lab = l2; }
+    }
+}
+
+// Same search as point_nearest with the 64 lanes of a wave sharing the cells:
+// lane j takes the (row, column range) pairs j, j + 64, ...  Every lane of the
+// wave must call it with the same point; every lane gets the answer.
+__device__ int wave_nearest(const Bufs &B, int X, int Y) {
+    const int MX = 256 * B.lx, MY = 256 * B.ly;
+    const int cx = X >> 13, cy = Y >> 13;
+    const int lane = threadIdx.x & 63;
+    const int *cs = B.cell_start;
+    long long bd = LLONG_MAX;
+    int dummy = 0;
+    for (int R = 1;; R *= 2) {
+        const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
+        const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
+        for (int j = lane; j < nrows * sx.n; j += 64) {
+            const int ri = j / sx.n, c = j % sx.n;
+            const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
+            const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
+            for (int e = e0; e < e1; ++e) {
+                const int2 q = B.cell_q[e];
+                const long long d = d2q(X, Y, q.x, q.y, MX, MY);
+                if (d < bd) bd = d;
+            }
+        }
+        wave_min_dl(bd, dummy);
+        if (bd != LLONG_MAX || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
+    }
+    const double rho = sqrt((double)bd) / 256.0 + 1.0;
+    const double px = X / 256.0, py = Y / 256.0;
+    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx);
+    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly);
+    const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
+    long long best = LLONG_MAX;
+    int bl = DV_EMPTY;
+    for (int j = lane; j < nrows * sx.n; j += 64) {
+        const int ri = j / sx.n, c = j % sx.n;
+        const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
+        const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
+        for (int e = e0; e < e1; ++e) {
+            const int2 q = B.cell_q[e];
+            const long long d = d2q(X, Y, q.x, q.y, MX, MY);
+            const int lab = B.cell_items[e];
+            if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
+        }
+    }
+    wave_min_dl(best, bl);
     return bl;
 }
 

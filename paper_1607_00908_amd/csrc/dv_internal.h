@@ -9,7 +9,7 @@
 #define DV_TILE_SITES (DV_TILE * DV_TILE)
 #define DV_BLOCK 256               // threads per tile workgroup
 #define DV_EMPTY 0x77777777        // MAXLINK: empty row slot / no colour
-#define DV_CAND_CAP 2048           // candidate centres held in LDS per chunk
+#define DV_CAND_CAP 512            // candidate centre images held in LDS per chunk
 
 // error bits raised on the device during a frame
 #define DV_E_KMAX 1u               // more components than K_max
@@ -35,6 +35,8 @@ struct DevState {
     int32_t global_trigger;
     int32_t status;        // 0 accepted, else DV_ERR_CAPACITY of the last push
     int32_t K_past_cmp;    // K of the past frame used by the current comparison
+    int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
+    int32_t done_diff;     // blocks of k_diff that have finished (last one resets)
     int32_t pad;
     int64_t frame;         // accepted frames
 };
@@ -46,8 +48,7 @@ struct CompBuf {
     int32_t *n;            // member count
     int32_t *root;         // smallest linear index of the component
     int32_t *amb;          // 1 when the component crosses its antipodal line
-    int32_t *adj;          // rows [K_max][max_degree], DV_EMPTY padded, sorted
-    int32_t *deg;          // row lengths
+    int32_t *adj;          // rows [K_max][max_degree]: unordered sets, DV_EMPTY padded
 };
 
 // Everything a kernel may touch.  Passed by value.
@@ -83,6 +84,7 @@ struct Bufs {
     int32_t *trigger;      // [K_max] local trigger per past label
     int32_t *nb, *na;      // [K_max] breaking / arising count per now row
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
+    int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
     int32_t *flips;        // [K_max * max_degree][6]
     CompBuf comp[2];
     DevState *st;
@@ -90,9 +92,8 @@ struct Bufs {
 
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
-    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RANK_SCAN, ST_RELABEL, ST_FINALIZE, ST_GRID_SCAN,
-    ST_GRID_SCATTER, ST_OWNER_EDGES, ST_ROWS, ST_MATCH, ST_DIFF_COUNT, ST_DIFF_SCAN,
-    ST_DIFF_WRITE, ST_COMMIT, ST_COUNT
+    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RANK_SCAN, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES,
+    ST_DIFF, ST_COUNT
 };
 
 // Optional event bracketing of one stage (measurement only).

@@ -1,192 +1,167 @@
-// Isomorphism, translation, trigger and flips (Sec. 3.2.3 and 3.2.4).
+// Translation, trigger and flips (Sec. 3.2.3 and 3.2.4), in one launch.
 //
-//   k_match       Phi(p) = nearest now centre of past centre p (exact, ties to
-//                 the lowest label) through the now bucket grid; preimage
-//                 counts; inverse map
-//   k_diff_count  one thread per now row n with exactly one preimage p: the
-//                 past row of p translated through Phi (kept entries only,
-//                 sorted) is compared with row n (kept entries only); counts
-//                 the breaking (only past) and arising (only now) couples with
-//                 the other end above n, and the local trigger of p
-//   k_diff_scan   offsets of every row's flips (breaking first, then arising,
-//                 each in (a, b) order)
-//   k_diff_write  writes the flip records
-//   k_commit      the frame becomes the past when it was accepted
+// One wave per now label n that has exactly one preimage p: lane j holds slot
+// j of the now row of n and slot j of the past row of p translated through
+// Phi (kept entries only).  Rows are sets, so membership is tested with wave
+// shuffles.  A couple of T(p) missing from R(n) is breaking, one of R(n)
+// missing from T(p) is arising; each is reported once, from the row of its
+// smaller now label, and staged in increasing order of the other end.  The
+// local trigger of p is set when the two rows differ.
+//
+// The last block to finish (atomic counter after a release fence) scans the
+// per-row counts, places the staged flips in canonical order (breaking first,
+// then arising, each by (a, b)) and commits the frame: the now buffer becomes
+// the past when the frame was accepted.
 #include "dv_device.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_match(Bufs B) {
+__global__ __launch_bounds__(256) void k_diff(Bufs B) {
+    __shared__ int wsum[16];
+    __shared__ int s_last;
+    __shared__ int s_red[3][4];
     DevState *st = B.st;
-    if (st->err || !st->past_valid) return;
-    const int past = st->sel;
-    const int KP = st->K[past], KN = st->K_now;
-    const CompBuf P = B.comp[past];
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < KP; p += gridDim.x * blockDim.x) {
-        if (KN == 0) { B.phi[p] = -1; continue; }
-        const int n = point_nearest(B, P.qx[p], P.qy[p]);
-        B.phi[p] = n;
-        atomicAdd(&B.cnt[n], 1);
-        B.inv[n] = p;
-    }
-}
-
-#define MAXD 64   // largest supported row capacity
-
-// Translated past row of p: pairs (Phi(q), q) for kept neighbours q, sorted by
-// Phi(q).  Returns its length.
-__device__ int translated_row(const Bufs &B, const CompBuf &P, int p, int *tv, int *tq) {
-    const int *row = P.adj + (size_t)p * B.maxdeg;
-    const int d = P.deg[p];
-    int m = 0;
-    for (int i = 0; i < d; ++i) {
-        const int q = row[i];
-        const int n = B.phi[q];
-        if (n < 0 || B.cnt[n] != 1) continue;
-        int j = m - 1;
-        while (j >= 0 && tv[j] > n) { tv[j + 1] = tv[j]; tq[j + 1] = tq[j]; --j; }
-        tv[j + 1] = n;
-        tq[j + 1] = q;
-        ++m;
-    }
-    return m;
-}
-
-__global__ __launch_bounds__(256) void k_diff_count(Bufs B) {
-    DevState *st = B.st;
-    if (st->err) return;
+    const bool ok = st->err == 0;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int KN = st->K_now;
     const int past = st->sel, now = 1 - past;
     const bool pv = st->past_valid != 0;
     const int KP = pv ? st->K[past] : 0;
     const CompBuf P = B.comp[past], N = B.comp[now];
-    int exn = 0, exp_ = 0;
-    const int stride = gridDim.x * blockDim.x;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    // dropped past points: Phi is reported as -1 (a concurrent reader of
-    // phi[q] skips q either way)
-    for (int p = tid; p < KP; p += stride) {
-        const int n = B.phi[p];
-        if (n < 0 || B.cnt[n] != 1) { B.trigger[p] = 0; B.phi[p] = -1; ++exp_; }
-    }
-    int tv[MAXD], tq[MAXD];
-    for (int n = tid; n < KN; n += stride) {
-        int cb = 0, ca = 0;
-        if (pv) {
-            if (B.cnt[n] != 1) {
-                ++exn;
-            } else {
-                const int p = B.inv[n];
-                const int m = translated_row(B, P, p, tv, tq);
-                const int *row = N.adj + (size_t)n * B.maxdeg;
-                const int d = N.deg[n];
-                int i = 0, j = 0;
-                bool differ = false;
-                // merge of two sorted lists; now entries without exactly one
-                // preimage are skipped
-                while (i < m || j < d) {
-                    if (j < d && B.cnt[row[j]] != 1) { ++j; continue; }
-                    if (j >= d || (i < m && tv[i] < row[j])) {
-                        differ = true;
-                        if (tv[i] > n) ++cb;
-                        ++i;
-                    } else if (i >= m || row[j] < tv[i]) {
-                        differ = true;
-                        if (row[j] > n) ++ca;
-                        ++j;
-                    } else {
-                        ++i;
-                        ++j;
-                    }
-                }
-                B.trigger[p] = differ ? 1 : 0;
+    const int D = B.maxdeg;
+    int e2 = 0, exn = 0, exp_ = 0;
+    if (ok) {
+        // dropped past points: Phi is reported as -1 (a concurrent reader of
+        // phi[q] skips q either way)
+        for (int p = blockIdx.x * blockDim.x + t; p < KP; p += gridDim.x * blockDim.x) {
+            const int n = B.phi[p];
+            if (n < 0 || B.cnt[n] != 1) {
+                B.trigger[p] = 0;
+                B.phi[p] = -1;
+                ++exp_;
             }
         }
-        B.nb[n] = cb;
-        B.na[n] = ca;
+        const int nwaves = gridDim.x * (blockDim.x >> 6);
+        for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
+            const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
+            const int dR = __popcll(__ballot(m != DV_EMPTY));
+            if (lane == 0) e2 += dR;
+            int cb = 0, ca = 0;
+            if (pv && B.cnt[n] != 1) {
+                if (lane == 0) ++exn;
+            } else if (pv) {
+                const int p = B.inv[n];
+                const int q = lane < D ? P.adj[(size_t)p * D + lane] : DV_EMPTY;
+                const int dT = __popcll(__ballot(q != DV_EMPTY));
+                int tv = DV_EMPTY;
+                if (q != DV_EMPTY) {
+                    const int nn = B.phi[q];
+                    if (nn >= 0 && B.cnt[nn] == 1) tv = nn;
+                }
+                const int mv = (m != DV_EMPTY && B.cnt[m] == 1) ? m : DV_EMPTY;
+                // slots are filled from the front: the first dR (dT) lanes
+                bool tin = false, min_ = false;
+                for (int k = 0; k < dR; ++k) tin |= (__shfl(mv, k, 64) == tv);
+                for (int k = 0; k < dT; ++k) min_ |= (__shfl(tv, k, 64) == mv);
+                const bool brk = tv != DV_EMPTY && !tin;
+                const bool ari = mv != DV_EMPTY && !min_;
+                const unsigned long long dmask = __ballot(brk || ari);
+                if (lane == 0) B.trigger[p] = dmask ? 1 : 0;
+                // each couple once, from the row of its smaller now label
+                const bool bo = brk && tv > n, ao = ari && mv > n;
+                cb = __popcll(__ballot(bo));
+                ca = __popcll(__ballot(ao));
+                int *stg = B.stage + (size_t)n * (2 * D) * 6;
+                const int bv = bo ? tv : DV_EMPTY, av = ao ? mv : DV_EMPTY;
+                int rb = 0, ra = 0;
+                for (int k = 0; k < dT; ++k) rb += (__shfl(bv, k, 64) < bv) ? 1 : 0;
+                for (int k = 0; k < dR; ++k) ra += (__shfl(av, k, 64) < av) ? 1 : 0;
+                if (bo) {
+                    int *r = stg + 6 * rb;
+                    r[0] = n; r[1] = tv; r[2] = p; r[3] = q; r[4] = -1; r[5] = 0;
+                }
+                if (ao) {
+                    int *r = stg + 6 * (D + ra);
+                    r[0] = n; r[1] = mv; r[2] = p; r[3] = B.inv[mv]; r[4] = 1; r[5] = 0;
+                }
+            }
+            if (lane == 0) {
+                B.nb[n] = cb;
+                B.na[n] = ca;
+            }
+        }
     }
+    // block totals of the counters
     for (int o = 32; o > 0; o >>= 1) {
+        e2 += __shfl_down(e2, o, 64);
         exn += __shfl_down(exn, o, 64);
         exp_ += __shfl_down(exp_, o, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
-        if (exn) atomicAdd(&st->n_excl_now, exn);
-        if (exp_) atomicAdd(&st->n_excl_past, exp_);
+    if (lane == 0) {
+        s_red[0][wid] = e2;
+        s_red[1][wid] = exn;
+        s_red[2][wid] = exp_;
     }
-}
-
-__global__ __launch_bounds__(1024) void k_diff_scan(Bufs B) {
-    __shared__ int wsum[16];
-    DevState *st = B.st;
-    if (st->err) return;
-    const int KN = st->K_now;
+    __syncthreads();
+    if (t == 0 && ok) {
+        int a = 0, b = 0, c = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a += s_red[0][w];
+            b += s_red[1][w];
+            c += s_red[2][w];
+        }
+        if (a) atomicAdd(&st->E2_now, a);
+        if (b) atomicAdd(&st->n_excl_now, b);
+        if (c) atomicAdd(&st->n_excl_past, c);
+    }
+    // ---- the last block: offsets, canonical placement, commit
+    // release: the barrier completes the block's stores, one thread writes
+    // the cache back and takes a ticket; acquire likewise in the last block
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        s_last = atomicAdd(&st->done_diff, 1) == (int)gridDim.x - 1;
+        if (s_last) __threadfence();
+    }
+    __syncthreads();
+    if (!s_last) return;
+    if (!ok) {
+        if (t == 0) {
+            st->done_diff = 0;
+            st->status = 2;   // DV_ERR_CAPACITY
+            st->n_flips = 0;
+            st->n_break = 0;
+            st->global_trigger = 0;
+        }
+        return;
+    }
     const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
     __syncthreads();
     const int nar = block_exclusive_scan(B.na, B.oa, KN, wsum);
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    for (int n = t; n < KN; n += blockDim.x) {
+        const int cb = B.nb[n], ca = B.na[n];
+        if (cb == 0 && ca == 0) continue;
+        const int *stg = B.stage + (size_t)n * (2 * D) * 6;
+        int *fb = B.flips + (size_t)6 * B.ob[n];
+        for (int j = 0; j < 6 * cb; ++j) fb[j] = stg[j];
+        int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
+        for (int j = 0; j < 6 * ca; ++j) fa[j] = stg[6 * D + j];
+    }
+    __syncthreads();
+    if (t == 0) {
+        st->done_diff = 0;
         st->n_break = nbk;
         st->n_flips = nbk + nar;
         st->global_trigger = (nbk + nar) > 0 ? 1 : 0;
+        st->K_past_cmp = pv ? st->K[past] : 0;
+        st->K[now] = KN;
+        st->E[now] = st->E2_now / 2;
+        st->sel = now;
+        st->past_valid = 1;
+        st->frame += 1;
+        st->status = 0;
     }
-}
-
-__global__ __launch_bounds__(256) void k_diff_write(Bufs B) {
-    DevState *st = B.st;
-    if (st->err || !st->past_valid) return;
-    const int KN = st->K_now;
-    const int past = st->sel, now = 1 - past;
-    const CompBuf P = B.comp[past], N = B.comp[now];
-    const int nbk = st->n_break;
-    int tv[MAXD], tq[MAXD];
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < KN; n += gridDim.x * blockDim.x) {
-        if (B.nb[n] == 0 && B.na[n] == 0) continue;
-        const int p = B.inv[n];
-        const int m = translated_row(B, P, p, tv, tq);
-        const int *row = N.adj + (size_t)n * B.maxdeg;
-        const int d = N.deg[n];
-        int *fb = B.flips + (size_t)6 * B.ob[n];
-        int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
-        int i = 0, j = 0;
-        while (i < m || j < d) {
-            if (j < d && B.cnt[row[j]] != 1) { ++j; continue; }
-            if (j >= d || (i < m && tv[i] < row[j])) {
-                if (tv[i] > n) {
-                    fb[0] = n; fb[1] = tv[i]; fb[2] = p; fb[3] = tq[i]; fb[4] = -1; fb[5] = 0;
-                    fb += 6;
-                }
-                ++i;
-            } else if (i >= m || row[j] < tv[i]) {
-                const int mm = row[j];
-                if (mm > n) {
-                    fa[0] = n; fa[1] = mm; fa[2] = p; fa[3] = B.inv[mm]; fa[4] = 1; fa[5] = 0;
-                    fa += 6;
-                }
-                ++j;
-            } else {
-                ++i;
-                ++j;
-            }
-        }
-    }
-}
-
-__global__ void k_commit(Bufs B) {
-    DevState *st = B.st;
-    if (st->err) {
-        st->status = 2;   // DV_ERR_CAPACITY
-        st->n_flips = 0;
-        st->n_break = 0;
-        st->global_trigger = 0;
-        return;
-    }
-    const int past = st->sel, now = 1 - past;
-    st->K_past_cmp = st->past_valid ? st->K[past] : 0;
-    st->K[now] = st->K_now;
-    st->E[now] = st->E2_now / 2;
-    st->sel = now;
-    st->past_valid = 1;
-    st->frame += 1;
-    st->status = 0;
 }
 
 // ---- inspection: sorted couple list (a < b) of the current buffer ----------
@@ -198,7 +173,7 @@ __global__ __launch_bounds__(256) void k_edge_count(Bufs B, int *cntv) {
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < K; a += gridDim.x * blockDim.x) {
         const int *row = C.adj + (size_t)a * B.maxdeg;
         int c = 0;
-        for (int i = 0; i < C.deg[a]; ++i) c += row[i] > a ? 1 : 0;
+        for (int i = 0; i < B.maxdeg && row[i] != DV_EMPTY; ++i) c += row[i] > a ? 1 : 0;
         cntv[a] = c;
     }
 }
@@ -210,6 +185,7 @@ __global__ __launch_bounds__(1024) void k_edge_scan(Bufs B, const int *cntv, int
     if (threadIdx.x == 0) *total = tot;
 }
 
+// entries above a, written in increasing order (rows are unordered sets)
 __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int *ab) {
     DevState *st = B.st;
     const int cur = st->sel;
@@ -217,35 +193,26 @@ __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int
     const CompBuf C = B.comp[cur];
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < K; a += gridDim.x * blockDim.x) {
         const int *row = C.adj + (size_t)a * B.maxdeg;
-        int o = offv[a];
-        for (int i = 0; i < C.deg[a]; ++i)
-            if (row[i] > a) {
-                ab[2 * o] = a;
-                ab[2 * o + 1] = row[i];
-                ++o;
-            }
+        const int o = offv[a];
+        for (int i = 0; i < B.maxdeg && row[i] != DV_EMPTY; ++i) {
+            const int v = row[i];
+            if (v <= a) continue;
+            int rank = 0;
+            for (int j = 0; j < B.maxdeg && row[j] != DV_EMPTY; ++j)
+                rank += (row[j] > a && row[j] < v) ? 1 : 0;
+            ab[2 * (o + rank)] = a;
+            ab[2 * (o + rank) + 1] = v;
+        }
     }
 }
 
 }  // namespace
 
 void launch_diff(const Bufs &B, hipStream_t s, Prof &P) {
-    const int kgrid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
-    P.begin(ST_MATCH, s);
-    hipLaunchKernelGGL(k_match, dim3(kgrid), dim3(256), 0, s, B);
-    P.end(ST_MATCH, s);
-    P.begin(ST_DIFF_COUNT, s);
-    hipLaunchKernelGGL(k_diff_count, dim3(kgrid), dim3(256), 0, s, B);
-    P.end(ST_DIFF_COUNT, s);
-    P.begin(ST_DIFF_SCAN, s);
-    hipLaunchKernelGGL(k_diff_scan, dim3(1), dim3(1024), 0, s, B);
-    P.end(ST_DIFF_SCAN, s);
-    P.begin(ST_DIFF_WRITE, s);
-    hipLaunchKernelGGL(k_diff_write, dim3(kgrid), dim3(256), 0, s, B);
-    P.end(ST_DIFF_WRITE, s);
-    P.begin(ST_COMMIT, s);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, B);
-    P.end(ST_COMMIT, s);
+    const int grid = (int)std::min<long long>((B.kmax + 3) / 4, 1024);
+    P.begin(ST_DIFF, s);
+    hipLaunchKernelGGL(k_diff, dim3(grid), dim3(256), 0, s, B);
+    P.end(ST_DIFF, s);
 }
 
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,

@@ -76,54 +76,90 @@ __device__ void gunite(int *P, int a, int b) {
 }
 
 // Thread t of a 256-thread block owns column t & 31 and rows (t >> 5) + 8i,
-// i = 0..3: every warp-wide load touches two full 128-byte rows.
+// i = 0..3: every wave-wide load touches two full 128-byte rows, and a wave
+// ballot gives the inside masks of those two rows.
 //
+// Start of the horizontal run of inside sites that contains column x, in a
+// row whose inside mask is m (bit x set).
+__device__ __forceinline__ int run_start(uint32_t m, int x) {
+    const uint32_t below = x == 31 ? 0xffffffffu : ((2u << x) - 1u);
+    const uint32_t out = ~m & below;
+    return out ? 32 - __clz(out) : 0;
+}
+
 // Labels the inside sites of one tile with tile-local union-find.  On return
 // (after a barrier) L[s] is the smallest tile-local index of the piece of s,
-// or -1 when s is outside or beyond the lattice.
-__device__ void tile_ccl(const Bufs &B, int x0, int y0, int tw, int th, int *L) {
-    const int t = threadIdx.x, cx = t & 31, ry = t >> 5;
+// or -1 when s is outside or beyond the lattice.  rowm: LDS [32] row masks.
+//
+// Runs of a row are connected by construction (each site points to its run's
+// first site).  Runs of consecutive rows are united once per touching pair:
+// a site unites its run with the run above that starts to be adjacent at its
+// responsibility column -- column x + 1 for every site, and additionally
+// columns a - 1 and a for the first site a of a run (8-connectivity), or
+// column x for every site (4-connectivity).
+__device__ void tile_ccl(const Bufs &B, int x0, int y0, int tw, int th, int *L, uint32_t *rowm) {
+    const int t = threadIdx.x, cx = t & 31, ry = t >> 5, lane = t & 63;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
+        const int y = ry + 8 * i;
         bool in = false;
         if (cx < tw && y < th)
             in = is_in(B.field[(size_t)(y0 + y) * B.lx + x0 + cx], B.thr, B.phase);
-        L[s] = in ? s : -1;
+        const unsigned long long bal = __ballot(in);
+        const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
+        if (cx == 0) rowm[y] = m;
+        L[y * 32 + cx] = in ? y * 32 + run_start(m, cx) : -1;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
-        if (L[s] < 0) continue;
+        if (y == 0 || L[s] < 0) continue;
+        const uint32_t m = rowm[y], up = rowm[y - 1];
+        if (up == 0u) continue;
+        const int a = run_start(m, cx);
+        const int me = y * 32 + a;
         if (B.conn == 8) {
-            // Backward neighbours N, W, NW, NE.  When N is inside, W, NW and NE
-            // are already joined to N through their own unions (they are
-            // lattice neighbours of N), so one union suffices; otherwise W (or
-            // NW, which is joined to W) and NE.
-            if (y > 0 && L[s - 32] >= 0) {
-                lunite(L, s, s - 32);
-            } else {
-                if (cx > 0 && L[s - 1] >= 0) lunite(L, s, s - 1);
-                else if (cx > 0 && y > 0 && L[s - 33] >= 0) lunite(L, s, s - 33);
-                if (cx < 31 && y > 0 && L[s - 31] >= 0) lunite(L, s, s - 31);
+            const int lo = a > 0 ? a - 1 : 0;
+            // candidate columns above: x + 1, plus a - 1 and a at the run start
+            int cand[3] = {cx + 1, -1, -1};
+            if (cx == a) { cand[1] = a - 1; cand[2] = a; }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int u = cand[k];
+                if (u < lo || u > 31 || !((up >> u) & 1u)) continue;
+                if (u > lo && ((up >> (u - 1)) & 1u)) continue;   // not the first of its run
+                lunite(L, me, (y - 1) * 32 + run_start(up, u));
             }
         } else {
-            if (y > 0 && L[s - 32] >= 0) lunite(L, s, s - 32);
-            if (cx > 0 && L[s - 1] >= 0) lunite(L, s, s - 1);
+            const int u = cx;
+            if ((up >> u) & 1u) {
+                if (u == a || !((up >> (u - 1)) & 1u)) lunite(L, me, (y - 1) * 32 + run_start(up, u));
+            }
         }
+    }
+    __syncthreads();
+    // roots of the run starts, then every site takes its run start's root
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i, s = y * 32 + cx;
+        if (L[s] == s || (L[s] >= 0 && L[s] < s && run_start(rowm[y], cx) == cx)) L[s] = lfind(L, s);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int s = (ry + 8 * i) * 32 + cx;
-        if (L[s] >= 0) L[s] = lfind(L, s);
+        const int y = ry + 8 * i, s = y * 32 + cx;
+        if (L[s] >= 0) {
+            const int st = y * 32 + run_start(rowm[y], cx);
+            if (st != s) L[s] = L[st];
+        }
     }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
     __shared__ int L[DV_TILE_SITES];
+    __shared__ uint32_t rowm[DV_TILE];
     __shared__ int npc;
     const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
@@ -156,7 +192,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
-    tile_ccl(B, x0, y0, tw, th, L);
+    tile_ccl(B, x0, y0, tw, th, L, rowm);
 
     const int cx = t & 31, ry = t >> 5;
 #pragma unroll
@@ -312,6 +348,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
     __shared__ int prx[DV_TILE_SITES], pry[DV_TILE_SITES];
     __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
     __shared__ uint8_t in34[34 * 34];
+    __shared__ uint32_t rowm[DV_TILE];
     DevState *st = B.st;
     if (st->err) return;
     const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
@@ -327,7 +364,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
         gy = gy < 0 ? gy + ly : (gy >= ly ? gy - ly : gy);
         in34[(wy + 1) * 34 + wx + 1] = is_in(B.field[(size_t)gy * lx + gx], B.thr, B.phase) ? 1 : 0;
     }
-    tile_ccl(B, x0, y0, tw, th, L);
+    tile_ccl(B, x0, y0, tw, th, L, rowm);
 
     const int np = B.npieces[tile];
     for (int i = t; i < np; i += DV_BLOCK) {

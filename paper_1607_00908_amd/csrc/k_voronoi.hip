@@ -1,16 +1,18 @@
 // Centres, bucket grid, digital Voronoi colouring and Delaunay couples
-// (Sec. 3.1 last step, Sec. 3.2.1 and Sec. 3.2.2 of the paper).
+// (Sec. 3.1 last step, Sec. 3.2.1 and Sec. 3.2.2 of the paper), plus the
+// kinematic isomorphism of Sec. 3.2.3, which needs only the bucket grid.
 //
 //   k_finalize      exact Q.8 and float64 centres from the integer sums;
-//                   counts the centres of each bucket cell
-//   k_grid_scan     cell offsets (one block)
-//   k_grid_scatter  centres ordered by cell
-//   k_owner_edges   per tile: candidate centres from the grid, nearest centre
-//                   of every site of the tile and its one-site ring (LDS),
-//                   owner map, frame-gap vertex test and the first / second
-//                   nearest-neighbour rules; couples go into the adjacency rows
-//                   with a lock-free insert that drops duplicates
-//   k_rows          sorts every row (the compression of the adjacency)
+//                   counts the centres of each bucket cell; the last block to
+//                   finish builds the grid (cell offsets, centres by cell)
+//   k_owner_edges   blocks [0, tiles): candidate centres from the grid, nearest
+//                   centre of every site of the tile and its one-site ring
+//                   (LDS), owner map, frame-gap vertex test and the first /
+//                   second nearest-neighbour rules; the distinct couples of the
+//                   tile go into the adjacency rows with a lock-free set insert
+//                   (rows are unordered sets, MAXLINK padded)
+//                   blocks [tiles, ...): Phi(p) = nearest now centre of every
+//                   past centre p, one wave per point; preimage counts
 #include "dv_device.h"
 
 namespace {
@@ -26,57 +28,65 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
     return r < 0 ? r + m : r;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(Bufs B) {
+__global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
+    __shared__ int wsum[16];
+    __shared__ int s_last;
     DevState *st = B.st;
-    if (st->err) return;
+    const bool ok = st->err == 0;
     const int K = st->K_now;
     const int now = 1 - st->sel;
     const CompBuf C = B.comp[now];
-    int namb = 0;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-        const long long n = B.acc_n[k], sx = B.acc_x[k], sy = B.acc_y[k];
-        const int root = B.acc_root[k], amb = B.acc_amb[k];
-        B.acc_n[k] = 0;
-        B.acc_x[k] = 0;
-        B.acc_y[k] = 0;
-        B.acc_amb[k] = 0;
-        const int rx = root % B.lx, ry = root / B.lx;
-        const int qx = (int)pmod64(256LL * rx + floor_div(512 * sx + n, 2 * n), 256LL * B.lx);
-        const int qy = (int)pmod64(256LL * ry + floor_div(512 * sy + n, 2 * n), 256LL * B.ly);
-        double fx = (double)rx + (double)sx / (double)n;
-        double fy = (double)ry + (double)sy / (double)n;
-        if (fx < 0) fx += B.lx; else if (fx >= B.lx) fx -= B.lx;
-        if (fy < 0) fy += B.ly; else if (fy >= B.ly) fy -= B.ly;
-        C.qx[k] = qx;
-        C.qy[k] = qy;
-        C.fx[k] = fx;
-        C.fy[k] = fy;
-        C.n[k] = (int)n;
-        C.root[k] = root;
-        C.amb[k] = amb;
-        namb += amb;
-        const int cell = (qy >> 13) * B.ntx + (qx >> 13);
-        B.comp_cell[k] = cell;
-        B.comp_slot[k] = atomicAdd(&B.cell_count[cell], 1);
-        B.cnt[k] = 0;
-        B.inv[k] = -1;
+    const int t = threadIdx.x;
+    if (ok) {
+        int namb = 0;
+        for (int k = blockIdx.x * blockDim.x + t; k < K; k += gridDim.x * blockDim.x) {
+            const long long n = B.acc_n[k], sx = B.acc_x[k], sy = B.acc_y[k];
+            const int root = B.acc_root[k], amb = B.acc_amb[k];
+            B.acc_n[k] = 0;
+            B.acc_x[k] = 0;
+            B.acc_y[k] = 0;
+            B.acc_amb[k] = 0;
+            const int rx = root % B.lx, ry = root / B.lx;
+            const int qx = (int)pmod64(256LL * rx + floor_div(512 * sx + n, 2 * n), 256LL * B.lx);
+            const int qy = (int)pmod64(256LL * ry + floor_div(512 * sy + n, 2 * n), 256LL * B.ly);
+            double fx = (double)rx + (double)sx / (double)n;
+            double fy = (double)ry + (double)sy / (double)n;
+            if (fx < 0) fx += B.lx; else if (fx >= B.lx) fx -= B.lx;
+            if (fy < 0) fy += B.ly; else if (fy >= B.ly) fy -= B.ly;
+            C.qx[k] = qx;
+            C.qy[k] = qy;
+            C.fx[k] = fx;
+            C.fy[k] = fy;
+            C.n[k] = (int)n;
+            C.root[k] = root;
+            C.amb[k] = amb;
+            namb += amb;
+            const int cell = (qy >> 13) * B.ntx + (qx >> 13);
+            B.comp_cell[k] = cell;
+            B.comp_slot[k] = atomicAdd(&B.cell_count[cell], 1);
+            B.cnt[k] = 0;
+            B.inv[k] = -1;
+        }
+        if (namb) atomicAdd(&st->n_amb, namb);
     }
-    if (namb) atomicAdd(&st->n_amb, namb);
-}
-
-__global__ __launch_bounds__(1024) void k_grid_scan(Bufs B) {
-    __shared__ int wsum[16];
-    if (B.st->err) return;
+    // the last block to finish sees every count and builds the grid
+    // release: the barrier completes the block's stores, one thread writes
+    // the cache back and takes a ticket; acquire likewise in the last block
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        s_last = atomicAdd(&st->done_fin, 1) == (int)gridDim.x - 1;
+        if (s_last) __threadfence();
+    }
+    __syncthreads();
+    if (!s_last) return;
+    if (t == 0) st->done_fin = 0;
+    if (!ok) return;
     const int total = block_exclusive_scan(B.cell_count, B.cell_start, B.ncells, wsum);
-    if (threadIdx.x == 0) B.cell_start[B.ncells] = total;
-}
-
-__global__ __launch_bounds__(256) void k_grid_scatter(Bufs B) {
-    DevState *st = B.st;
-    if (st->err) return;
-    const int K = st->K_now;
-    const CompBuf C = B.comp[1 - st->sel];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    if (t == 0) B.cell_start[B.ncells] = total;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = t; k < K; k += blockDim.x) {
         const int pos = B.cell_start[B.comp_cell[k]] + B.comp_slot[k];
         B.cell_items[pos] = k;
         B.cell_q[pos] = make_int2(C.qx[k], C.qy[k]);
@@ -90,158 +100,283 @@ __constant__ int FRY[8] = {0, 1, 1, 1, 0, -1, -1, -1};
 __constant__ int INX[4] = {128, -128, -128, 128};
 __constant__ int INY[4] = {128, 128, -128, -128};
 
+// Lock-free set insert into a row (slots fill from the front; DV_EMPTY marks
+// free slots).  Rows are 16-byte aligned (max_degree is a multiple of 4), so
+// four slots are read per load.
 __device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, DevState *st) {
-    for (int i = 0; i < maxdeg; ++i) {
-        const int cur = row[i];
-        if (cur == v) return;
-        if (cur == DV_EMPTY) {
-            const int old = atomicCAS(&row[i], DV_EMPTY, v);
-            if (old == DV_EMPTY || old == v) return;
+    for (int i = 0; i < maxdeg; i += 4) {
+        const int4 q = *reinterpret_cast<const int4 *>(row + i);
+        const int e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (e[j] == v) return;
+            if (e[j] == DV_EMPTY) {
+                // claim the first free slot; on a lost race re-examine it
+                for (int k = i + j; k < maxdeg; ++k) {
+                    const int old = atomicCAS(&row[k], DV_EMPTY, v);
+                    if (old == DV_EMPTY || old == v) return;
+                }
+                atomicOr(&st->err, DV_E_DEGREE);
+                return;
+            }
         }
     }
     atomicOr(&st->err, DV_E_DEGREE);
 }
 
-__device__ __forceinline__ void emit(const Bufs &B, int *adj, int a, int b) {
-    row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, B.st);
-    row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, B.st);
+#define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
+
+// Phi_{P->N} (Sec. 3.2.3): one wave per past centre, nearest now centre by
+// the grid, exact, ties to the lowest label.
+__device__ void match_block(const Bufs &B, int mb, int nmb) {
+    DevState *st = B.st;
+    if (!st->past_valid) return;
+    const int past = st->sel;
+    const int KP = st->K[past], KN = st->K_now;
+    const CompBuf P = B.comp[past];
+    const int lane = threadIdx.x & 63;
+    const int nw = DV_BLOCK / 64;
+    for (int p = mb * nw + (threadIdx.x >> 6); p < KP; p += nmb * nw) {
+        int n = -1;
+        if (KN > 0) n = wave_nearest(B, P.qx[p], P.qy[p]);
+        if (lane == 0) {
+            B.phi[p] = n;
+            if (n >= 0) {
+                atomicAdd(&B.cnt[n], 1);
+                B.inv[n] = p;
+            }
+        }
+    }
 }
 
-#define WSITES 5   // ceil(34*34 / 256) window sites per thread
+#define WSITES 5      // ceil(34*34 / 256) window sites per thread
+#define RCAP 256      // item ranges held in LDS per batch
+#define IMG_MAX 9     // periodic images one centre can contribute (tiny lattices)
+#define CAND_BATCH 32 // centres appended per batch (room for IMG_MAX images each)
+
+// Shared state of one colouring tile.
+struct OwnerLds {
+    int own[34 * 34];
+    // candidate centres: tile-relative Q.8 image positions, |c|^2, label
+    int cx[DV_CAND_CAP], cy[DV_CAND_CAP];
+    double ck[DV_CAND_CAP];
+    int lab[DV_CAND_CAP];
+    int ncand;
+    int nchunks;   // times the list was evaluated and emptied before the end
+    // item ranges of the cell rectangle being visited
+    int r_e0[RCAP], r_pre[RCAP + 1];
+    int nranges;
+    unsigned long long best;
+    int wsum[16];
+    // couples found by the tile, (a << 32 | b) with a < b
+    unsigned long long pair[PAIR_CAP];
+    int npair;
+};
+
+// Visit every item (index into the cell-ordered centre arrays) of the cells
+// in rows sy x column ranges sx.  fn(e) is called by the block's threads in
+// parallel, in batches of at most `batch` items; before each batch every
+// thread calls before(m) with the batch size m (uniform control flow; all
+// earlier fn calls have completed).
+template <class Fn, class Before>
+__device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Span &sy, int batch,
+                            Fn fn, Before before) {
+    const int t = threadIdx.x;
+    const int *cs = B.cell_start;
+    // rows of the rectangle, enumerated in order
+    int nrows = 0;
+    for (int i = 0; i < sy.n; ++i) nrows += sy.hi(i) - sy.lo(i) + 1;
+    const int per_row = sx.n;
+    for (int rb = 0; rb < nrows; rb += RCAP / 2) {
+        const int nr = min(RCAP / 2, nrows - rb);
+        const int nrng = nr * per_row;
+        // range j -> (row index rb + j / per_row, column range j % per_row)
+        int cnt = 0;
+        if (t < nrng) {
+            int ri = rb + t / per_row;
+            const int n0 = sy.hi0 - sy.lo0 + 1;
+            const int row = (ri < n0) ? sy.lo0 + ri : sy.lo1 + (ri - n0);
+            const int c = t % per_row;
+            const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
+            S.r_e0[t] = e0;
+            cnt = e1 - e0;
+        }
+        // exclusive scan of the counts (nrng <= RCAP / 2 * 2 <= blockDim)
+        {
+            const int lane = t & 63, wid = t >> 6;
+            int x = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) S.wsum[wid] = x;
+            __syncthreads();
+            int before = 0;
+            for (int w = 0; w < wid; ++w) before += S.wsum[w];
+            if (t < RCAP) S.r_pre[t] = before + x - cnt;
+            if (t == blockDim.x - 1) S.r_pre[RCAP] = before + x;
+            __syncthreads();
+        }
+        const int total = S.r_pre[RCAP];
+        for (int f0 = 0; f0 < total; f0 += batch) {
+            const int m = min(batch, total - f0);
+            before(m);
+            for (int j = t; j < m; j += blockDim.x) {
+                const int f = f0 + j;
+                // range holding flat index f: last j with pre[j] <= f
+                int lo = 0, hi = nrng - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (S.r_pre[mid] <= f) lo = mid; else hi = mid - 1;
+                }
+                fn(S.r_e0[lo] + (f - S.r_pre[lo]));
+            }
+            __syncthreads();
+        }
+    }
+}
 
 __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
-    __shared__ int own[34 * 34];
-    __shared__ int cqx[DV_CAND_CAP], cqy[DV_CAND_CAP], clab[DV_CAND_CAP];
-    __shared__ int ncand;
-    __shared__ unsigned long long s_best;
+    __shared__ OwnerLds S;
     DevState *st = B.st;
     if (st->err) return;
+    if ((int)blockIdx.x >= B.ncells) {
+        match_block(B, blockIdx.x - B.ncells, gridDim.x - B.ncells);
+        return;
+    }
     const int K = st->K_now;
     const int now = 1 - st->sel;
     int *adj = B.comp[now].adj;
-    const int tx = blockIdx.x, ty = blockIdx.y;
+    const int tx = blockIdx.x % B.ntx, ty = blockIdx.x / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int W = tw + 2, H = th + 2;
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
     const int MX = 256 * lx, MY = 256 * ly;
-    const int *cs = B.cell_start;
+    const int OX = 256 * x0, OY = 256 * y0;   // tile origin (Q.8); coordinates below are relative
 
-    long long bd[WSITES];
-    int bl[WSITES], wX[WSITES], wY[WSITES];
+    // window sites of this thread: exact tile-relative Q.8 coordinates
+    double m2x[WSITES], m2y[WSITES], be[WSITES];
+    int bl[WSITES];
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
-        bd[i] = LLONG_MAX;
-        bl[i] = DV_EMPTY;
         const int w = t + i * DV_BLOCK;
         const int wx = w % W - 1, wy = w / W - 1;
-        wX[i] = 256 * pmod(x0 + wx, lx);
-        wY[i] = 256 * pmod(y0 + wy, ly);
+        m2x[i] = -2.0 * (256.0 * wx);
+        m2y[i] = -2.0 * (256.0 * wy);
+        be[i] = 1.0e300;
+        bl[i] = DV_EMPTY;
     }
+    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; }
+    __syncthreads();
+
+    // tile centre (absolute Q.8) and the window's relative x / y extent
+    const int tcx = OX + 128 * (tw - 1), tcy = OY + 128 * (th - 1);
+    const int wxlo = -256, wxhi = 256 * tw, wylo = -256, wyhi = 256 * th;
+
+    auto eval_owners = [&]() {
+        const int nc = S.ncand;
+        for (int c = 0; c < nc; ++c) {
+            const double cx = (double)S.cx[c], cy = (double)S.cy[c], kk = S.ck[c];
+            const int lab = S.lab[c];
+#pragma unroll
+            for (int i = 0; i < WSITES; ++i) {
+                const double e = fma(m2x[i], cx, fma(m2y[i], cy, kk));
+                if (e < be[i] || (e == be[i] && lab < bl[i])) { be[i] = e; bl[i] = lab; }
+            }
+        }
+    };
 
     if (K > 0) {
-        // --- a first bound on the distance from the tile centre to a centre
-        const int tcx = 256 * x0 + 128 * (tw - 1), tcy = 256 * y0 + 128 * (th - 1);
-        if (t == 0) s_best = ~0ull;
-        __syncthreads();
+        // --- a first bound: nearest centre to the tile centre in a growing
+        // square of cells
         for (int R = 1;; R *= 2) {
             const Span sx = span_cells(tx, R, B.ntx), sy = span_cells(ty, R, B.nty);
-            for (int ry = 0; ry < sy.n; ++ry)
-                for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row)
-                    for (int rx = 0; rx < sx.n; ++rx) {
-                        const int e0 = cs[row * B.ntx + sx.lo[rx]], e1 = cs[row * B.ntx + sx.hi[rx] + 1];
-                        for (int e = e0 + t; e < e1; e += DV_BLOCK) {
+            visit_items(B, S, sx, sy, 1 << 30,
+                        [&](int e) {
                             const int2 q = B.cell_q[e];
-                            atomicMin(&s_best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
-                        }
-                    }
-            __syncthreads();
-            if (s_best != ~0ull || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
-            __syncthreads();
+                            atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
+                        },
+                        [](int) {});
+            if (S.best != ~0ull || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
         }
-        // --- every centre within r0 + 2h of the tile centre (h: half diagonal
-        // of the tile plus its ring) can own a site or inner-frame point here
+        // --- every centre within r0 + 2h of the tile centre (h: half
+        // diagonal of the window) can own a window site or inner-frame point
         const double hx = 0.5 * (tw + 1), hy = 0.5 * (th + 1);
-        const double rho = sqrt((double)s_best) / 256.0 + 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
-        const double rq = 256.0 * rho;
+        const double rho = sqrt((double)S.best) / 256.0 + 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
+        const double rq2 = (256.0 * rho) * (256.0 * rho);
         const double px = tcx / 256.0, py = tcy / 256.0;
         const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx);
         const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), ly);
-        if (t == 0) ncand = 0;
-        __syncthreads();
-        // rows are visited one at a time; the LDS list is evaluated and
-        // emptied whenever the next batch could overflow it
-        for (int ry = 0; ry < sy.n; ++ry)
-            for (int row = sy.lo[ry]; row <= sy.hi[ry]; ++row) {
-                int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-                a0 = cs[row * B.ntx + sx.lo[0]];
-                a1 = cs[row * B.ntx + sx.hi[0] + 1];
-                if (sx.n == 2) {
-                    b0 = cs[row * B.ntx + sx.lo[1]];
-                    b1 = cs[row * B.ntx + sx.hi[1] + 1];
-                }
-                const int na = a1 - a0, total = na + (b1 - b0);
-                for (int base = 0; base < total; base += DV_CAND_CAP) {
-                    const int m = min(DV_CAND_CAP, total - base);
-                    if (ncand + m > DV_CAND_CAP) {
-                        // evaluate and empty the list
-                        const int nc = ncand;
-                        for (int c = 0; c < nc; ++c) {
-                            const int qx = cqx[c], qy = cqy[c], lab = clab[c];
-#pragma unroll
-                            for (int i = 0; i < WSITES; ++i) {
-                                const long long d = d2q(wX[i], wY[i], qx, qy, MX, MY);
-                                if (d < bd[i] || (d == bd[i] && lab < bl[i])) { bd[i] = d; bl[i] = lab; }
-                            }
-                        }
-                        __syncthreads();
-                        if (t == 0) ncand = 0;
-                        __syncthreads();
+        visit_items(
+            B, S, sx, sy, CAND_BATCH,
+            [&](int e) {
+                const int2 q = B.cell_q[e];
+                if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) > rq2) return;
+                // images of the centre that are the minimum image of some
+                // window point: relative offset within [-M/2, M/2] of it
+                const int rx = q.x - OX, ry = q.y - OY;
+                const int kx0 = (int)ceil((double)(wxlo - rx - MX / 2) / MX);
+                const int kx1 = (int)floor((double)(wxhi - rx + MX / 2) / MX);
+                const int ky0 = (int)ceil((double)(wylo - ry - MY / 2) / MY);
+                const int ky1 = (int)floor((double)(wyhi - ry + MY / 2) / MY);
+                const int lab = B.cell_items[e];
+                for (int kx = kx0; kx <= kx1; ++kx)
+                    for (int ky = ky0; ky <= ky1; ++ky) {
+                        const int cx = rx + kx * MX, cy = ry + ky * MY;
+                        const int slot = atomicAdd(&S.ncand, 1);
+                        S.cx[slot] = cx;
+                        S.cy[slot] = cy;
+                        S.ck[slot] = (double)cx * cx + (double)cy * cy;
+                        S.lab[slot] = lab;
                     }
-                    for (int j = t; j < m; j += DV_BLOCK) {
-                        const int f = base + j;
-                        const int e = f < na ? a0 + f : b0 + (f - na);
-                        const int2 q = B.cell_q[e];
-                        const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
-                        if ((double)d <= rq * rq) {
-                            const int slot = atomicAdd(&ncand, 1);
-                            cqx[slot] = q.x;
-                            cqy[slot] = q.y;
-                            clab[slot] = B.cell_items[e];
-                        }
-                    }
+            },
+            [&](int m) {
+                // evaluate and empty the list when this batch could overflow it
+                if (S.ncand + m * IMG_MAX > DV_CAND_CAP) {
+                    eval_owners();
+                    __syncthreads();
+                    if (t == 0) { S.ncand = 0; S.nchunks += 1; }
                     __syncthreads();
                 }
-            }
-        const int nc = ncand;
-        for (int c = 0; c < nc; ++c) {
-            const int qx = cqx[c], qy = cqy[c], lab = clab[c];
-#pragma unroll
-            for (int i = 0; i < WSITES; ++i) {
-                const long long d = d2q(wX[i], wY[i], qx, qy, MX, MY);
-                if (d < bd[i] || (d == bd[i] && lab < bl[i])) { bd[i] = d; bl[i] = lab; }
-            }
-        }
+            });
+        eval_owners();
     }
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
         const int w = t + i * DV_BLOCK;
-        if (w < W * H) own[(w / W) * 34 + (w % W)] = bl[i];
+        if (w < W * H) S.own[(w / W) * 34 + (w % W)] = bl[i];
     }
     __syncthreads();
 
-    const int cx = t & 31, ry = t >> 5;
+    // --- frame gaps and the neighbour rules.  A wave colours the inner-frame
+    // points its lanes need one at a time: the lanes share the candidates and
+    // reduce the exact (distance, label) minimum.  After a candidate-list
+    // overflow the asking lane uses the exact grid search instead.
+    const bool in_lds = S.nchunks == 0;
+    const int ncl = S.ncand;
+    auto emit = [&](int a, int b) {
+        const int slot = atomicAdd(&S.npair, 1);
+        if (slot < PAIR_CAP) {
+            S.pair[slot] = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+        } else {
+            row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, st);
+            row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, st);
+        }
+    };
+    const int cx = t & 31, ry = t >> 5, lane = t & 63;
+    unsigned pend = 0;   // bit 4i + r: site i needs the colour of inner-frame point r
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
         if (cx >= tw || y >= th) continue;
         const int c = (y + 1) * 34 + cx + 1;
-        const int ck = own[c];
-        if (B.keep_maps) B.owner[(size_t)(y0 + y) * lx + x0 + cx] = ck;
-        if (ck == DV_EMPTY) continue;
+        const int ckk = S.own[c];
+        if (B.keep_maps) B.owner[(size_t)(y0 + y) * lx + x0 + cx] = ckk;
+        if (ckk == DV_EMPTY) continue;
         int f[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = own[c + FRY[k] * 34 + FRX[k]];
+        for (int k = 0; k < 8; ++k) f[k] = S.own[c + FRY[k] * 34 + FRX[k]];
         int gaps = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -249,65 +384,80 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
             gaps += (a != b && a != DV_EMPTY && b != DV_EMPTY) ? 1 : 0;
         }
         if (gaps < 3) continue;
-        const int gx = x0 + cx, gy = y0 + y;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int tg = f[2 * r];
             const int pa = f[(2 * r + 2) & 7], pb = f[(2 * r + 7) & 7];
-            if (tg != DV_EMPTY && pa != pb && tg != ck) emit(B, adj, min(ck, tg), max(ck, tg));
+            if (tg != DV_EMPTY && pa != pb && tg != ckk) emit(min(ckk, tg), max(ckk, tg));
             const int dg = f[2 * r + 1];
-            if (dg != DV_EMPTY && dg != ck && pa != pb && pa != tg) {
-                int X = 256 * gx + INX[r], Y = 256 * gy + INY[r];
+            if (dg != DV_EMPTY && dg != ckk && pa != pb && pa != tg) pend |= 1u << (4 * i + r);
+        }
+    }
+    for (;;) {
+        const unsigned long long busy = __ballot(pend != 0);
+        if (busy == 0) break;
+        const int src = __ffsll(busy) - 1;
+        const int bit = __shfl(pend ? __ffs(pend) - 1 : 0, src, 64);
+        const int i = bit >> 2, r = bit & 3;
+        const int qsx = src & 31, qsy = ((t >> 6) << 1) + (src >> 5) + 8 * i;
+        int m;
+        if (in_lds) {
+            const double qx = 256.0 * qsx + INX[r], qy = 256.0 * qsy + INY[r];
+            double bee = 1.0e300;
+            int bll = DV_EMPTY;
+            for (int k = lane; k < ncl; k += 64) {
+                const double e = fma(-2.0 * qx, (double)S.cx[k], fma(-2.0 * qy, (double)S.cy[k], S.ck[k]));
+                const int lab = S.lab[k];
+                if (e < bee || (e == bee && lab < bll)) { bee = e; bll = lab; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double e2 = __shfl_xor(bee, o, 64);
+                const int l2 = __shfl_xor(bll, o, 64);
+                if (e2 < bee || (e2 == bee && l2 < bll)) { bee = e2; bll = l2; }
+            }
+            m = bll;
+        } else {
+            m = 0;
+            if (lane == src) {
+                int X = OX + 256 * qsx + INX[r], Y = OY + 256 * qsy + INY[r];
                 if (X < 0) X += MX;
                 if (Y < 0) Y += MY;
-                const int m = point_nearest(B, X, Y);
-                if (m == dg || m == ck) emit(B, adj, min(ck, dg), max(ck, dg));
+                m = point_nearest(B, X, Y);
             }
+            m = __shfl(m, src, 64);
+        }
+        if (lane == src) {
+            pend &= ~(1u << bit);
+            const int c = (qsy + 1) * 34 + qsx + 1;
+            const int ckk = S.own[c];
+            const int dg = S.own[c + FRY[2 * r + 1] * 34 + FRX[2 * r + 1]];
+            if (m == dg || m == ckk) emit(min(ckk, dg), max(ckk, dg));
         }
     }
-}
-
-// Sort each row ascending; DV_EMPTY padding stays at the end.
-__global__ __launch_bounds__(256) void k_rows(Bufs B) {
-    DevState *st = B.st;
-    if (st->err) return;
-    const int K = st->K_now;
-    const CompBuf C = B.comp[1 - st->sel];
-    int e2 = 0;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-        int *row = C.adj + (size_t)k * B.maxdeg;
-        int n = 0;
-        while (n < B.maxdeg && row[n] != DV_EMPTY) ++n;
-        for (int i = 1; i < n; ++i) {
-            const int v = row[i];
-            int j = i - 1;
-            while (j >= 0 && row[j] > v) { row[j + 1] = row[j]; --j; }
-            row[j + 1] = v;
-        }
-        C.deg[k] = n;
-        e2 += n;
+    __syncthreads();
+    // --- distinct couples of the tile go into both rows, one thread each
+    const int np = min(S.npair, PAIR_CAP);
+    for (int i = t; i < 2 * np; i += DV_BLOCK) {
+        const unsigned long long key = S.pair[i >> 1];
+        bool first = true;
+        for (int j = 0; j < (i >> 1); ++j)
+            if (S.pair[j] == key) { first = false; break; }
+        if (!first) continue;
+        const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
+        if (i & 1) row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, st);
+        else row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, st);
     }
-    for (int o = 32; o > 0; o >>= 1) e2 += __shfl_down(e2, o, 64);
-    if ((threadIdx.x & 63) == 0 && e2) atomicAdd(&st->E2_now, e2);
 }
 
 }  // namespace
 
 void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P) {
-    const int kgrid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
+    const int fgrid = (int)std::min<long long>((B.kmax + 1023) / 1024, 256);
+    const int mgrid = (int)std::min<long long>((B.kmax + 3) / 4, 2048);
     P.begin(ST_FINALIZE, s);
-    hipLaunchKernelGGL(k_finalize, dim3(kgrid), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(k_finalize, dim3(fgrid), dim3(1024), 0, s, B);
     P.end(ST_FINALIZE, s);
-    P.begin(ST_GRID_SCAN, s);
-    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, B);
-    P.end(ST_GRID_SCAN, s);
-    P.begin(ST_GRID_SCATTER, s);
-    hipLaunchKernelGGL(k_grid_scatter, dim3(kgrid), dim3(256), 0, s, B);
-    P.end(ST_GRID_SCATTER, s);
     P.begin(ST_OWNER_EDGES, s);
-    hipLaunchKernelGGL(k_owner_edges, dim3(B.ntx, B.nty), dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_owner_edges, dim3(B.ncells + mgrid), dim3(DV_BLOCK), 0, s, B);
     P.end(ST_OWNER_EDGES, s);
-    P.begin(ST_ROWS, s);
-    hipLaunchKernelGGL(k_rows, dim3(kgrid), dim3(256), 0, s, B);
-    P.end(ST_ROWS, s);
 }

@@ -30,9 +30,8 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
            "dv_status_str", "dv_last_error")
 
-STAGES = ("tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "grid_scan",
-          "grid_scatter", "owner_edges", "rows", "match", "diff_count", "diff_scan", "diff_write",
-          "commit")
+STAGES = ("tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "owner_edges",
+          "diff")
 
 
 class DVConfig(ctypes.Structure):

@@ -229,3 +229,15 @@ def test_grf4096_full_size():
     sim, spec = synth.workload("grf4096")
     fields = list(sim.frames(2))
     run_sequence(fields, spec["threshold"], kmax=32768, tag="grf4096")
+
+
+def test_sparse_cluster_exercises_candidate_overflow():
+    """1600 one-site components packed in one corner of an empty lattice:
+    far tiles must consider every centre, more than one LDS chunk holds."""
+    L = 512
+    f = np.zeros((L, L), np.float32)
+    f[10:90:2, 20:100:2] = 1.0
+    g = f.copy()
+    g[10:90:2, 20:100:2] = 0.0
+    g[11:91:2, 21:101:2] = 1.0          # the whole cluster moves by (1, 1)
+    run_sequence([f, g], 0.5, kmax=2048, tag="cluster")
