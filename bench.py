@@ -14,6 +14,13 @@ Reported beside the throughput:
                 timed region; algorithmic bytes per launch / mean duration
   latency_ms    p50 / p99 of push -> flips returned (host-synchronous loop)
   cpu_baseline  the CPU oracle on a bounded sample of the same frames
+
+HBM traffic of the roofline stage comes from two rocprofv3 counter runs
+(FETCH_SIZE, then WRITE_SIZE) of this script with --copy-probe-mib, which first
+runs a plain elementwise copy of known size in the same process; the counters
+of that copy give the scale from counter KiB to bytes.  --counters-from turns
+the two CSV outputs into profiles/counters.json, keyed by the stage's source
+hash so that a changed kernel reports traffic null until counted again.
 """
 from __future__ import annotations
 
@@ -21,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -71,6 +79,61 @@ def counter_traffic(stage: str, workload: str, maps: bool):
     return int(round(e["bytes_per_dispatch"]))
 
 
+COPY_PROBE_REPS = 8
+
+
+def copy_probe(mib: int):
+    """A plain elementwise copy (read 4 B, write 4 B per element) of known size,
+    the calibration kernel for the HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(COPY_PROBE_REPS):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def _read_counter_csv(path: str):
+    """(kernel name, counter value) per dispatch from a rocprofv3 counter CSV."""
+    import csv
+    out = {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            key = (row.get("Dispatch_Id") or row.get("Correlation_Id"), row["Counter_Name"])
+            out[key] = (row["Kernel_Name"], float(row["Counter_Value"]))
+    return list(out.values())
+
+
+def counters_from(fetch_csv: str, write_csv: str, stage: str, workload: str, maps: bool,
+                  copy_mib: int):
+    """Scaled HBM bytes per dispatch of `stage` from FETCH_SIZE / WRITE_SIZE runs."""
+    import statistics
+    kname = "k_" + stage
+    res = {}
+    for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _read_counter_csv(path)
+        ker = [v for k, v in rows if re.search(r"\b%s\b" % kname, k)]
+        cpy = [v for k, v in rows if "neg" in k.lower()]
+        if not ker or not cpy:
+            raise SystemExit(f"{path}: no dispatches of {kname} or of the copy probe")
+        expect_kib = copy_mib * 1024.0
+        scale = expect_kib / statistics.median(cpy)
+        res[tag] = {"kib_per_dispatch": statistics.mean(ker), "dispatches": len(ker),
+                    "copy_kib_median": statistics.median(cpy), "copy_expected_kib": expect_kib,
+                    "scale": scale}
+    bytes_per = sum(r["kib_per_dispatch"] * r["scale"] * 1024.0 for r in res.values())
+    p = os.path.join(ROOT, "profiles", "counters.json")
+    d = json.load(open(p)) if os.path.exists(p) else {}
+    d[f"{stage}:{workload}:{'maps' if maps else 'flips'}"] = {
+        "source_sha": source_hash(stage), "bytes_per_dispatch": bytes_per, **res}
+    with open(p, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    print(json.dumps({"stage": stage, "bytes_per_dispatch": round(bytes_per), **res}))
+
+
 def make_frames(workload: str, frames: int | None):
     from paper_1607_00908_amd import synth
     sim, spec = synth.workload(workload)
@@ -110,7 +173,16 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run the counter calibration copy of this size first")
+    ap.add_argument("--counters-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/counters.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+
+    if args.counters_from:
+        counters_from(*args.counters_from, args.stage, args.workload, not args.flips_only,
+                      args.copy_probe_mib)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -120,6 +192,8 @@ def main():
     import torch
     from paper_1607_00908_amd import dv
 
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
     t0 = time.perf_counter()
     frames, spec = make_frames(args.workload, args.frames)
     spec["name"] = args.workload

@@ -159,7 +159,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
     const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
     const size_t segs = (size_t)B.ly * B.ntx;
-    bool ok = dalloc(c, &B.parent, N) && dalloc(c, &B.pieces, tiles * DV_TILE_SITES) &&
+    bool ok = dalloc(c, &B.parent, N) && dalloc(c, &B.lab16, N) &&
+              dalloc(c, &B.pieces, tiles * DV_TILE_SITES) &&
               dalloc(c, &B.npieces, tiles) && dalloc(c, &B.seg_mask, segs) &&
               dalloc(c, &B.seg_prefix, segs) && dalloc(c, &B.band_sum, (size_t)B.nty) &&
               dalloc(c, &B.acc_x, K) && dalloc(c, &B.acc_y, K) && dalloc(c, &B.acc_n, K) &&
@@ -340,7 +341,10 @@ dv_status dv_get_matching(dv_ctx *c, int32_t *phi, int32_t capacity, int32_t *n_
     if (KP > capacity) return fail(c, DV_ERR_CAPACITY, "matching buffer too small");
     if (KP == 0) return DV_OK;
     if (!phi) return fail(c, DV_ERR_ARG, "phi is NULL");
-    if (hipMemcpy(phi, c->B.phi, (size_t)KP * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    // Phi with dropped past points as -1, written to scratch on the device
+    launch_phi_out(c->B, c->d_edge_ab, c->stream);
+    if (hipMemcpyAsync(phi, c->d_edge_ab, (size_t)KP * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
     return DV_OK;
 }
@@ -352,7 +356,7 @@ void dv_destroy(dv_ctx *c) {
 }
 
 static const char *const STAGE_NAMES[ST_COUNT] = {
-    "tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "owner_edges", "diff"};
+    "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "diff", "place"};
 
 const char *dv_stage_name(int32_t stage) {
     return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;

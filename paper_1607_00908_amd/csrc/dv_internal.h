@@ -36,7 +36,7 @@ struct DevState {
     int32_t status;        // 0 accepted, else DV_ERR_CAPACITY of the last push
     int32_t K_past_cmp;    // K of the past frame used by the current comparison
     int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
-    int32_t done_diff;     // blocks of k_diff that have finished (last one resets)
+    int32_t done_spare;
     int32_t pad;
     int64_t frame;         // accepted frames
 };
@@ -63,11 +63,12 @@ struct Bufs {
     int32_t *parent;       // [N] union-find over tile-border sites and piece roots
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
+    uint16_t *lab16;       // [N] tile-local root of every site, 0xffff outside
     uint16_t *pieces;      // [tiles][DV_TILE_SITES] local roots of each tile
     int32_t *npieces;      // [tiles]
     uint32_t *seg_mask;    // [ly][ntx] component-root bits per (row, tile column)
-    int32_t *seg_prefix;   // [ly][ntx] roots before each segment (raster order)
-    int32_t *band_sum;     // [nty] roots per tile row band
+    int32_t *seg_prefix;   // [ly][ntx] roots before each segment within its band
+    int32_t *band_sum;     // [nty] roots per band of 32 rows
     // component accumulation (self-cleaning: finalize zeroes what it reads)
     long long *acc_x, *acc_y;
     int32_t *acc_n, *acc_amb, *acc_root;
@@ -81,7 +82,7 @@ struct Bufs {
     int32_t *phi;          // [K_max] past -> now
     int32_t *cnt;          // [K_max] preimages of each now label
     int32_t *inv;          // [K_max] now -> past (valid when cnt == 1)
-    int32_t *trigger;      // [K_max] local trigger per past label
+    int32_t *trigger;      // [K_max] local trigger per kept past label
     int32_t *nb, *na;      // [K_max] breaking / arising count per now row
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
     int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
@@ -92,8 +93,8 @@ struct Bufs {
 
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
-    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RANK_SCAN, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES,
-    ST_DIFF, ST_COUNT
+    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_DIFF,
+    ST_PLACE, ST_COUNT
 };
 
 // Optional event bracketing of one stage (measurement only).
@@ -119,5 +120,6 @@ void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P);
 // launchers (k_diff.hip)
 void launch_diff(const Bufs &B, hipStream_t s, Prof &P);
 // inspection helpers (k_diff.hip)
+void launch_phi_out(const Bufs &B, int32_t *d_out, hipStream_t s);
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,
                       hipStream_t s);

@@ -8,126 +8,102 @@
 // smaller now label, and staged in increasing order of the other end.  The
 // local trigger of p is set when the two rows differ.
 //
-// The last block to finish (atomic counter after a release fence) scans the
-// per-row counts, places the staged flips in canonical order (breaking first,
-// then arising, each by (a, b)) and commits the frame: the now buffer becomes
-// the past when the frame was accepted.
+// k_place (one block) then scans the per-row counts, places the staged flips
+// in canonical order (breaking first, then arising, each by (a, b)) and
+// commits the frame: the now buffer becomes the past when the frame was
+// accepted.  Kept past and now points correspond one to one, so the number of
+// dropped past points is K_past - (K_now - dropped now points).
 #include "dv_device.h"
 
 namespace {
 
 __global__ __launch_bounds__(256) void k_diff(Bufs B) {
-    __shared__ int wsum[16];
-    __shared__ int s_last;
-    __shared__ int s_red[3][4];
+    __shared__ int s_red[2][4];
     DevState *st = B.st;
-    const bool ok = st->err == 0;
+    if (st->err) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int KN = st->K_now;
     const int past = st->sel, now = 1 - past;
     const bool pv = st->past_valid != 0;
-    const int KP = pv ? st->K[past] : 0;
     const CompBuf P = B.comp[past], N = B.comp[now];
     const int D = B.maxdeg;
-    int e2 = 0, exn = 0, exp_ = 0;
-    if (ok) {
-        // dropped past points: Phi is reported as -1 (a concurrent reader of
-        // phi[q] skips q either way)
-        for (int p = blockIdx.x * blockDim.x + t; p < KP; p += gridDim.x * blockDim.x) {
-            const int n = B.phi[p];
-            if (n < 0 || B.cnt[n] != 1) {
-                B.trigger[p] = 0;
-                B.phi[p] = -1;
-                ++exp_;
+    int e2 = 0, exn = 0;
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
+        const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
+        const int cn = B.cnt[n];
+        const int p = B.inv[n];
+        const int dR = __popcll(__ballot(m != DV_EMPTY));
+        if (lane == 0) e2 += dR;
+        int cb = 0, ca = 0;
+        if (pv && cn != 1) {
+            if (lane == 0) ++exn;
+        } else if (pv) {
+            const int q = lane < D ? P.adj[(size_t)p * D + lane] : DV_EMPTY;
+            const int dT = __popcll(__ballot(q != DV_EMPTY));
+            const int mv = (m != DV_EMPTY && B.cnt[m] == 1) ? m : DV_EMPTY;
+            int tv = DV_EMPTY;
+            if (q != DV_EMPTY) {
+                const int nn = B.phi[q];
+                if (nn >= 0 && B.cnt[nn] == 1) tv = nn;
+            }
+            // slots are filled from the front: the first dR (dT) lanes
+            bool tin = false, min_ = false;
+            for (int k = 0; k < dR; ++k) tin |= (__shfl(mv, k, 64) == tv);
+            for (int k = 0; k < dT; ++k) min_ |= (__shfl(tv, k, 64) == mv);
+            const bool brk = tv != DV_EMPTY && !tin;
+            const bool ari = mv != DV_EMPTY && !min_;
+            const unsigned long long dmask = __ballot(brk || ari);
+            if (lane == 0) B.trigger[p] = dmask ? 1 : 0;
+            // each couple once, from the row of its smaller now label
+            const bool bo = brk && tv > n, ao = ari && mv > n;
+            cb = __popcll(__ballot(bo));
+            ca = __popcll(__ballot(ao));
+            int *stg = B.stage + (size_t)n * (2 * D) * 6;
+            const int bv = bo ? tv : DV_EMPTY, av = ao ? mv : DV_EMPTY;
+            int rb = 0, ra = 0;
+            for (int k = 0; k < dT; ++k) rb += (__shfl(bv, k, 64) < bv) ? 1 : 0;
+            for (int k = 0; k < dR; ++k) ra += (__shfl(av, k, 64) < av) ? 1 : 0;
+            if (bo) {
+                int *r = stg + 6 * rb;
+                r[0] = n; r[1] = tv; r[2] = p; r[3] = q; r[4] = -1; r[5] = 0;
+            }
+            if (ao) {
+                int *r = stg + 6 * (D + ra);
+                r[0] = n; r[1] = mv; r[2] = p; r[3] = B.inv[mv]; r[4] = 1; r[5] = 0;
             }
         }
-        const int nwaves = gridDim.x * (blockDim.x >> 6);
-        for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
-            const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
-            const int dR = __popcll(__ballot(m != DV_EMPTY));
-            if (lane == 0) e2 += dR;
-            int cb = 0, ca = 0;
-            if (pv && B.cnt[n] != 1) {
-                if (lane == 0) ++exn;
-            } else if (pv) {
-                const int p = B.inv[n];
-                const int q = lane < D ? P.adj[(size_t)p * D + lane] : DV_EMPTY;
-                const int dT = __popcll(__ballot(q != DV_EMPTY));
-                int tv = DV_EMPTY;
-                if (q != DV_EMPTY) {
-                    const int nn = B.phi[q];
-                    if (nn >= 0 && B.cnt[nn] == 1) tv = nn;
-                }
-                const int mv = (m != DV_EMPTY && B.cnt[m] == 1) ? m : DV_EMPTY;
-                // slots are filled from the front: the first dR (dT) lanes
-                bool tin = false, min_ = false;
-                for (int k = 0; k < dR; ++k) tin |= (__shfl(mv, k, 64) == tv);
-                for (int k = 0; k < dT; ++k) min_ |= (__shfl(tv, k, 64) == mv);
-                const bool brk = tv != DV_EMPTY && !tin;
-                const bool ari = mv != DV_EMPTY && !min_;
-                const unsigned long long dmask = __ballot(brk || ari);
-                if (lane == 0) B.trigger[p] = dmask ? 1 : 0;
-                // each couple once, from the row of its smaller now label
-                const bool bo = brk && tv > n, ao = ari && mv > n;
-                cb = __popcll(__ballot(bo));
-                ca = __popcll(__ballot(ao));
-                int *stg = B.stage + (size_t)n * (2 * D) * 6;
-                const int bv = bo ? tv : DV_EMPTY, av = ao ? mv : DV_EMPTY;
-                int rb = 0, ra = 0;
-                for (int k = 0; k < dT; ++k) rb += (__shfl(bv, k, 64) < bv) ? 1 : 0;
-                for (int k = 0; k < dR; ++k) ra += (__shfl(av, k, 64) < av) ? 1 : 0;
-                if (bo) {
-                    int *r = stg + 6 * rb;
-                    r[0] = n; r[1] = tv; r[2] = p; r[3] = q; r[4] = -1; r[5] = 0;
-                }
-                if (ao) {
-                    int *r = stg + 6 * (D + ra);
-                    r[0] = n; r[1] = mv; r[2] = p; r[3] = B.inv[mv]; r[4] = 1; r[5] = 0;
-                }
-            }
-            if (lane == 0) {
-                B.nb[n] = cb;
-                B.na[n] = ca;
-            }
+        if (lane == 0) {
+            B.nb[n] = cb;
+            B.na[n] = ca;
         }
     }
-    // block totals of the counters
     for (int o = 32; o > 0; o >>= 1) {
         e2 += __shfl_down(e2, o, 64);
         exn += __shfl_down(exn, o, 64);
-        exp_ += __shfl_down(exp_, o, 64);
     }
     if (lane == 0) {
         s_red[0][wid] = e2;
         s_red[1][wid] = exn;
-        s_red[2][wid] = exp_;
     }
     __syncthreads();
-    if (t == 0 && ok) {
-        int a = 0, b = 0, c = 0;
+    if (t == 0) {
+        int a = 0, b = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
             a += s_red[0][w];
             b += s_red[1][w];
-            c += s_red[2][w];
         }
         if (a) atomicAdd(&st->E2_now, a);
         if (b) atomicAdd(&st->n_excl_now, b);
-        if (c) atomicAdd(&st->n_excl_past, c);
     }
-    // ---- the last block: offsets, canonical placement, commit
-    // release: the barrier completes the block's stores, one thread writes
-    // the cache back and takes a ticket; acquire likewise in the last block
-    __syncthreads();
-    if (t == 0) {
-        __threadfence();
-        s_last = atomicAdd(&st->done_diff, 1) == (int)gridDim.x - 1;
-        if (s_last) __threadfence();
-    }
-    __syncthreads();
-    if (!s_last) return;
-    if (!ok) {
+}
+
+__global__ __launch_bounds__(1024) void k_place(Bufs B) {
+    __shared__ int wsum[16];
+    DevState *st = B.st;
+    const int t = threadIdx.x;
+    if (st->err) {
         if (t == 0) {
-            st->done_diff = 0;
             st->status = 2;   // DV_ERR_CAPACITY
             st->n_flips = 0;
             st->n_break = 0;
@@ -135,6 +111,10 @@ __global__ __launch_bounds__(256) void k_diff(Bufs B) {
         }
         return;
     }
+    const int KN = st->K_now;
+    const int past = st->sel, now = 1 - past;
+    const bool pv = st->past_valid != 0;
+    const int D = B.maxdeg;
     const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
     __syncthreads();
     const int nar = block_exclusive_scan(B.na, B.oa, KN, wsum);
@@ -150,17 +130,28 @@ __global__ __launch_bounds__(256) void k_diff(Bufs B) {
     }
     __syncthreads();
     if (t == 0) {
-        st->done_diff = 0;
+        const int KP = pv ? st->K[past] : 0;
+        st->n_excl_past = pv ? KP - (KN - st->n_excl_now) : 0;
         st->n_break = nbk;
         st->n_flips = nbk + nar;
         st->global_trigger = (nbk + nar) > 0 ? 1 : 0;
-        st->K_past_cmp = pv ? st->K[past] : 0;
+        st->K_past_cmp = KP;
         st->K[now] = KN;
         st->E[now] = st->E2_now / 2;
         st->sel = now;
         st->past_valid = 1;
         st->frame += 1;
         st->status = 0;
+    }
+}
+
+// Phi of the last comparison with dropped past points as -1 (inspection).
+__global__ __launch_bounds__(256) void k_phi_out(Bufs B, int *out) {
+    DevState *st = B.st;
+    const int KP = st->K_past_cmp;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < KP; p += gridDim.x * blockDim.x) {
+        const int n = B.phi[p];
+        out[p] = (n >= 0 && B.cnt[n] == 1) ? n : -1;
     }
 }
 
@@ -209,10 +200,18 @@ __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int
 }  // namespace
 
 void launch_diff(const Bufs &B, hipStream_t s, Prof &P) {
-    const int grid = (int)std::min<long long>((B.kmax + 3) / 4, 1024);
+    const int grid = (int)std::min<long long>((B.kmax + 3) / 4, 2048);
     P.begin(ST_DIFF, s);
     hipLaunchKernelGGL(k_diff, dim3(grid), dim3(256), 0, s, B);
     P.end(ST_DIFF, s);
+    P.begin(ST_PLACE, s);
+    hipLaunchKernelGGL(k_place, dim3(1), dim3(1024), 0, s, B);
+    P.end(ST_PLACE, s);
+}
+
+void launch_phi_out(const Bufs &B, int32_t *d_out, hipStream_t s) {
+    const int grid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_phi_out, dim3(grid), dim3(256), 0, s, B, d_out);
 }
 
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,

@@ -5,17 +5,20 @@
 //                site and every tile-local root ("piece") gets an entry in the
 //                global parent array (global linear site indices);
 //   k_merge      unions across tile borders and the periodic seams;
-//   k_resolve    each piece finds its global root; component roots (which are
-//                the smallest linear index of each component) are marked in a
-//                bitmap of (row, tile column) segments;
-//   k_rank_scan  per band of 32 rows: exclusive prefix of the root bits in
-//                raster order -> canonical label of every root; K;
-//   k_relabel    re-runs the tile union-find, writes canonical labels and
-//                accumulates exact integer offsets from each component's root
-//                (signed minimum image) per piece, then per component.
+//   k_resolve    per band of 32 rows: each piece finds its global root;
+//                component roots (the smallest linear index of each component)
+//                are marked in a bitmap of (row, tile column) segments, which
+//                is scanned in raster order within the band;
+//   k_relabel    reads the tile-local roots written by k_tile_ccl, writes
+//                canonical labels and accumulates exact integer offsets from
+//                each component's root (signed minimum image) per piece, then
+//                per component.
 // Union-find always links the larger index under the smaller one, so the root
 // of every tree is its smallest index.
-#include "dv_internal.h"
+#include "dv_device.h"
+
+#define RES_TILES 1024   // tiles of a band handled per pass of k_resolve
+#define RL_BANDS 2048    // bands whose offsets k_relabel keeps in LDS
 
 namespace {
 
@@ -24,10 +27,23 @@ __device__ __forceinline__ bool is_in(float v, float thr, int phase) {
 }
 
 // ---- union-find in LDS over tile-local indices -----------------------------
-__device__ __forceinline__ int lfind(const int *L, int a) {
+// Every parent is a smaller index than its child, so walks end at a root.
+// Finds shorten the path they walk with plain stores (path splitting: a node
+// gets its grandparent).  Such a store can replace a hook that another thread
+// has just made on the same node; but that node had already stopped being a
+// root, so the hooking thread's atomicMin returned its earlier parent and
+// the thread retries with it: no union is lost.
+__device__ __forceinline__ int lfind(int *L, int a) {
     int p = L[a];
-    while (p != a) { a = p; p = L[a]; }
-    return a;
+    if (p == a) return a;
+    int prev = a;
+    for (;;) {
+        const int next = L[p];
+        if (next == p) return p;
+        L[prev] = next;
+        prev = p;
+        p = next;
+    }
 }
 
 __device__ void lunite(int *L, int a, int b) {
@@ -50,9 +66,28 @@ __device__ void lunite(int *L, int a, int b) {
 }
 
 // ---- union-find in global memory over linear site indices -------------------
-__device__ __forceinline__ int gfind(const int *P, int a) {
+// Same path shortening as lfind.  gfind_ro walks without writing: it is the
+// find of a pass that also stores final roots, which a concurrent shortening
+// store could otherwise replace with an intermediate ancestor.
+__device__ __forceinline__ int gfind(int *P, int a) {
     int p = P[a];
-    while (p != a) { a = p; p = P[a]; }
+    if (p == a) return a;
+    int prev = a;
+    for (;;) {
+        const int next = P[p];
+        if (next == p) return p;
+        P[prev] = next;
+        prev = p;
+        p = next;
+    }
+}
+
+__device__ __forceinline__ int gfind_ro(const int *P, int a) {
+    int p = P[a];
+    while (p != a) {
+        a = p;
+        p = P[a];
+    }
     return a;
 }
 
@@ -139,12 +174,21 @@ __device__ void tile_ccl(const Bufs &B, int x0, int y0, int tw, int th, int *L, 
         }
     }
     __syncthreads();
-    // roots of the run starts, then every site takes its run start's root
+    // roots of the run starts, then every site takes its run start's root.
+    // The roots are stored only after a barrier: a find that is still
+    // shortening its path could otherwise overwrite a stored root with an
+    // intermediate ancestor.
+    int root[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
-        if (L[s] == s || (L[s] >= 0 && L[s] < s && run_start(rowm[y], cx) == cx)) L[s] = lfind(L, s);
+        const int v = L[s];
+        root[i] = (v >= 0 && v < s && run_start(rowm[y], cx) == cx) ? lfind(L, s) : -1;
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (root[i] >= 0) L[(ry + 8 * i) * 32 + cx] = root[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -182,9 +226,9 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
     }
     if (t == 0) {
         B.cell_count[tile] = 0;
-        if (tx == 0) B.band_sum[ty] = 0;
         npc = 0;
     }
+    if (t < th) B.seg_mask[(size_t)(y0 + t) * B.ntx + tx] = 0u;
     {   // empty the rows of the buffer this frame will fill
         const size_t total = (size_t)st->rows_dirty[now] * B.maxdeg;
         const size_t stride = (size_t)gridDim.x * gridDim.y * DV_BLOCK;
@@ -199,13 +243,20 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
         const int r = L[s];
-        if (r < 0) continue;
+        const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
+        if (cx < tw && y < th)
+            B.lab16[(size_t)(y0 + y) * B.lx + x0 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
+        if (r < 0) {
+            // an outside border site is marked so that merging needs no field
+            if (border && cx < tw && y < th) B.parent[(y0 + y) * B.lx + x0 + cx] = -1;
+            continue;
+        }
         const int g = (y0 + y) * B.lx + x0 + cx;
         if (r == s) {
             const int slot = atomicAdd(&npc, 1);
             B.pieces[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
             B.parent[g] = g;
-        } else if (cx == 0 || y == 0 || cx == tw - 1 || y == th - 1) {
+        } else if (border) {
             B.parent[g] = (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
         }
     }
@@ -213,7 +264,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
     if (t == 0) B.npieces[tile] = npc;
 }
 
-// Unions between inside sites of neighbouring tiles.  Thread j < 32 takes row
+// Unions between inside sites of neighbouring tiles (every tile-border site
+// holds its piece root in the parent array, or -1 when outside).  Thread j < 32 takes row
 // j of the tile's last column against the next column (periodic); thread
 // 32 + j takes column j of the last row against the next row.  Together they
 // cover every adjacent pair that crosses a tile border, including the
@@ -228,88 +280,87 @@ __global__ __launch_bounds__(64) void k_merge(Bufs B) {
         if (j >= th) return;
         const int x = x0 + tw - 1, y = y0 + j;
         const int s = y * lx + x;
-        if (!is_in(B.field[s], B.thr, B.phase)) return;
         const int xn = (x + 1 == lx) ? 0 : x + 1;
-        for (int dy = -1; dy <= 1; ++dy) {
-            if (B.conn == 4 && dy != 0) continue;
-            int yn = y + dy;
+        int u[3];
+        for (int k = 0; k < 3; ++k) {
+            int yn = y + k - 1;
             yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
-            const int u = yn * lx + xn;
-            if (is_in(B.field[u], B.thr, B.phase)) gunite(B.parent, s, u);
+            u[k] = yn * lx + xn;
+        }
+        // every border site holds its piece root, or -1 when outside
+        const int ps = B.parent[s];
+        const int pu0 = B.parent[u[0]], pu1 = B.parent[u[1]], pu2 = B.parent[u[2]];
+        if (ps < 0) return;
+        if (pu1 >= 0) gunite(B.parent, s, u[1]);
+        if (B.conn == 8) {
+            if (pu0 >= 0) gunite(B.parent, s, u[0]);
+            if (pu2 >= 0) gunite(B.parent, s, u[2]);
         }
     } else {
         j -= 32;
         if (j >= tw) return;
         const int x = x0 + j, y = y0 + th - 1;
         const int s = y * lx + x;
-        if (!is_in(B.field[s], B.thr, B.phase)) return;
         const int yn = (y + 1 == ly) ? 0 : y + 1;
-        for (int dx = -1; dx <= 1; ++dx) {
-            if (B.conn == 4 && dx != 0) continue;
-            int xn = x + dx;
+        int u[3];
+        for (int k = 0; k < 3; ++k) {
+            int xn = x + k - 1;
             xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
-            const int u = yn * lx + xn;
-            if (is_in(B.field[u], B.thr, B.phase)) gunite(B.parent, s, u);
+            u[k] = yn * lx + xn;
+        }
+        const int ps = B.parent[s];
+        const int pu0 = B.parent[u[0]], pu1 = B.parent[u[1]], pu2 = B.parent[u[2]];
+        if (ps < 0) return;
+        if (pu1 >= 0) gunite(B.parent, s, u[1]);
+        if (B.conn == 8) {
+            if (pu0 >= 0) gunite(B.parent, s, u[0]);
+            if (pu2 >= 0) gunite(B.parent, s, u[2]);
         }
     }
 }
 
-// Each piece finds its component root; roots are marked per segment.
-__global__ __launch_bounds__(DV_BLOCK) void k_resolve(Bufs B) {
-    __shared__ uint32_t mask[DV_TILE];
-    __shared__ int nroot;
-    const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
-    const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
-    const int th = min(DV_TILE, B.ly - y0);
-    const int t = threadIdx.x;
-    if (t < DV_TILE) mask[t] = 0u;
-    if (t == 0) nroot = 0;
-    __syncthreads();
-    const int np = B.npieces[tile];
-    for (int i = t; i < np; i += DV_BLOCK) {
-        const int r = B.pieces[(size_t)tile * DV_TILE_SITES + i];
-        const int g = (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
-        const int root = gfind(B.parent, g);
-        if (root != g) {
-            B.parent[g] = root;
-        } else {
-            atomicOr(&mask[r >> 5], 1u << (r & 31));
-            atomicAdd(&nroot, 1);
-        }
-    }
-    __syncthreads();
-    if (t < th) B.seg_mask[(size_t)(y0 + t) * B.ntx + tx] = mask[t];
-    if (t == 0 && nroot) atomicAdd(&B.band_sum[ty], nroot);
-}
-
-// Exclusive prefix (raster order) of root bits, one block per band of rows.
+// One block per band of 32 rows: every piece of the band's tiles finds its
+// component root (the smallest linear index of the component); component
+// roots set their bit in the band's (row, tile column) segment words, which
+// are then scanned in raster order.  seg_prefix holds the number of roots
+// before each segment within the band, band_sum the band's total.
 // Segment (y, tile column c) covers sites y*lx + 32c .. 32c+31, so raster
 // order of segments is the row-major order of the [ly][ntx] arrays.
-__global__ __launch_bounds__(DV_BLOCK) void k_rank_scan(Bufs B) {
-    __shared__ int wsum[DV_BLOCK / 64];
-    __shared__ int s_off;
+__global__ __launch_bounds__(1024) void k_resolve(Bufs B) {
+    __shared__ int pre[RES_TILES + 1];
+    __shared__ int wsum[16];
     const int ty = blockIdx.x, t = threadIdx.x;
-    const int lane = t & 63, wid = t >> 6;
     const int y0 = ty * DV_TILE, th = min(DV_TILE, B.ly - y0);
-    // offset of this band = roots in all earlier bands
-    int part = 0;
-    for (int b = t; b < ty; b += DV_BLOCK) part += B.band_sum[b];
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
-    if (lane == 0) wsum[wid] = part;
-    __syncthreads();
-    if (t == 0) {
-        int s = 0;
-        for (int w = 0; w < DV_BLOCK / 64; ++w) s += wsum[w];
-        s_off = s;
+    const int ntx = B.ntx;
+    for (int c0 = 0; c0 < ntx; c0 += RES_TILES) {
+        const int nt = min(RES_TILES, ntx - c0);
+        const int tile0 = ty * ntx + c0;
+        // pieces of tiles c0 .. c0 + nt - 1, numbered through a block scan
+        const int total = block_exclusive_scan(B.npieces + tile0, pre, nt, wsum);
+        __syncthreads();
+        for (int f = t; f < total; f += blockDim.x) {
+            int lo = 0, hi = nt - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            const int tx = c0 + lo;
+            const int r = B.pieces[(size_t)(tile0 + lo) * DV_TILE_SITES + (f - pre[lo])];
+            const int g = (y0 + (r >> 5)) * B.lx + tx * DV_TILE + (r & 31);
+            const int root = gfind_ro(B.parent, g);
+            if (root != g) B.parent[g] = root;
+            else atomicOr(&B.seg_mask[(size_t)(y0 + (r >> 5)) * ntx + tx], 1u << (r & 31));
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    int carry = s_off;
-    const int n = th * B.ntx;
-    const size_t base = (size_t)y0 * B.ntx;
-    for (int c0 = 0; c0 < n; c0 += DV_BLOCK) {
+    // raster-order prefix of the root bits within the band
+    const int n = th * ntx;
+    const size_t base = (size_t)y0 * ntx;
+    const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
         const int i = c0 + t;
         const int v = i < n ? __popc(B.seg_mask[base + i]) : 0;
-        // inclusive scan within the wave
         int x = v;
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(x, o, 64);
@@ -322,16 +373,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_rank_scan(Bufs B) {
         for (int w = 0; w < wid; ++w) before += wsum[w];
         if (i < n) B.seg_prefix[base + i] = before + x - v;
         int tot = 0;
-        for (int w = 0; w < DV_BLOCK / 64; ++w) tot += wsum[w];
+        for (int w = 0; w < nw; ++w) tot += wsum[w];
         carry += tot;
     }
-    if (ty == B.nty - 1 && t == 0) {
-        DevState *st = B.st;
-        const int K = carry;
-        st->K_now = K;
-        if (K > B.kmax) st->err |= DV_E_KMAX;
-        st->rows_dirty[1 - st->sel] = min(K, B.kmax);
-    }
+    if (t == 0) B.band_sum[ty] = carry;
 }
 
 __device__ __forceinline__ int wrap_off(int v, int L) {
@@ -348,33 +393,51 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
     __shared__ int prx[DV_TILE_SITES], pry[DV_TILE_SITES];
     __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
     __shared__ uint8_t in34[34 * 34];
-    __shared__ uint32_t rowm[DV_TILE];
+    __shared__ int boff[RL_BANDS];
+    __shared__ int wsum[16];
     DevState *st = B.st;
-    if (st->err) return;
-    const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
+    const int tx = blockIdx.x, ty = blockIdx.y;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
 
-    // inside flags of the tile and its one-site ring (periodic)
+    // tile-local roots of the tile and inside flags of its one-site ring
+    // (periodic), as written by k_tile_ccl
     for (int w = t; w < (tw + 2) * (th + 2); w += DV_BLOCK) {
         const int wx = w % (tw + 2) - 1, wy = w / (tw + 2) - 1;
         int gx = x0 + wx, gy = y0 + wy;
         gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
         gy = gy < 0 ? gy + ly : (gy >= ly ? gy - ly : gy);
-        in34[(wy + 1) * 34 + wx + 1] = is_in(B.field[(size_t)gy * lx + gx], B.thr, B.phase) ? 1 : 0;
+        const uint16_t v = B.lab16[(size_t)gy * lx + gx];
+        in34[(wy + 1) * 34 + wx + 1] = v != 0xffff ? 1 : 0;
+        if (wx >= 0 && wx < tw && wy >= 0 && wy < th) L[wy * 32 + wx] = v != 0xffff ? (int)v : -1;
     }
-    tile_ccl(B, x0, y0, tw, th, L, rowm);
+    for (int s = t; s < DV_TILE_SITES; s += DV_BLOCK)
+        if ((s & 31) >= tw || (s >> 5) >= th) L[s] = -1;
+    // roots in the bands before each band (exclusive prefix of band totals);
+    // the first block publishes K and the capacity check
+    // (ly <= 65536, so there are at most RL_BANDS bands)
+    const int K = block_exclusive_scan(B.band_sum, boff, B.nty, wsum);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+        st->K_now = K;
+        if (K > B.kmax) st->err |= DV_E_KMAX;
+        st->rows_dirty[1 - st->sel] = min(K, B.kmax);
+    }
+    __syncthreads();
 
-    const int np = B.npieces[tile];
-    for (int i = t; i < np; i += DV_BLOCK) {
-        const int r = B.pieces[(size_t)tile * DV_TILE_SITES + i];
-        const int g = (y0 + (r >> 5)) * lx + x0 + (r & 31);
+    // each piece root (a site that is its own tile-local root) looks up the
+    // component root and its canonical rank
+    const int cx = t & 31, ry = t >> 5;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i, r = y * 32 + cx;
+        if (L[r] != r) continue;
+        const int g = (y0 + y) * lx + x0 + cx;
         const int G = B.parent[g];          // component root (compressed)
         const int gx = G % lx, gy = G / lx;
         const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
         const uint32_t below = (1u << (gx & 31)) - 1u;
-        const int rank = B.seg_prefix[seg] + __popc(B.seg_mask[seg] & below);
+        const int rank = boff[gy / DV_TILE] + B.seg_prefix[seg] + __popc(B.seg_mask[seg] & below);
         prank[r] = rank;
         prx[r] = gx;
         pry[r] = gy;
@@ -385,7 +448,6 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
     }
     __syncthreads();
 
-    const int cx = t & 31, ry = t >> 5;
     const int hix = lx - 1 - (lx >> 1), hiy = ly - 1 - (ly >> 1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -415,8 +477,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
         if (amb && prank[r] < B.kmax) atomicOr(&B.acc_amb[prank[r]], 1);
     }
     __syncthreads();
-    for (int i = t; i < np; i += DV_BLOCK) {
-        const int r = B.pieces[(size_t)tile * DV_TILE_SITES + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i, r = y * 32 + cx;
+        if (L[r] != r) continue;
         const int rank = prank[r];
         if (rank >= B.kmax) continue;
         atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)(long long)psx[r]);
@@ -436,11 +500,8 @@ void launch_label(const Bufs &B, hipStream_t s, Prof &P) {
     hipLaunchKernelGGL(k_merge, tiles, dim3(64), 0, s, B);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
-    hipLaunchKernelGGL(k_resolve, tiles, dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_resolve, dim3(B.nty), dim3(1024), 0, s, B);
     P.end(ST_RESOLVE, s);
-    P.begin(ST_RANK_SCAN, s);
-    hipLaunchKernelGGL(k_rank_scan, dim3(B.nty), dim3(DV_BLOCK), 0, s, B);
-    P.end(ST_RANK_SCAN, s);
     P.begin(ST_RELABEL, s);
     hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), 0, s, B);
     P.end(ST_RELABEL, s);

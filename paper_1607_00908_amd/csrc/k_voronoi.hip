@@ -94,11 +94,12 @@ __global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
 }
 
 // Frame of a site (Sec. 3.2.2), cyclic: spx, spxpy, spy, spymx, smx, smxmy,
-// smy, smypx; inner-frame points a_k, b_k, c_k, d_k at (+-1/2, +-1/2).
-__constant__ int FRX[8] = {1, 1, 0, -1, -1, -1, 0, 1};
-__constant__ int FRY[8] = {0, 1, 1, 1, 0, -1, -1, -1};
-__constant__ int INX[4] = {128, -128, -128, 128};
-__constant__ int INY[4] = {128, 128, -128, -128};
+// smy, smypx; inner-frame points a_k, b_k, c_k, d_k at (+-1/2, +-1/2) in Q.8.
+// Written as expressions so that no table is read from memory.
+__device__ __forceinline__ int frx(int k) { return (k == 0 || k == 1 || k == 7) ? 1 : (k == 2 || k == 6) ? 0 : -1; }
+__device__ __forceinline__ int fry(int k) { return (k == 1 || k == 2 || k == 3) ? 1 : (k == 0 || k == 4) ? 0 : -1; }
+__device__ __forceinline__ int inx(int r) { return (r == 1 || r == 2) ? -128 : 128; }
+__device__ __forceinline__ int iny(int r) { return r >= 2 ? -128 : 128; }
 
 // Lock-free set insert into a row (slots fill from the front; DV_EMPTY marks
 // free slots).  Rows are 16-byte aligned (max_degree is a multiple of 4), so
@@ -125,6 +126,8 @@ __device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, DevState
 }
 
 #define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
+#define QCAP 512        // inner-frame queries answered per chunk
+#define TMP_CAP 256     // centres kept from the first pass
 
 // Phi_{P->N} (Sec. 3.2.3): one wave per past centre, nearest now centre by
 // the grid, exact, ties to the lowest label.
@@ -168,9 +171,14 @@ struct OwnerLds {
     int nranges;
     unsigned long long best;
     int wsum[16];
+    // centres seen in the first pass
+    int tmp[TMP_CAP];
+    int ntmp;
     // couples found by the tile, (a << 32 | b) with a < b
     unsigned long long pair[PAIR_CAP];
     int npair;
+    // inner-frame queries of one chunk: (site << 2) | r
+    int q[QCAP];
 };
 
 // Visit every item (index into the cell-ordered centre arrays) of the cells
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
         be[i] = 1.0e300;
         bl[i] = DV_EMPTY;
     }
-    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; }
+    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; }
     __syncthreads();
 
     // tile centre (absolute Q.8) and the window's relative x / y extent
@@ -287,59 +295,101 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
         }
     };
 
+    // candidate list entry for centre e: every image of the centre that is the
+    // minimum image of some window point (relative offset within [-M/2, M/2])
+    auto add_images = [&](int e, int2 q) {
+        const int rx = q.x - OX, ry = q.y - OY;
+        const int kx0 = (int)ceil((double)(wxlo - rx - MX / 2) / MX);
+        const int kx1 = (int)floor((double)(wxhi - rx + MX / 2) / MX);
+        const int ky0 = (int)ceil((double)(wylo - ry - MY / 2) / MY);
+        const int ky1 = (int)floor((double)(wyhi - ry + MY / 2) / MY);
+        const int lab = B.cell_items[e];
+        for (int kx = kx0; kx <= kx1; ++kx)
+            for (int ky = ky0; ky <= ky1; ++ky) {
+                const int cx = rx + kx * MX, cy = ry + ky * MY;
+                const int slot = atomicAdd(&S.ncand, 1);
+                if (slot >= DV_CAND_CAP) continue;   // overflow: caller falls back
+                S.cx[slot] = cx;
+                S.cy[slot] = cy;
+                S.ck[slot] = (double)cx * cx + (double)cy * cy;
+                S.lab[slot] = lab;
+            }
+    };
+    // radius around the tile centre that holds every centre able to own a
+    // window site or inner-frame point: bound + twice the window's half diagonal
+    const double hx = 0.5 * (tw + 1), hy = 0.5 * (th + 1);
+    const double hdiag2 = 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
+
     if (K > 0) {
-        // --- a first bound: nearest centre to the tile centre in a growing
-        // square of cells
-        for (int R = 1;; R *= 2) {
-            const Span sx = span_cells(tx, R, B.ntx), sy = span_cells(ty, R, B.nty);
-            visit_items(B, S, sx, sy, 1 << 30,
-                        [&](int e) {
-                            const int2 q = B.cell_q[e];
-                            atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
-                        },
-                        [](int) {});
-            if (S.best != ~0ull || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
-        }
-        // --- every centre within r0 + 2h of the tile centre (h: half
-        // diagonal of the window) can own a window site or inner-frame point
-        const double hx = 0.5 * (tw + 1), hy = 0.5 * (th + 1);
-        const double rho = sqrt((double)S.best) / 256.0 + 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
-        const double rq2 = (256.0 * rho) * (256.0 * rho);
-        const double px = tcx / 256.0, py = tcy / 256.0;
-        const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx);
-        const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), ly);
-        visit_items(
-            B, S, sx, sy, CAND_BATCH,
-            [&](int e) {
-                const int2 q = B.cell_q[e];
-                if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) > rq2) return;
-                // images of the centre that are the minimum image of some
-                // window point: relative offset within [-M/2, M/2] of it
-                const int rx = q.x - OX, ry = q.y - OY;
-                const int kx0 = (int)ceil((double)(wxlo - rx - MX / 2) / MX);
-                const int kx1 = (int)floor((double)(wxhi - rx + MX / 2) / MX);
-                const int ky0 = (int)ceil((double)(wylo - ry - MY / 2) / MY);
-                const int ky1 = (int)floor((double)(wyhi - ry + MY / 2) / MY);
-                const int lab = B.cell_items[e];
-                for (int kx = kx0; kx <= kx1; ++kx)
-                    for (int ky = ky0; ky <= ky1; ++ky) {
-                        const int cx = rx + kx * MX, cy = ry + ky * MY;
-                        const int slot = atomicAdd(&S.ncand, 1);
-                        S.cx[slot] = cx;
-                        S.cy[slot] = cy;
-                        S.ck[slot] = (double)cx * cx + (double)cy * cy;
-                        S.lab[slot] = lab;
-                    }
-            },
-            [&](int m) {
-                // evaluate and empty the list when this batch could overflow it
-                if (S.ncand + m * IMG_MAX > DV_CAND_CAP) {
-                    eval_owners();
-                    __syncthreads();
-                    if (t == 0) { S.ncand = 0; S.nchunks += 1; }
-                    __syncthreads();
+        // --- usual case, one pass: the 7x7 cells around the tile give a bound
+        // (nearest centre seen) and, when they cover the radius it implies,
+        // every candidate as well
+        const int R0 = 3;
+        const Span sx0 = span_cells(tx, R0, B.ntx), sy0 = span_cells(ty, R0, B.nty);
+        visit_items(B, S, sx0, sy0, 1 << 30,
+                    [&](int e) {
+                        const int2 q = B.cell_q[e];
+                        atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
+                        const int slot = atomicAdd(&S.ntmp, 1);
+                        if (slot < TMP_CAP) S.tmp[slot] = e;
+                    },
+                    [](int) {});
+        bool done = false;
+        if (S.best != ~0ull && S.ntmp <= TMP_CAP) {
+            const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
+            const int wlx = lx - DV_TILE * (B.ntx - 1), wly = ly - DV_TILE * (B.nty - 1);
+            const double cov_x = span_full(sx0, B.ntx) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wlx);
+            const double cov_y = span_full(sy0, B.nty) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wly);
+            if (rho <= cov_x && rho <= cov_y) {
+                const double rq2 = (256.0 * rho) * (256.0 * rho);
+                const int n = S.ntmp;
+                for (int j = t; j < n; j += DV_BLOCK) {
+                    const int e = S.tmp[j];
+                    const int2 q = B.cell_q[e];
+                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(e, q);
                 }
-            });
+                __syncthreads();
+                done = S.ncand <= DV_CAND_CAP;
+                __syncthreads();
+                if (!done && t == 0) S.ncand = 0;
+                __syncthreads();
+            }
+        }
+        if (!done) {
+            // --- general case: a growing square of cells for the bound, then
+            // every cell meeting the disc, evaluated in LDS-sized chunks
+            for (int R = R0;; R *= 2) {
+                if (S.best != ~0ull) break;
+                const Span sx = span_cells(tx, 2 * R, B.ntx), sy = span_cells(ty, 2 * R, B.nty);
+                visit_items(B, S, sx, sy, 1 << 30,
+                            [&](int e) {
+                                const int2 q = B.cell_q[e];
+                                atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
+                            },
+                            [](int) {});
+                if (span_full(sx, B.ntx) && span_full(sy, B.nty)) break;
+            }
+            const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
+            const double rq2 = (256.0 * rho) * (256.0 * rho);
+            const double px = tcx / 256.0, py = tcy / 256.0;
+            const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx);
+            const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), ly);
+            visit_items(
+                B, S, sx, sy, CAND_BATCH,
+                [&](int e) {
+                    const int2 q = B.cell_q[e];
+                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(e, q);
+                },
+                [&](int m) {
+                    // evaluate and empty the list when this batch could overflow it
+                    if (S.ncand + m * IMG_MAX > DV_CAND_CAP) {
+                        eval_owners();
+                        __syncthreads();
+                        if (t == 0) { S.ncand = 0; S.nchunks += 1; }
+                        __syncthreads();
+                    }
+                });
+        }
         eval_owners();
     }
 #pragma unroll
@@ -349,10 +399,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
     }
     __syncthreads();
 
-    // --- frame gaps and the neighbour rules.  A wave colours the inner-frame
-    // points its lanes need one at a time: the lanes share the candidates and
-    // reduce the exact (distance, label) minimum.  After a candidate-list
-    // overflow the asking lane uses the exact grid search instead.
+    // --- frame gaps and the neighbour rules.  The inner-frame points whose
+    // colour decides a second-neighbour link are collected, then coloured
+    // against the candidate list (or, after a candidate-list overflow, by the
+    // exact grid search).
     const bool in_lds = S.nchunks == 0;
     const int ncl = S.ncand;
     auto emit = [&](int a, int b) {
@@ -376,7 +426,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
         if (ckk == DV_EMPTY) continue;
         int f[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = S.own[c + FRY[k] * 34 + FRX[k]];
+        for (int k = 0; k < 8; ++k) f[k] = S.own[c + fry(k) * 34 + frx(k)];
         int gaps = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -393,45 +443,61 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
             if (dg != DV_EMPTY && dg != ckk && pa != pb && pa != tg) pend |= 1u << (4 * i + r);
         }
     }
-    for (;;) {
-        const unsigned long long busy = __ballot(pend != 0);
-        if (busy == 0) break;
-        const int src = __ffsll(busy) - 1;
-        const int bit = __shfl(pend ? __ffs(pend) - 1 : 0, src, 64);
-        const int i = bit >> 2, r = bit & 3;
-        const int qsx = src & 31, qsy = ((t >> 6) << 1) + (src >> 5) + 8 * i;
-        int m;
-        if (in_lds) {
-            const double qx = 256.0 * qsx + INX[r], qy = 256.0 * qsy + INY[r];
-            double bee = 1.0e300;
-            int bll = DV_EMPTY;
-            for (int k = lane; k < ncl; k += 64) {
-                const double e = fma(-2.0 * qx, (double)S.cx[k], fma(-2.0 * qy, (double)S.cy[k], S.ck[k]));
-                const int lab = S.lab[k];
-                if (e < bee || (e == bee && lab < bll)) { bee = e; bll = lab; }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double e2 = __shfl_xor(bee, o, 64);
-                const int l2 = __shfl_xor(bll, o, 64);
-                if (e2 < bee || (e2 == bee && l2 < bll)) { bee = e2; bll = l2; }
-            }
-            m = bll;
-        } else {
-            m = 0;
-            if (lane == src) {
-                int X = OX + 256 * qsx + INX[r], Y = OY + 256 * qsy + INY[r];
-                if (X < 0) X += MX;
-                if (Y < 0) Y += MY;
-                m = point_nearest(B, X, Y);
-            }
-            m = __shfl(m, src, 64);
+    // inner-frame queries: numbered by a block scan of the per-thread counts,
+    // written to LDS in chunks, each answered by one thread
+    {
+        const int cnt = __popc(pend);
+        int x = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        if (lane == src) {
-            pend &= ~(1u << bit);
-            const int c = (qsy + 1) * 34 + qsx + 1;
-            const int ckk = S.own[c];
-            const int dg = S.own[c + FRY[2 * r + 1] * 34 + FRX[2 * r + 1]];
-            if (m == dg || m == ckk) emit(min(ckk, dg), max(ckk, dg));
+        if (lane == 63) S.wsum[t >> 6] = x;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < DV_BLOCK / 64; ++w) {
+            if (w < (t >> 6)) before += S.wsum[w];
+            total += S.wsum[w];
+        }
+        before += x - cnt;
+        for (int c0 = 0; c0 < total; c0 += QCAP) {
+            // this thread's queries with numbers in [c0, c0 + QCAP)
+            unsigned rest = pend;
+            for (int j = before; rest; ++j) {
+                const int bit = __ffs(rest) - 1;
+                rest &= rest - 1;
+                if (j >= c0 && j < c0 + QCAP) {
+                    const int i = bit >> 2, r = bit & 3;
+                    S.q[j - c0] = (((ry + 8 * i) * 32 + cx) << 2) | r;
+                }
+            }
+            __syncthreads();
+            const int nq = min(QCAP, total - c0);
+            for (int j = t; j < nq; j += DV_BLOCK) {
+                const int code = S.q[j], r = code & 3, sxy = code >> 2;
+                const int qsx = sxy & 31, qsy = sxy >> 5;
+                int m;
+                if (in_lds) {
+                    const double qx = -2.0 * (256.0 * qsx + inx(r)), qy = -2.0 * (256.0 * qsy + iny(r));
+                    double bee = 1.0e300;
+                    m = DV_EMPTY;
+                    for (int k = 0; k < ncl; ++k) {
+                        const double e = fma(qx, (double)S.cx[k], fma(qy, (double)S.cy[k], S.ck[k]));
+                        const int lab = S.lab[k];
+                        if (e < bee || (e == bee && lab < m)) { bee = e; m = lab; }
+                    }
+                } else {
+                    int X = OX + 256 * qsx + inx(r), Y = OY + 256 * qsy + iny(r);
+                    if (X < 0) X += MX;
+                    if (Y < 0) Y += MY;
+                    m = point_nearest(B, X, Y);
+                }
+                const int c = (qsy + 1) * 34 + qsx + 1;
+                const int ckk = S.own[c];
+                const int dg = S.own[c + fry(2 * r + 1) * 34 + frx(2 * r + 1)];
+                if (m == dg || m == ckk) emit(min(ckk, dg), max(ckk, dg));
+            }
+            __syncthreads();
         }
     }
     __syncthreads();

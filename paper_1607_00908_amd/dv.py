@@ -30,8 +30,8 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
            "dv_status_str", "dv_last_error")
 
-STAGES = ("tile_ccl", "merge", "resolve", "rank_scan", "relabel", "finalize", "owner_edges",
-          "diff")
+STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "diff",
+          "place")
 
 
 class DVConfig(ctypes.Structure):
