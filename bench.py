@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # compulsory HBM bytes per site of each per-site stage (maps kept / flips only)
 STAGE_BYTES = {
     "tile_ccl": (4, 4),        # field read
-    "relabel": (8, 4),         # field read + label map write
+    "relabel": (4, 0),         # label map write
     "owner_edges": (4, 0),     # owner map write
 }
 STAGE_SOURCES = {
@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
     ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
     ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
+    ap.add_argument("--pipeline-depth", type=int, default=0,
+                    help="frames in flight on the device (0: the library default)")
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -207,13 +209,15 @@ def main():
     maps = not args.flips_only
     kmax = 32768 if N > (1 << 22) else 4096
     det = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
-                      keep_maps=maps)
+                      keep_maps=maps, pipeline_depth=args.pipeline_depth)
     F = ring.shape[0]
 
-    # the context's stream does all device work; pushes need no cross-stream wait
+    # the ring is complete on the device (synchronised above): frames are
+    # pushed as raw device pointers, no per-push stream bookkeeping
     torch.cuda.set_stream(det.stream)
+    ptrs = [ring[i].data_ptr() for i in range(F)]
     for i in range(args.warmup):
-        det.push(ring[i % F])
+        det.push(ptrs[i % F])
     det.sync()
     info = det.info()
     log(f"warmup done: K={info.n_components} E={info.n_edges} flips={info.n_flips}")
@@ -222,7 +226,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        det.push(ring[(args.warmup + i) % F])
+        det.push(ptrs[(args.warmup + i) % F])
     det.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -237,7 +241,7 @@ def main():
     # latency: push -> flips returned, host-synchronous
     lat = []
     for i in range(args.latency_frames):
-        f = ring[i % F]
+        f = ptrs[i % F]
         a = time.perf_counter()
         det.push(f)
         det.flips()
@@ -269,7 +273,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lx": lx, "ly": ly, "frames_in_ring": F,
                    "components": info.n_components, "edges": info.n_edges,
-                   "mode": "maps+flips" if maps else "flips-only", "parallelism": "single-gpu"},
+                   "mode": "maps+flips" if maps else "flips-only",
+                   "pipeline_depth": args.pipeline_depth or dv.DEFAULT_PIPELINE_DEPTH, "parallelism": "single-gpu"},
         "frames_per_s": round(args.steps / elapsed, 1),
         "hbm_frac_pipeline": round(msites * 1e6 * (12 if maps else 4) / (HBM_PEAK_GBS * 1e9), 5),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),

@@ -1,9 +1,17 @@
 // Host side of libdv: the C ABI declared in include/dv.h.
 //
-// A context owns every device buffer, sized once from the lattice and K_max,
-// and enqueues the whole per-frame procedure on one HIP stream without any
-// host synchronisation.  Synchronising calls copy the device frame header
-// (and the requested arrays) back through pinned host memory.
+// A context owns every device buffer, sized once from the lattice and K_max.
+// Frames go through a pipeline of `depth` slots: frame f uses slot f % depth
+// for everything up to its Delaunay couples (labelling, centres, colouring),
+// enqueued on that slot's stream, so consecutive frames overlap on the
+// device.  Its comparison with the last accepted frame (matching, diff,
+// commit) runs on one chain stream in frame order.  Events order the work:
+//   slot stream  waits for the caller's stream at the push (the field is
+//                ready) and for the chain of the slot's previous frame (its
+//                buffers are free again);
+//   chain        waits for the slot's stage of the frame.
+// No host synchronisation happens in a push.  Synchronising calls wait for the
+// chain and copy the sequence header (and the requested arrays) back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,14 +23,26 @@
 #include "dv.h"
 #include "dv_internal.h"
 
+#define DV_MAX_DEPTH 4
+
+struct Slot {
+    Bufs B;                  // slot buffers + the shared chain buffers
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_s1 = nullptr, ev_done = nullptr;
+};
+
 struct dv_ctx {
     dv_config cfg;
     int device;
-    hipStream_t stream;
+    hipStream_t stream;      // the caller's (or owned) stream: input ordering
     bool own_stream;
-    Bufs B;
+    hipStream_t chain;       // comparison chain
+    int depth;
+    Slot slot[DV_MAX_DEPTH];
+    int64_t pushes;          // frames pushed so far
+    int last;                // slot of the most recent push
     std::vector<void *> allocs;
-    DevState *h_state;       // pinned mirror of the device header
+    SeqState *h_state;       // pinned mirror of the sequence header
     int32_t *d_edge_scratch; // [2 * K_max] for the couple-list getter
     int32_t *d_edge_ab;      // [K_max * max_degree] pairs
     int32_t *d_edge_total;
@@ -59,15 +79,37 @@ void drop_events(dv_ctx *c) {
     c->prof = Prof();
 }
 
+// wait for every stream of the context
+bool drain(dv_ctx *c) {
+    bool ok = true;
+    for (int k = 0; k < c->depth; ++k)
+        if (c->slot[k].stream) ok = hipStreamSynchronize(c->slot[k].stream) == hipSuccess && ok;
+    if (c->chain) ok = hipStreamSynchronize(c->chain) == hipSuccess && ok;
+    if (c->stream) ok = hipStreamSynchronize(c->stream) == hipSuccess && ok;
+    return ok;
+}
+
 void release(dv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)drain(c);
     drop_events(c);
+    for (int k = 0; k < DV_MAX_DEPTH; ++k) {
+        Slot &S = c->slot[k];
+        if (S.ev_in) (void)hipEventDestroy(S.ev_in);
+        if (S.ev_s1) (void)hipEventDestroy(S.ev_s1);
+        if (S.ev_done) (void)hipEventDestroy(S.ev_done);
+        if (S.stream) (void)hipStreamDestroy(S.stream);
+        S = Slot();
+    }
+    if (c->chain) (void)hipStreamDestroy(c->chain);
+    c->chain = nullptr;
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_state) (void)hipHostFree(c->h_state);
+    c->h_state = nullptr;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->stream = nullptr;
 }
 
 dv_status check_cfg(const dv_config *cfg) {
@@ -87,13 +129,16 @@ dv_status check_cfg(const dv_config *cfg) {
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
     if (cfg->flags & ~DV_KEEP_MAPS) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
+    if (cfg->pipeline_depth < 0 || cfg->pipeline_depth > DV_MAX_DEPTH)
+        return fail(nullptr, DV_ERR_ARG, "pipeline_depth must be 0 or in [1, 4]");
     return DV_OK;
 }
 
 dv_status sync_state(dv_ctx *c) {
-    if (hipMemcpyAsync(c->h_state, c->B.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+    if (!drain(c) ||
+        hipMemcpyAsync(c->h_state, c->slot[0].B.st, sizeof(SeqState), hipMemcpyDeviceToHost,
+                       c->chain) != hipSuccess ||
+        hipStreamSynchronize(c->chain) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
     return DV_OK;
 }
@@ -129,7 +174,13 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     if (c->cfg.max_degree == 0) c->cfg.max_degree = 48;
     // row slots are read four at a time
     c->cfg.max_degree = (c->cfg.max_degree + 3) & ~3;
+    if (c->cfg.pipeline_depth == 0) c->cfg.pipeline_depth = 3;
+    c->depth = c->cfg.pipeline_depth;
     c->device = c->cfg.device;
+    c->chain = nullptr;
+    c->pushes = 0;
+    c->last = 0;
+    c->h_state = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -144,7 +195,22 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
         }
         c->own_stream = true;
     }
-    Bufs &B = c->B;
+    bool ok = hipStreamCreateWithFlags(&c->chain, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; ok && k < c->depth; ++k) {
+        Slot &S = c->slot[k];
+        ok = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&S.ev_s1, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&S.ev_done, hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        release(c);
+        delete c;
+        return fail(nullptr, DV_ERR_DEVICE, "stream or event creation failed");
+    }
+
+    // shared part of the buffer table
+    Bufs B;
     std::memset(&B, 0, sizeof(B));
     B.lx = c->cfg.lx;
     B.ly = c->cfg.ly;
@@ -159,44 +225,54 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
     const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
     const size_t segs = (size_t)B.ly * B.ntx;
-    bool ok = dalloc(c, &B.parent, N) && dalloc(c, &B.lab16, N) &&
-              dalloc(c, &B.pieces, tiles * DV_TILE_SITES) &&
-              dalloc(c, &B.npieces, tiles) && dalloc(c, &B.seg_mask, segs) &&
-              dalloc(c, &B.seg_prefix, segs) && dalloc(c, &B.band_sum, (size_t)B.nty) &&
-              dalloc(c, &B.acc_x, K) && dalloc(c, &B.acc_y, K) && dalloc(c, &B.acc_n, K) &&
-              dalloc(c, &B.acc_amb, K) && dalloc(c, &B.acc_root, K) &&
-              dalloc(c, &B.cell_count, tiles) && dalloc(c, &B.cell_start, tiles + 1) &&
-              dalloc(c, &B.cell_items, K) && dalloc(c, &B.cell_q, K) &&
-              dalloc(c, &B.comp_cell, K) && dalloc(c, &B.comp_slot, K) && dalloc(c, &B.phi, K) &&
-              dalloc(c, &B.cnt, K) && dalloc(c, &B.inv, K) && dalloc(c, &B.trigger, K) &&
-              dalloc(c, &B.nb, K) && dalloc(c, &B.na, K) && dalloc(c, &B.ob, K) &&
-              dalloc(c, &B.oa, K) && dalloc(c, &B.flips, K * B.maxdeg * 6) &&
-              dalloc(c, &B.stage, K * B.maxdeg * 12) &&
-              dalloc(c, &B.st, 1) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
-              dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
-    if (ok && B.keep_maps) ok = dalloc(c, &B.labels, N) && dalloc(c, &B.owner, N);
-    for (int b = 0; ok && b < 2; ++b) {
-        CompBuf &C = B.comp[b];
-        ok = dalloc(c, &C.qx, K) && dalloc(c, &C.qy, K) && dalloc(c, &C.fx, K) &&
-             dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
-             dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
+    auto comp_alloc = [&](CompBuf &C) {
+        return dalloc(c, &C.qx, K) && dalloc(c, &C.qy, K) && dalloc(c, &C.fx, K) &&
+               dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
+               dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
+    };
+    ok = dalloc(c, &B.phi, K) && dalloc(c, &B.trigger, K) && dalloc(c, &B.nb, K) &&
+         dalloc(c, &B.na, K) && dalloc(c, &B.ob, K) && dalloc(c, &B.oa, K) &&
+         dalloc(c, &B.flips, K * B.maxdeg * 6) && dalloc(c, &B.stage, K * B.maxdeg * 12) &&
+         dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
+         dalloc(c, &c->d_edge_scratch, 2 * K) && dalloc(c, &c->d_edge_ab, K * B.maxdeg) &&
+         dalloc(c, &c->d_edge_total, 1);
+    // per-slot buffers
+    for (int k = 0; ok && k < c->depth; ++k) {
+        Bufs &b = c->slot[k].B;
+        b = B;
+        ok = dalloc(c, &b.parent, N) && dalloc(c, &b.lab16, N) &&
+             dalloc(c, &b.pieces, tiles * DV_TILE_SITES) && dalloc(c, &b.npieces, tiles) &&
+             dalloc(c, &b.seg_mask, segs) && dalloc(c, &b.seg_prefix, segs) &&
+             dalloc(c, &b.band_sum, (size_t)B.nty) && dalloc(c, &b.acc_x, K) &&
+             dalloc(c, &b.acc_y, K) && dalloc(c, &b.acc_n, K) && dalloc(c, &b.acc_amb, K) &&
+             dalloc(c, &b.acc_root, K) && dalloc(c, &b.cell_count, tiles) &&
+             dalloc(c, &b.cell_start, tiles + 1) && dalloc(c, &b.cell_items, K) &&
+             dalloc(c, &b.cell_q, K) && dalloc(c, &b.comp_cell, K) && dalloc(c, &b.comp_slot, K) &&
+             dalloc(c, &b.cnt, K) && dalloc(c, &b.inv, K) && dalloc(c, &b.fs, 1) &&
+             comp_alloc(b.cur);
+        if (ok && B.keep_maps) ok = dalloc(c, &b.labels, N) && dalloc(c, &b.owner, N);
     }
-    if (ok && hipHostMalloc((void **)&c->h_state, sizeof(DevState)) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void **)&c->h_state, sizeof(SeqState)) != hipSuccess) ok = false;
     if (!ok) {
         release(c);
         delete c;
         return fail(nullptr, DV_ERR_NOMEM, "device allocation failed");
     }
-    // initial contents: zero accumulators and header, empty rows
-    bool z = hipMemsetAsync(B.acc_x, 0, K * sizeof(long long), c->stream) == hipSuccess &&
-             hipMemsetAsync(B.acc_y, 0, K * sizeof(long long), c->stream) == hipSuccess &&
-             hipMemsetAsync(B.acc_n, 0, K * sizeof(int), c->stream) == hipSuccess &&
-             hipMemsetAsync(B.acc_amb, 0, K * sizeof(int), c->stream) == hipSuccess &&
-             hipMemsetAsync(B.st, 0, sizeof(DevState), c->stream) == hipSuccess;
+    // initial contents: zero accumulators and headers, empty rows
+    hipStream_t s0 = c->chain;
+    bool z = hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
     for (int b = 0; z && b < 2; ++b)
-        z = hipMemsetD32Async((hipDeviceptr_t)B.comp[b].adj, DV_EMPTY, K * B.maxdeg, c->stream) ==
-            hipSuccess;
-    if (!z || hipStreamSynchronize(c->stream) != hipSuccess) {
+        z = hipMemsetD32Async((hipDeviceptr_t)B.past[b].adj, DV_EMPTY, K * B.maxdeg, s0) == hipSuccess;
+    for (int k = 0; z && k < c->depth; ++k) {
+        const Bufs &b = c->slot[k].B;
+        z = hipMemsetAsync(b.acc_x, 0, K * sizeof(long long), s0) == hipSuccess &&
+            hipMemsetAsync(b.acc_y, 0, K * sizeof(long long), s0) == hipSuccess &&
+            hipMemsetAsync(b.acc_n, 0, K * sizeof(int), s0) == hipSuccess &&
+            hipMemsetAsync(b.acc_amb, 0, K * sizeof(int), s0) == hipSuccess &&
+            hipMemsetAsync(b.fs, 0, sizeof(FrameState), s0) == hipSuccess &&
+            hipMemsetD32Async((hipDeviceptr_t)b.cur.adj, DV_EMPTY, K * B.maxdeg, s0) == hipSuccess;
+    }
+    if (!z || hipStreamSynchronize(s0) != hipSuccess) {
         release(c);
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "device initialisation failed");
@@ -210,12 +286,25 @@ dv_status dv_push_frame(dv_ctx *c, const float *field_device) {
     if (!c) return DV_ERR_ARG;
     if (!field_device) return fail(c, DV_ERR_ARG, "field is NULL");
     (void)hipSetDevice(c->device);
-    c->B.field = field_device;
-    launch_label(c->B, c->stream, c->prof);
-    launch_voronoi(c->B, c->stream, c->prof);
-    launch_diff(c->B, c->stream, c->prof);
+    const int k = (int)(c->pushes % c->depth);
+    Slot &S = c->slot[k];
+    S.B.field = field_device;
+    bool ok = hipEventRecord(S.ev_in, c->stream) == hipSuccess &&
+              hipStreamWaitEvent(S.stream, S.ev_in, 0) == hipSuccess;
+    // the slot's previous frame must have left the chain (no-op before its first use)
+    if (ok && c->pushes >= c->depth) ok = hipStreamWaitEvent(S.stream, S.ev_done, 0) == hipSuccess;
+    if (!ok) return fail(c, DV_ERR_DEVICE, "event ordering failed");
+    launch_label(S.B, S.stream, c->prof);
+    launch_voronoi(S.B, S.stream, c->prof);
+    ok = hipEventRecord(S.ev_s1, S.stream) == hipSuccess &&
+         hipStreamWaitEvent(c->chain, S.ev_s1, 0) == hipSuccess;
+    if (!ok) return fail(c, DV_ERR_DEVICE, "event ordering failed");
+    launch_chain(S.B, c->chain, c->prof);
+    if (hipEventRecord(S.ev_done, c->chain) != hipSuccess) return fail(c, DV_ERR_DEVICE, "event record failed");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    c->last = k;
+    c->pushes += 1;
     c->pushed = true;
     return DV_OK;
 }
@@ -223,7 +312,7 @@ dv_status dv_push_frame(dv_ctx *c, const float *field_device) {
 dv_status dv_sync(dv_ctx *c) {
     if (!c) return DV_ERR_ARG;
     (void)hipSetDevice(c->device);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
     return DV_OK;
 }
 
@@ -233,7 +322,7 @@ dv_status dv_get_info(dv_ctx *c, dv_frame_info *info) {
     (void)hipSetDevice(c->device);
     dv_status s = sync_state(c);
     if (s != DV_OK) return s;
-    const DevState &h = *c->h_state;
+    const SeqState &h = *c->h_state;
     dv_frame_info fi;
     std::memset(&fi, 0, sizeof(fi));
     fi.frame = h.frame;
@@ -259,7 +348,7 @@ dv_status dv_get_flips(dv_ctx *c, dv_flip *host_out, int32_t capacity, int32_t *
     if (n > capacity) return fail(c, DV_ERR_CAPACITY, "flip buffer too small");
     if (n > 0) {
         if (!host_out) return fail(c, DV_ERR_ARG, "host_out is NULL");
-        if (hipMemcpy(host_out, c->B.flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(host_out, c->slot[0].B.flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, DV_ERR_DEVICE, "copy failed");
     }
     return DV_OK;
@@ -267,22 +356,24 @@ dv_status dv_get_flips(dv_ctx *c, dv_flip *host_out, int32_t capacity, int32_t *
 
 dv_status dv_get_labels(dv_ctx *c, int32_t *host_out) {
     if (!c || !host_out) return DV_ERR_ARG;
-    if (!c->B.keep_maps) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
+    if (!(c->cfg.flags & DV_KEEP_MAPS)) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const size_t N = (size_t)c->B.lx * c->B.ly;
-    if (hipMemcpy(host_out, c->B.labels, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    const Bufs &B = c->slot[c->last].B;
+    const size_t N = (size_t)B.lx * B.ly;
+    if (hipMemcpy(host_out, B.labels, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
     return DV_OK;
 }
 
 dv_status dv_get_owner(dv_ctx *c, int32_t *host_out) {
     if (!c || !host_out) return DV_ERR_ARG;
-    if (!c->B.keep_maps) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
+    if (!(c->cfg.flags & DV_KEEP_MAPS)) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const size_t N = (size_t)c->B.lx * c->B.ly;
-    if (hipMemcpy(host_out, c->B.owner, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    const Bufs &B = c->slot[c->last].B;
+    const size_t N = (size_t)B.lx * B.ly;
+    if (hipMemcpy(host_out, B.owner, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
     return DV_OK;
 }
@@ -292,12 +383,12 @@ dv_status dv_get_components(dv_ctx *c, int32_t *q8_xy, double *xy, int32_t *size
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const DevState &h = *c->h_state;
+    const SeqState &h = *c->h_state;
     const int K = h.K[h.sel];
     *n_out = K;
     if (K > capacity) return fail(c, DV_ERR_CAPACITY, "component buffer too small");
     if (K == 0) return DV_OK;
-    const CompBuf &C = c->B.comp[h.sel];
+    const CompBuf &C = c->slot[0].B.past[h.sel];
     std::vector<int32_t> qx(K), qy(K);
     std::vector<double> fx(K), fy(K);
     bool ok = hipMemcpy(qx.data(), C.qx, K * 4, hipMemcpyDeviceToHost) == hipSuccess &&
@@ -317,10 +408,10 @@ dv_status dv_get_edges(dv_ctx *c, int32_t *ab, int32_t capacity, int32_t *n_out)
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    launch_edge_list(c->B, c->d_edge_ab, c->d_edge_total, c->d_edge_scratch, c->stream);
+    launch_edge_list(c->slot[c->last].B, c->d_edge_ab, c->d_edge_total, c->d_edge_scratch, c->chain);
     int32_t E = 0;
-    if (hipMemcpyAsync(&E, c->d_edge_total, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+    if (hipMemcpyAsync(&E, c->d_edge_total, 4, hipMemcpyDeviceToHost, c->chain) != hipSuccess ||
+        hipStreamSynchronize(c->chain) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "edge list failed");
     *n_out = E;
     if (E > capacity) return fail(c, DV_ERR_CAPACITY, "edge buffer too small");
@@ -342,9 +433,9 @@ dv_status dv_get_matching(dv_ctx *c, int32_t *phi, int32_t capacity, int32_t *n_
     if (KP == 0) return DV_OK;
     if (!phi) return fail(c, DV_ERR_ARG, "phi is NULL");
     // Phi with dropped past points as -1, written to scratch on the device
-    launch_phi_out(c->B, c->d_edge_ab, c->stream);
-    if (hipMemcpyAsync(phi, c->d_edge_ab, (size_t)KP * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
+    launch_phi_out(c->slot[c->last].B, c->d_edge_ab, c->chain);
+    if (hipMemcpyAsync(phi, c->d_edge_ab, (size_t)KP * 4, hipMemcpyDeviceToHost, c->chain) != hipSuccess ||
+        hipStreamSynchronize(c->chain) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
     return DV_OK;
 }
@@ -356,7 +447,7 @@ void dv_destroy(dv_ctx *c) {
 }
 
 static const char *const STAGE_NAMES[ST_COUNT] = {
-    "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "diff", "place"};
+    "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "match", "diff", "place"};
 
 const char *dv_stage_name(int32_t stage) {
     return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;
@@ -367,7 +458,7 @@ dv_status dv_set_profile(dv_ctx *c, int32_t stage, int32_t capacity) {
     if (stage < -1 || stage >= ST_COUNT || (stage >= 0 && (capacity < 1 || capacity > (1 << 20))))
         return fail(c, DV_ERR_ARG, "bad stage or capacity");
     (void)hipSetDevice(c->device);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
     drop_events(c);
     if (stage < 0) return DV_OK;
     c->prof.ev = new hipEvent_t[2 * (size_t)capacity];
@@ -387,7 +478,7 @@ dv_status dv_set_profile(dv_ctx *c, int32_t stage, int32_t capacity) {
 dv_status dv_get_profile(dv_ctx *c, double *total_ms, int32_t *launches) {
     if (!c || !total_ms || !launches) return DV_ERR_ARG;
     (void)hipSetDevice(c->device);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
     double tot = 0.0;
     for (int i = 0; i < c->prof.used; ++i) {
         float ms = 0.f;

@@ -15,28 +15,37 @@
 #define DV_E_KMAX 1u               // more components than K_max
 #define DV_E_DEGREE 2u             // a Delaunay row overflowed max_degree
 
-// Frame header kept in device memory.  Two component / adjacency buffers
-// alternate: buffer `sel` holds the last accepted frame (the past), buffer
-// 1 - sel receives the frame being processed.
-struct DevState {
+// Per-frame header, one per pipeline slot (device memory).
+struct FrameState {
+    int32_t K_now;         // components found in the frame (raw, may exceed K_max)
+    uint32_t err;          // DV_E_* bits of the frame
+    int32_t rows_dirty;    // rows of the slot's adjacency that may hold entries
+    int32_t n_amb;         // components crossing their own antipodal line
+    int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
+    int32_t pad[3];
+};
+
+// Sequence header (device memory), touched only by the comparison chain.  Two
+// past buffers alternate: buffer `sel` holds the last accepted frame; the
+// comparison of a frame copies its components into buffer 1 - sel, which
+// becomes the past when the frame is accepted.
+struct SeqState {
     int32_t sel;
     int32_t past_valid;
-    int32_t K[2];          // components held by each buffer
-    int32_t E[2];          // undirected couples held by each buffer
-    int32_t rows_dirty[2]; // rows of each buffer that may hold entries
-    int32_t K_now;         // components found in the current frame (raw)
-    uint32_t err;          // DV_E_* bits of the current frame
-    int32_t E2_now;        // sum of row lengths of the current frame (2E)
+    int32_t K[2];          // components held by each past buffer
+    int32_t E[2];          // undirected couples held by each past buffer
+    int32_t E2_acc;        // sum of now row lengths (2E), zeroed by the commit
+    int32_t excl_acc;      // now points dropped, zeroed by the commit
+    // outputs of the most recent frame
+    int32_t status;        // 0 accepted, else DV_ERR_CAPACITY
+    int32_t K_now;
     int32_t n_flips;
     int32_t n_break;
     int32_t n_excl_past;
     int32_t n_excl_now;
     int32_t n_amb;
     int32_t global_trigger;
-    int32_t status;        // 0 accepted, else DV_ERR_CAPACITY of the last push
-    int32_t K_past_cmp;    // K of the past frame used by the current comparison
-    int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
-    int32_t done_spare;
+    int32_t K_past_cmp;    // K of the past frame used by the comparison
     int32_t pad;
     int64_t frame;         // accepted frames
 };
@@ -51,7 +60,9 @@ struct CompBuf {
     int32_t *adj;          // rows [K_max][max_degree]: unordered sets, DV_EMPTY padded
 };
 
-// Everything a kernel may touch.  Passed by value.
+// Everything a kernel may touch: the buffers of one pipeline slot (one frame
+// in flight) and those of the comparison chain shared by all slots.  Passed
+// by value.
 struct Bufs {
     int32_t lx, ly, ntx, nty;
     float thr;
@@ -78,23 +89,25 @@ struct Bufs {
     int32_t *cell_items;   // [K_max] labels ordered by cell
     int2 *cell_q;          // [K_max] their Q.8 centres
     int32_t *comp_cell, *comp_slot;  // [K_max]
-    // matching / diff
-    int32_t *phi;          // [K_max] past -> now
     int32_t *cnt;          // [K_max] preimages of each now label
     int32_t *inv;          // [K_max] now -> past (valid when cnt == 1)
+    CompBuf cur;           // components and rows of the frame
+    FrameState *fs;
+    // comparison chain (shared by the slots)
+    int32_t *phi;          // [K_max] past -> now
     int32_t *trigger;      // [K_max] local trigger per kept past label
     int32_t *nb, *na;      // [K_max] breaking / arising count per now row
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
     int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
     int32_t *flips;        // [K_max * max_degree][6]
-    CompBuf comp[2];
-    DevState *st;
+    CompBuf past[2];
+    SeqState *st;
 };
 
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
-    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_DIFF,
-    ST_PLACE, ST_COUNT
+    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_MATCH,
+    ST_DIFF, ST_PLACE, ST_COUNT
 };
 
 // Optional event bracketing of one stage (measurement only).
@@ -117,8 +130,8 @@ struct Prof {
 void launch_label(const Bufs &B, hipStream_t s, Prof &P);
 // launchers (k_voronoi.hip)
 void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P);
-// launchers (k_diff.hip)
-void launch_diff(const Bufs &B, hipStream_t s, Prof &P);
+// launchers (k_diff.hip): the comparison chain of a frame
+void launch_chain(const Bufs &B, hipStream_t s, Prof &P);
 // inspection helpers (k_diff.hip)
 void launch_phi_out(const Bufs &B, int32_t *d_out, hipStream_t s);
 void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,

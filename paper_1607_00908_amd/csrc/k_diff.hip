@@ -1,36 +1,79 @@
-// Translation, trigger and flips (Sec. 3.2.3 and 3.2.4), in one launch.
+// Comparison chain of a frame with the last accepted one (Sec. 3.2.3 and
+// 3.2.4).  It runs in frame order; everything before it (labelling, centres,
+// colouring) only touches the frame's own pipeline slot, so consecutive
+// frames overlap up to here.
 //
-// One wave per now label n that has exactly one preimage p: lane j holds slot
-// j of the now row of n and slot j of the past row of p translated through
-// Phi (kept entries only).  Rows are sets, so membership is tested with wave
-// shuffles.  A couple of T(p) missing from R(n) is breaking, one of R(n)
-// missing from T(p) is arising; each is reported once, from the row of its
-// smaller now label, and staged in increasing order of the other end.  The
-// local trigger of p is set when the two rows differ.
-//
-// k_place (one block) then scans the per-row counts, places the staged flips
-// in canonical order (breaking first, then arising, each by (a, b)) and
-// commits the frame: the now buffer becomes the past when the frame was
-// accepted.  Kept past and now points correspond one to one, so the number of
-// dropped past points is K_past - (K_now - dropped now points).
+//   k_match   Phi(p) = nearest now centre of every past centre p, one wave
+//             per point through the now bucket grid, exact, ties to the
+//             lowest label; preimage counts of the now points.
+//   k_diff    one wave per now label n: copies the components and row of n
+//             into the spare past buffer (the past of the next frame once
+//             this one is accepted); when n has exactly one preimage p, lane
+//             j holds slot j of the now row of n and slot j of the past row of
+//             p translated through Phi (kept entries only).  Rows are sets, so
+//             membership is tested with wave shuffles.  A couple of T(p)
+//             missing from R(n) is breaking, one of R(n) missing from T(p) is
+//             arising; each is reported once, from the row of its smaller now
+//             label, and staged in increasing order of the other end.  The
+//             local trigger of p is set when the two rows differ.
+//   k_place   (one block) scans the per-row counts, places the staged flips in
+//             canonical order (breaking first, then arising, each by (a, b))
+//             and commits: the spare past buffer becomes the past when the
+//             frame was accepted.  Kept past and now points correspond one to
+//             one, so the number of dropped past points is
+//             K_past - (K_now - dropped now points).
 #include "dv_device.h"
 
 namespace {
 
+__global__ __launch_bounds__(256) void k_match(Bufs B) {
+    const SeqState *st = B.st;
+    const FrameState *fs = B.fs;
+    if (fs->err || !st->past_valid) return;
+    const int past = st->sel;
+    const int KP = st->K[past], KN = fs->K_now;
+    const CompBuf P = B.past[past];
+    const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    for (int p = blockIdx.x * nw + (threadIdx.x >> 6); p < KP; p += gridDim.x * nw) {
+        int n = -1;
+        if (KN > 0) n = wave_nearest(B, P.qx[p], P.qy[p]);
+        if (lane == 0) {
+            B.phi[p] = n;
+            if (n >= 0) {
+                atomicAdd(&B.cnt[n], 1);
+                B.inv[n] = p;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_diff(Bufs B) {
     __shared__ int s_red[2][4];
-    DevState *st = B.st;
-    if (st->err) return;
+    SeqState *st = B.st;
+    if (B.fs->err) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int KN = st->K_now;
-    const int past = st->sel, now = 1 - past;
+    const int KN = B.fs->K_now;
+    const int past = st->sel;
     const bool pv = st->past_valid != 0;
-    const CompBuf P = B.comp[past], N = B.comp[now];
+    const CompBuf P = B.past[past], N = B.cur, Q = B.past[1 - past];
     const int D = B.maxdeg;
     int e2 = 0, exn = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
     for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
         const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
+        // copy of component n for the next comparison
+        if (lane < D) Q.adj[(size_t)n * D + lane] = m;
+        switch (lane) {
+            case 0: Q.qx[n] = N.qx[n]; break;
+            case 1: Q.qy[n] = N.qy[n]; break;
+            case 2: Q.fx[n] = N.fx[n]; break;
+            case 3: Q.fy[n] = N.fy[n]; break;
+            case 4: Q.n[n] = N.n[n]; break;
+            case 5: Q.root[n] = N.root[n]; break;
+            case 6: Q.amb[n] = N.amb[n]; break;
+            default: break;
+        }
         const int cn = B.cnt[n];
         const int p = B.inv[n];
         const int dR = __popcll(__ballot(m != DV_EMPTY));
@@ -93,25 +136,32 @@ __global__ __launch_bounds__(256) void k_diff(Bufs B) {
             a += s_red[0][w];
             b += s_red[1][w];
         }
-        if (a) atomicAdd(&st->E2_now, a);
-        if (b) atomicAdd(&st->n_excl_now, b);
+        if (a) atomicAdd(&st->E2_acc, a);
+        if (b) atomicAdd(&st->excl_acc, b);
     }
 }
 
 __global__ __launch_bounds__(1024) void k_place(Bufs B) {
     __shared__ int wsum[16];
-    DevState *st = B.st;
+    SeqState *st = B.st;
+    const FrameState *fs = B.fs;
     const int t = threadIdx.x;
-    if (st->err) {
+    if (fs->err) {
         if (t == 0) {
-            st->status = 2;   // DV_ERR_CAPACITY
+            st->status = 2;   // DV_ERR_CAPACITY; the past is kept
+            st->K_now = fs->K_now;
+            st->n_amb = fs->n_amb;
             st->n_flips = 0;
             st->n_break = 0;
+            st->n_excl_past = 0;
+            st->n_excl_now = 0;
             st->global_trigger = 0;
+            st->E2_acc = 0;
+            st->excl_acc = 0;
         }
         return;
     }
-    const int KN = st->K_now;
+    const int KN = fs->K_now;
     const int past = st->sel, now = 1 - past;
     const bool pv = st->past_valid != 0;
     const int D = B.maxdeg;
@@ -131,13 +181,19 @@ __global__ __launch_bounds__(1024) void k_place(Bufs B) {
     __syncthreads();
     if (t == 0) {
         const int KP = pv ? st->K[past] : 0;
-        st->n_excl_past = pv ? KP - (KN - st->n_excl_now) : 0;
+        const int excl = st->excl_acc;
+        st->K_now = KN;
+        st->n_amb = fs->n_amb;
+        st->n_excl_now = excl;
+        st->n_excl_past = pv ? KP - (KN - excl) : 0;
         st->n_break = nbk;
         st->n_flips = nbk + nar;
         st->global_trigger = (nbk + nar) > 0 ? 1 : 0;
         st->K_past_cmp = KP;
         st->K[now] = KN;
-        st->E[now] = st->E2_now / 2;
+        st->E[now] = st->E2_acc / 2;
+        st->E2_acc = 0;
+        st->excl_acc = 0;
         st->sel = now;
         st->past_valid = 1;
         st->frame += 1;
@@ -147,7 +203,7 @@ __global__ __launch_bounds__(1024) void k_place(Bufs B) {
 
 // Phi of the last comparison with dropped past points as -1 (inspection).
 __global__ __launch_bounds__(256) void k_phi_out(Bufs B, int *out) {
-    DevState *st = B.st;
+    const SeqState *st = B.st;
     const int KP = st->K_past_cmp;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < KP; p += gridDim.x * blockDim.x) {
         const int n = B.phi[p];
@@ -157,10 +213,10 @@ __global__ __launch_bounds__(256) void k_phi_out(Bufs B, int *out) {
 
 // ---- inspection: sorted couple list (a < b) of the current buffer ----------
 __global__ __launch_bounds__(256) void k_edge_count(Bufs B, int *cntv) {
-    DevState *st = B.st;
+    const SeqState *st = B.st;
     const int cur = st->sel;
     const int K = st->K[cur];
-    const CompBuf C = B.comp[cur];
+    const CompBuf C = B.past[cur];
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < K; a += gridDim.x * blockDim.x) {
         const int *row = C.adj + (size_t)a * B.maxdeg;
         int c = 0;
@@ -178,10 +234,10 @@ __global__ __launch_bounds__(1024) void k_edge_scan(Bufs B, const int *cntv, int
 
 // entries above a, written in increasing order (rows are unordered sets)
 __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int *ab) {
-    DevState *st = B.st;
+    const SeqState *st = B.st;
     const int cur = st->sel;
     const int K = st->K[cur];
-    const CompBuf C = B.comp[cur];
+    const CompBuf C = B.past[cur];
     for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < K; a += gridDim.x * blockDim.x) {
         const int *row = C.adj + (size_t)a * B.maxdeg;
         const int o = offv[a];
@@ -199,8 +255,11 @@ __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int
 
 }  // namespace
 
-void launch_diff(const Bufs &B, hipStream_t s, Prof &P) {
+void launch_chain(const Bufs &B, hipStream_t s, Prof &P) {
     const int grid = (int)std::min<long long>((B.kmax + 3) / 4, 2048);
+    P.begin(ST_MATCH, s);
+    hipLaunchKernelGGL(k_match, dim3(grid), dim3(256), 0, s, B);
+    P.end(ST_MATCH, s);
     P.begin(ST_DIFF, s);
     hipLaunchKernelGGL(k_diff, dim3(grid), dim3(256), 0, s, B);
     P.end(ST_DIFF, s);

@@ -209,30 +209,23 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x;
-    DevState *st = B.st;
-    const int now = 1 - st->sel;
+    FrameState *fs = B.fs;
 
     // per-frame resets spread over the grid
     if (tile == 0 && t == 0) {
-        st->K_now = 0;
-        st->err = 0;
-        st->E2_now = 0;
-        st->n_flips = 0;
-        st->n_break = 0;
-        st->n_excl_past = 0;
-        st->n_excl_now = 0;
-        st->n_amb = 0;
-        st->global_trigger = 0;
+        fs->K_now = 0;
+        fs->err = 0;
+        fs->n_amb = 0;
     }
     if (t == 0) {
         B.cell_count[tile] = 0;
         npc = 0;
     }
     if (t < th) B.seg_mask[(size_t)(y0 + t) * B.ntx + tx] = 0u;
-    {   // empty the rows of the buffer this frame will fill
-        const size_t total = (size_t)st->rows_dirty[now] * B.maxdeg;
+    {   // empty the rows this frame will fill
+        const size_t total = (size_t)fs->rows_dirty * B.maxdeg;
         const size_t stride = (size_t)gridDim.x * gridDim.y * DV_BLOCK;
-        int *adj = B.comp[now].adj;
+        int *adj = B.cur.adj;
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
@@ -392,42 +385,39 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
     __shared__ int prank[DV_TILE_SITES];
     __shared__ int prx[DV_TILE_SITES], pry[DV_TILE_SITES];
     __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
-    __shared__ uint8_t in34[34 * 34];
     __shared__ int boff[RL_BANDS];
     __shared__ int wsum[16];
-    DevState *st = B.st;
+    FrameState *fs = B.fs;
     const int tx = blockIdx.x, ty = blockIdx.y;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
 
-    // tile-local roots of the tile and inside flags of its one-site ring
-    // (periodic), as written by k_tile_ccl
-    for (int w = t; w < (tw + 2) * (th + 2); w += DV_BLOCK) {
-        const int wx = w % (tw + 2) - 1, wy = w / (tw + 2) - 1;
-        int gx = x0 + wx, gy = y0 + wy;
-        gx = gx < 0 ? gx + lx : (gx >= lx ? gx - lx : gx);
-        gy = gy < 0 ? gy + ly : (gy >= ly ? gy - ly : gy);
-        const uint16_t v = B.lab16[(size_t)gy * lx + gx];
-        in34[(wy + 1) * 34 + wx + 1] = v != 0xffff ? 1 : 0;
-        if (wx >= 0 && wx < tw && wy >= 0 && wy < th) L[wy * 32 + wx] = v != 0xffff ? (int)v : -1;
+    // tile-local roots of the tile, as written by k_tile_ccl
+    const int cx = t & 31, ry = t >> 5;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i;
+        int v = -1;
+        if (cx < tw && y < th) {
+            const uint16_t u = B.lab16[(size_t)(y0 + y) * lx + x0 + cx];
+            v = u != 0xffff ? (int)u : -1;
+        }
+        L[y * 32 + cx] = v;
     }
-    for (int s = t; s < DV_TILE_SITES; s += DV_BLOCK)
-        if ((s & 31) >= tw || (s >> 5) >= th) L[s] = -1;
     // roots in the bands before each band (exclusive prefix of band totals);
     // the first block publishes K and the capacity check
     // (ly <= 65536, so there are at most RL_BANDS bands)
     const int K = block_exclusive_scan(B.band_sum, boff, B.nty, wsum);
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
-        st->K_now = K;
-        if (K > B.kmax) st->err |= DV_E_KMAX;
-        st->rows_dirty[1 - st->sel] = min(K, B.kmax);
+        fs->K_now = K;
+        if (K > B.kmax) atomicOr(&fs->err, DV_E_KMAX);
+        fs->rows_dirty = min(K, B.kmax);
     }
     __syncthreads();
 
     // each piece root (a site that is its own tile-local root) looks up the
     // component root and its canonical rank
-    const int cx = t & 31, ry = t >> 5;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, r = y * 32 + cx;
@@ -463,16 +453,22 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
         atomicAdd(&psy[r], dy);
         atomicAdd(&pn[r], 1);
         // an adjacent inside site is a member; crossing the antipodal line of
-        // the root makes the unwrapped coordinates jump by L - 1
+        // the root makes the unwrapped coordinates jump by L - 1.  Sites on
+        // that line are rare: their neighbours are read from the global map.
         bool amb = false;
-        const int w = (y + 1) * 34 + cx + 1;
-        if (dx == hix) {
-            if (B.conn == 8) amb = in34[w - 34 + 1] | in34[w + 1] | in34[w + 34 + 1];
-            else amb = in34[w + 1];
-        }
-        if (dy == hiy) {
-            if (B.conn == 8) amb |= in34[w + 34 - 1] | in34[w + 34] | in34[w + 34 + 1];
-            else amb |= in34[w + 34];
+        if (dx == hix || dy == hiy) {
+            const int gx = x0 + cx, gy = y0 + y;
+            const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
+            const int yp = gy + 1 == ly ? 0 : gy + 1, ym = gy == 0 ? ly - 1 : gy - 1;
+            auto inside = [&](int xx, int yy) { return B.lab16[(size_t)yy * lx + xx] != 0xffff; };
+            if (dx == hix) {
+                amb = inside(xp, gy);
+                if (B.conn == 8) amb = amb || inside(xp, ym) || inside(xp, yp);
+            }
+            if (dy == hiy) {
+                amb = amb || inside(gx, yp);
+                if (B.conn == 8) amb = amb || inside(xm, yp) || inside(xp, yp);
+            }
         }
         if (amb && prank[r] < B.kmax) atomicOr(&B.acc_amb[prank[r]], 1);
     }

@@ -1,18 +1,15 @@
 // Centres, bucket grid, digital Voronoi colouring and Delaunay couples
-// (Sec. 3.1 last step, Sec. 3.2.1 and Sec. 3.2.2 of the paper), plus the
-// kinematic isomorphism of Sec. 3.2.3, which needs only the bucket grid.
+// (Sec. 3.1 last step, Sec. 3.2.1 and Sec. 3.2.2 of the paper).
 //
 //   k_finalize      exact Q.8 and float64 centres from the integer sums;
 //                   counts the centres of each bucket cell; the last block to
 //                   finish builds the grid (cell offsets, centres by cell)
-//   k_owner_edges   blocks [0, tiles): candidate centres from the grid, nearest
-//                   centre of every site of the tile and its one-site ring
-//                   (LDS), owner map, frame-gap vertex test and the first /
+//   k_owner_edges   one block per tile: candidate centres from the grid,
+//                   nearest centre of every site of the tile and its one-site
+//                   ring (LDS), owner map, frame-gap vertex test and the first /
 //                   second nearest-neighbour rules; the distinct couples of the
 //                   tile go into the adjacency rows with a lock-free set insert
 //                   (rows are unordered sets, MAXLINK padded)
-//                   blocks [tiles, ...): Phi(p) = nearest now centre of every
-//                   past centre p, one wave per point; preimage counts
 #include "dv_device.h"
 
 namespace {
@@ -31,11 +28,10 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
 __global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
     __shared__ int wsum[16];
     __shared__ int s_last;
-    DevState *st = B.st;
-    const bool ok = st->err == 0;
-    const int K = st->K_now;
-    const int now = 1 - st->sel;
-    const CompBuf C = B.comp[now];
+    FrameState *fs = B.fs;
+    const bool ok = fs->err == 0;
+    const int K = fs->K_now;
+    const CompBuf C = B.cur;
     const int t = threadIdx.x;
     if (ok) {
         int namb = 0;
@@ -67,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
             B.cnt[k] = 0;
             B.inv[k] = -1;
         }
-        if (namb) atomicAdd(&st->n_amb, namb);
+        if (namb) atomicAdd(&fs->n_amb, namb);
     }
     // the last block to finish sees every count and builds the grid
     // release: the barrier completes the block's stores, one thread writes
@@ -75,12 +71,12 @@ __global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
     __syncthreads();
     if (t == 0) {
         __threadfence();
-        s_last = atomicAdd(&st->done_fin, 1) == (int)gridDim.x - 1;
+        s_last = atomicAdd(&fs->done_fin, 1) == (int)gridDim.x - 1;
         if (s_last) __threadfence();
     }
     __syncthreads();
     if (!s_last) return;
-    if (t == 0) st->done_fin = 0;
+    if (t == 0) fs->done_fin = 0;
     if (!ok) return;
     const int total = block_exclusive_scan(B.cell_count, B.cell_start, B.ncells, wsum);
     if (t == 0) B.cell_start[B.ncells] = total;
@@ -104,7 +100,7 @@ __device__ __forceinline__ int iny(int r) { return r >= 2 ? -128 : 128; }
 // Lock-free set insert into a row (slots fill from the front; DV_EMPTY marks
 // free slots).  Rows are 16-byte aligned (max_degree is a multiple of 4), so
 // four slots are read per load.
-__device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, DevState *st) {
+__device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, FrameState *fs) {
     for (int i = 0; i < maxdeg; i += 4) {
         const int4 q = *reinterpret_cast<const int4 *>(row + i);
         const int e[4] = {q.x, q.y, q.z, q.w};
@@ -117,40 +113,17 @@ __device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, DevState
                     const int old = atomicCAS(&row[k], DV_EMPTY, v);
                     if (old == DV_EMPTY || old == v) return;
                 }
-                atomicOr(&st->err, DV_E_DEGREE);
+                atomicOr(&fs->err, DV_E_DEGREE);
                 return;
             }
         }
     }
-    atomicOr(&st->err, DV_E_DEGREE);
+    atomicOr(&fs->err, DV_E_DEGREE);
 }
 
 #define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
 #define QCAP 512        // inner-frame queries answered per chunk
 #define TMP_CAP 256     // centres kept from the first pass
-
-// Phi_{P->N} (Sec. 3.2.3): one wave per past centre, nearest now centre by
-// the grid, exact, ties to the lowest label.
-__device__ void match_block(const Bufs &B, int mb, int nmb) {
-    DevState *st = B.st;
-    if (!st->past_valid) return;
-    const int past = st->sel;
-    const int KP = st->K[past], KN = st->K_now;
-    const CompBuf P = B.comp[past];
-    const int lane = threadIdx.x & 63;
-    const int nw = DV_BLOCK / 64;
-    for (int p = mb * nw + (threadIdx.x >> 6); p < KP; p += nmb * nw) {
-        int n = -1;
-        if (KN > 0) n = wave_nearest(B, P.qx[p], P.qy[p]);
-        if (lane == 0) {
-            B.phi[p] = n;
-            if (n >= 0) {
-                atomicAdd(&B.cnt[n], 1);
-                B.inv[n] = p;
-            }
-        }
-    }
-}
 
 #define WSITES 5      // ceil(34*34 / 256) window sites per thread
 #define RCAP 256      // item ranges held in LDS per batch
@@ -246,15 +219,10 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
 
 __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
     __shared__ OwnerLds S;
-    DevState *st = B.st;
-    if (st->err) return;
-    if ((int)blockIdx.x >= B.ncells) {
-        match_block(B, blockIdx.x - B.ncells, gridDim.x - B.ncells);
-        return;
-    }
-    const int K = st->K_now;
-    const int now = 1 - st->sel;
-    int *adj = B.comp[now].adj;
+    FrameState *fs = B.fs;
+    if (fs->err) return;
+    const int K = fs->K_now;
+    int *adj = B.cur.adj;
     const int tx = blockIdx.x % B.ntx, ty = blockIdx.x / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
@@ -410,8 +378,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
         if (slot < PAIR_CAP) {
             S.pair[slot] = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
         } else {
-            row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, st);
-            row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, st);
+            row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, fs);
+            row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
         }
     };
     const int cx = t & 31, ry = t >> 5, lane = t & 63;
@@ -510,8 +478,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
             if (S.pair[j] == key) { first = false; break; }
         if (!first) continue;
         const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
-        if (i & 1) row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, st);
-        else row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, st);
+        if (i & 1) row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
+        else row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, fs);
     }
 }
 
@@ -519,11 +487,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
 
 void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P) {
     const int fgrid = (int)std::min<long long>((B.kmax + 1023) / 1024, 256);
-    const int mgrid = (int)std::min<long long>((B.kmax + 3) / 4, 2048);
     P.begin(ST_FINALIZE, s);
     hipLaunchKernelGGL(k_finalize, dim3(fgrid), dim3(1024), 0, s, B);
     P.end(ST_FINALIZE, s);
     P.begin(ST_OWNER_EDGES, s);
-    hipLaunchKernelGGL(k_owner_edges, dim3(B.ncells + mgrid), dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_owner_edges, dim3(B.ncells), dim3(DV_BLOCK), 0, s, B);
     P.end(ST_OWNER_EDGES, s);
 }

@@ -30,8 +30,10 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
            "dv_status_str", "dv_last_error")
 
-STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "diff",
-          "place")
+DEFAULT_PIPELINE_DEPTH = 3   # what pipeline_depth = 0 selects
+
+STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "match",
+          "diff", "place")
 
 
 class DVConfig(ctypes.Structure):
@@ -39,7 +41,7 @@ class DVConfig(ctypes.Structure):
                 ("threshold", ctypes.c_float), ("phase", ctypes.c_int32),
                 ("connectivity", ctypes.c_int32), ("max_components", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("pipeline_depth", ctypes.c_int32)]
 
 
 class DVFlip(ctypes.Structure):
@@ -131,20 +133,22 @@ class FrameInfo:
 class Detector:
     """One detection context (one sequence of frames) on one device.
 
-    ``stream``: the torch.cuda.Stream the context enqueues its kernels on;
-    None creates one.  Before each push the context's stream waits (on the
-    device, without a host synchronisation) for the caller's current stream,
-    so a field produced there is complete when the kernels read it.
+    ``stream``: the torch.cuda.Stream that orders the context's input; None
+    creates one.  Before each push that stream waits (on the device, without
+    a host synchronisation) for the caller's current stream, and the frame's
+    kernels start after it, so a field produced there is complete when they
+    read it.  ``pipeline_depth``: frames in flight on the device (0: the
+    library's default).
     """
 
     def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
-                 device: int = 0, keep_maps: bool = True, stream=None):
+                 device: int = 0, keep_maps: bool = True, stream=None, pipeline_depth: int = 0):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
         cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
                        int(connectivity), int(max_components), int(max_degree), int(device),
-                       KEEP_MAPS if keep_maps else 0)
+                       KEEP_MAPS if keep_maps else 0, int(pipeline_depth))
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))
@@ -158,7 +162,7 @@ class Detector:
             raise DVError(st, self.lib.dv_last_error(None).decode())
         self.h = h
         self.cfg = cfg
-        self._field_ref = None
+        self._field_refs = []
 
     # -- lifecycle -----------------------------------------------------------
     def close(self):
@@ -201,12 +205,14 @@ class Detector:
             if cur.cuda_stream != self.stream.cuda_stream:
                 self.stream.wait_stream(cur)
                 field.record_stream(self.stream)
-            self._field_ref = field  # kept alive until the next synchronising call
+            # frames overlap on the device: every field pushed since the last
+            # synchronising call may still be read
+            self._field_refs.append(field)
         self._check(self.lib.dv_push_frame(self.h, ctypes.c_void_p(ptr)))
 
     def sync(self):
         self._check(self.lib.dv_sync(self.h))
-        self._field_ref = None
+        self._field_refs.clear()
 
     def flips(self) -> np.ndarray:
         """Flips of the most recent frame: int32 [F, 6] = (a, b, pa, pb, kind, flags)."""
@@ -214,13 +220,13 @@ class Detector:
         self._check(self.lib.dv_get_flips(self.h, None, 0, ctypes.byref(n)), allow=(ERR_CAPACITY,))
         out = np.zeros((max(n.value, 1), 6), dtype=np.int32)
         self._check(self.lib.dv_get_flips(self.h, _ptr(out), n.value, ctypes.byref(n)))
-        self._field_ref = None
+        self._field_refs.clear()
         return out[:n.value]
 
     def info(self) -> FrameInfo:
         fi = DVFrameInfo()
         self._check(self.lib.dv_get_info(self.h, ctypes.byref(fi)), allow=(ERR_CAPACITY,))
-        self._field_ref = None
+        self._field_refs.clear()
         return FrameInfo(fi.frame, fi.status, fi.n_components, fi.n_edges, fi.n_flips,
                          fi.n_breaking, fi.n_excluded_past, fi.n_excluded_now,
                          fi.n_ambiguous_centroids, fi.global_trigger)

@@ -29,25 +29,26 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(dv.DVConfig) == 40
+    assert ctypes.sizeof(dv.DVConfig) == 44
     assert ctypes.sizeof(dv.DVFlip) == 24
     assert ctypes.sizeof(dv.DVFrameInfo) == 48
 
 
 def _cfg(**kw):
     base = dict(lx=64, ly=64, threshold=0.5, phase=0, connectivity=8, max_components=100,
-                max_degree=0, device=0, flags=1)
+                max_degree=0, device=0, flags=1, pipeline_depth=0)
     base.update(kw)
     c = dv.DVConfig(ctypes.sizeof(dv.DVConfig), base["lx"], base["ly"], base["threshold"],
                     base["phase"], base["connectivity"], base["max_components"],
-                    base["max_degree"], base["device"], base["flags"])
+                    base["max_degree"], base["device"], base["flags"], base["pipeline_depth"])
     return c
 
 
 @pytest.mark.parametrize("bad", [
     dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
     dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
-    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=2)])
+    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=2),
+    dict(pipeline_depth=-1), dict(pipeline_depth=5)])
 def test_invalid_config_is_rejected_on_the_host(bad):
     lib = dv.load()
     h = ctypes.c_void_p()

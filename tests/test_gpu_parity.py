@@ -181,6 +181,51 @@ def test_capacity_rejection_keeps_the_past():
     det.close()
 
 
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+def test_pipelined_bursts_match_the_oracle(depth):
+    """Frames pushed back to back with no synchronisation in between overlap on
+    the device; the state after each burst (flips against the previous frame,
+    labels, couples, matching) must equal the oracle's."""
+    lx, ly = 200, 160
+    sim = synth.DiskSim(lx, ly, 30, 4.0, 7.0, 0.6, 3e-3, seed=91 + depth)
+    frames = list(sim.frames(11))
+    dev = [torch.from_numpy(f).cuda() for f in frames]
+    det = dv.Detector(lx, ly, 0.5, max_components=256, pipeline_depth=depth)
+    seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
+    for k, f in enumerate(frames):
+        now, ref = seq.push(f)
+        det.push(dev[k])
+        if k in (0, 4, 10):
+            say(f"  [pipe{depth}] burst ends at frame {k}")
+            check_frame(det, now, ref, lx, ly)
+    assert det.info().frame == len(frames)
+    det.close()
+
+
+def test_rejection_inside_a_pipelined_burst():
+    """A rejected frame in the middle of a burst: the frame after it is compared
+    with the last accepted one."""
+    sim = synth.DiskSim(120, 100, 12, 4.0, 6.0, 0.8, 2e-3, seed=78)
+    a, b, c, d = list(sim.frames(4))
+    noise = (synth.tiny_random_field(120, 100, 5) > 0.85).astype(np.float32)
+    dev = [torch.from_numpy(x).cuda() for x in (a, b, noise, c)]
+    det = dv.Detector(120, 100, 0.5, max_components=64, pipeline_depth=3)
+    for x in dev:
+        det.push(x)
+    got = det.flips()
+    ref = oracle.compare(oracle.frame(b, 0.5), oracle.frame(c, 0.5))
+    assert np.array_equal(got, ref.flips)
+    assert det.info().frame == 3
+    det.push(torch.from_numpy(d).cuda())
+    det.push(dev[2])
+    with pytest.raises(dv.DVError):
+        det.flips()
+    det.push(dev[1])
+    ref = oracle.compare(oracle.frame(d, 0.5), oracle.frame(b, 0.5))
+    assert np.array_equal(det.flips(), ref.flips)
+    det.close()
+
+
 def test_degree_overflow_is_reported():
     sim = synth.DiskSim(128, 128, 30, 3.0, 5.0, 0.5, 1e-3, seed=8)
     f = next(sim.frames(1))
@@ -214,6 +259,24 @@ def test_disks256_all_frames():
 def test_disks1024_frames():
     sim, spec = synth.workload("disks1024")
     run_sequence(list(sim.frames(6)), spec["threshold"], kmax=4096, tag="disks1024")
+
+
+def test_disks1024_pipelined_burst():
+    """Twenty full-size frames pushed back to back in the benchmark's launch
+    configuration (default pipeline depth); the last comparison against the
+    oracle."""
+    sim, spec = synth.workload("disks1024")
+    frames = list(sim.frames(20))
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    det = dv.Detector(1024, 1024, spec["threshold"], spec["phase"], 8, max_components=4096)
+    for k in range(len(frames)):
+        det.push(dev[k])
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS)
+    seq.push(frames[-2])
+    now, ref = seq.push(frames[-1])
+    check_frame(det, now, ref, 1024, 1024)
+    assert det.info().frame == len(frames)
+    det.close()
 
 
 def test_grf1024_frames():
