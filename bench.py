@@ -62,7 +62,16 @@ def source_hash(stage: str) -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(stage: str, workload: str, maps: bool):
+def _default_batch() -> int:
+    from paper_1607_00908_amd import dv
+    return dv.DEFAULT_BATCH
+
+
+def counter_key(stage: str, workload: str, maps: bool, batch: int) -> str:
+    return f"{stage}:{workload}:{'maps' if maps else 'flips'}:batch{batch}"
+
+
+def counter_traffic(stage: str, workload: str, maps: bool, batch: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, when
     it was taken on the current source of the stage; else None."""
     p = os.path.join(ROOT, "profiles", "counters.json")
@@ -72,8 +81,7 @@ def counter_traffic(stage: str, workload: str, maps: bool):
         d = json.load(open(p))
     except ValueError:
         return None
-    key = f"{stage}:{workload}:{'maps' if maps else 'flips'}"
-    e = d.get(key)
+    e = d.get(counter_key(stage, workload, maps, batch))
     if not e or e.get("source_sha") != source_hash(stage):
         return None
     return int(round(e["bytes_per_dispatch"]))
@@ -97,26 +105,31 @@ def copy_probe(mib: int):
 
 
 def _read_counter_csv(path: str):
-    """(kernel name, counter value) per dispatch from a rocprofv3 counter CSV."""
+    """(kernel name, grid size, counter value) per dispatch from a rocprofv3
+    counter CSV."""
     import csv
     out = {}
     with open(path, newline="") as fh:
         for row in csv.DictReader(fh):
             key = (row.get("Dispatch_Id") or row.get("Correlation_Id"), row["Counter_Name"])
-            out[key] = (row["Kernel_Name"], float(row["Counter_Value"]))
+            out[key] = (row["Kernel_Name"], int(row.get("Grid_Size") or 0),
+                        float(row["Counter_Value"]))
     return list(out.values())
 
 
 def counters_from(fetch_csv: str, write_csv: str, stage: str, workload: str, maps: bool,
-                  copy_mib: int):
+                  copy_mib: int, batch: int):
     """Scaled HBM bytes per dispatch of `stage` from FETCH_SIZE / WRITE_SIZE runs."""
     import statistics
     kname = "k_" + stage
     res = {}
     for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = _read_counter_csv(path)
-        ker = [v for k, v in rows if re.search(r"\b%s\b" % kname, k)]
-        cpy = [v for k, v in rows if "neg" in k.lower()]
+        # dispatches of the full batch only (the largest grid of the kernel)
+        kr = [(g, v) for k, g, v in rows if re.search(r"\b%s\b" % kname, k)]
+        gmax = max((g for g, _ in kr), default=0)
+        ker = [v for g, v in kr if g == gmax]
+        cpy = [v for k, g, v in rows if "neg" in k.lower()]
         if not ker or not cpy:
             raise SystemExit(f"{path}: no dispatches of {kname} or of the copy probe")
         expect_kib = copy_mib * 1024.0
@@ -127,7 +140,7 @@ def counters_from(fetch_csv: str, write_csv: str, stage: str, workload: str, map
     bytes_per = sum(r["kib_per_dispatch"] * r["scale"] * 1024.0 for r in res.values())
     p = os.path.join(ROOT, "profiles", "counters.json")
     d = json.load(open(p)) if os.path.exists(p) else {}
-    d[f"{stage}:{workload}:{'maps' if maps else 'flips'}"] = {
+    d[counter_key(stage, workload, maps, batch)] = {
         "source_sha": source_hash(stage), "bytes_per_dispatch": bytes_per, **res}
     with open(p, "w") as fh:
         json.dump(d, fh, indent=1, sort_keys=True)
@@ -170,8 +183,8 @@ def main():
     ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
     ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
     ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
-    ap.add_argument("--pipeline-depth", type=int, default=0,
-                    help="frames in flight on the device (0: the library default)")
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="frames per launch of each stage (0: the library default)")
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -183,7 +196,7 @@ def main():
 
     if args.counters_from:
         counters_from(*args.counters_from, args.stage, args.workload, not args.flips_only,
-                      args.copy_probe_mib)
+                      args.copy_probe_mib, args.max_batch or _default_batch())
         return
 
     if args.gpus != 1:
@@ -209,7 +222,7 @@ def main():
     maps = not args.flips_only
     kmax = 32768 if N > (1 << 22) else 4096
     det = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
-                      keep_maps=maps, pipeline_depth=args.pipeline_depth)
+                      keep_maps=maps, max_batch=args.max_batch)
     F = ring.shape[0]
 
     # the ring is complete on the device (synchronised above): frames are
@@ -248,15 +261,19 @@ def main():
         lat.append(time.perf_counter() - a)
     lat = np.array(lat) * 1e3
 
+    # one launch of a stage covers every frame of a batch
     stage_avg_ms = stage_ms / max(launches, 1)
+    frames_per_launch = args.steps / max(launches, 1)
     per_site = STAGE_BYTES.get(args.stage, (0, 0))[0 if maps else 1]
-    alg_bytes = per_site * N
+    alg_bytes = per_site * N * frames_per_launch
     achieved = alg_bytes / (stage_avg_ms * 1e-3) / 1e9 if stage_avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": counter_traffic(args.stage, args.workload, maps),
-                "kernel": args.stage, "kernel_us": round(stage_avg_ms * 1e3, 2),
-                "algorithmic_bytes": alg_bytes}
+                "traffic": counter_traffic(args.stage, args.workload, maps,
+                                           args.max_batch or dv.DEFAULT_BATCH),
+                "kernel": args.stage, "launch_us": round(stage_avg_ms * 1e3, 2),
+                "launches": launches, "frames_per_launch": round(frames_per_launch, 3),
+                "algorithmic_bytes_per_launch": int(round(alg_bytes))}
 
     out = {
         "metric": "Msites/s through label+Voronoi+flip pipeline (%HBM peak); p50/p99 frame latency",
@@ -274,12 +291,12 @@ def main():
         "config": {"workload": args.workload, "lx": lx, "ly": ly, "frames_in_ring": F,
                    "components": info.n_components, "edges": info.n_edges,
                    "mode": "maps+flips" if maps else "flips-only",
-                   "pipeline_depth": args.pipeline_depth or dv.DEFAULT_PIPELINE_DEPTH, "parallelism": "single-gpu"},
+                   "max_batch": args.max_batch or dv.DEFAULT_BATCH, "parallelism": "single-gpu"},
         "frames_per_s": round(args.steps / elapsed, 1),
         "hbm_frac_pipeline": round(msites * 1e6 * (12 if maps else 4) / (HBM_PEAK_GBS * 1e9), 5),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4),
-                       "samples": len(lat)},
+        "latency_ms": ({"p50": round(float(np.percentile(lat, 50)), 4),
+                        "p99": round(float(np.percentile(lat, 99)), 4),
+                        "samples": len(lat)} if len(lat) else None),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -81,8 +81,8 @@ typedef struct {
                                 4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
     uint32_t flags;          /* DV_KEEP_MAPS                                       */
-    int32_t pipeline_depth;  /* frames in flight on the device, 1 .. 4; 0 selects 3.
-                                Each one holds its own per-site buffers.          */
+    int32_t max_batch;       /* frames sent to the device together, 1 .. 8; 0
+                                selects 4.  Each holds its own per-site buffers. */
 } dv_config;
 
 /* One edge flip (Sec. 3.2.4).  a < b are now labels; pa, pb the past labels
@@ -113,20 +113,21 @@ typedef struct {
 } dv_frame_info;
 
 /* Create a context on cfg->device.  hip_stream is a hipStream_t on that
- * device, or NULL for a stream the context creates (and destroys).  The work
- * of a push starts after everything enqueued on that stream before the push;
- * it then runs on streams the context owns, so that consecutive frames
- * overlap (up to pipeline_depth of them), and the comparisons with the past
- * run in push order.  On success *out owns every device buffer; on failure
- * *out is NULL. */
+ * device, or NULL for a stream the context creates (and destroys).  All
+ * device work of the context is ordered on that stream.  Pushed frames are
+ * queued on the host and sent to the device together, max_batch at a time
+ * (or fewer, at the next synchronising call): every stage then runs as one
+ * launch over all of them.  On success *out owns every device buffer; on
+ * failure *out is NULL. */
 dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
 
 /* Enqueue one frame.  field_device: lx*ly float32 values in device memory,
- * row-major (x fastest).  The field is read asynchronously, after the work
- * enqueued on the context's stream before this call: the caller keeps it
- * alive and unmodified until the next synchronising call (dv_get_flips,
- * dv_get_info, any getter, dv_sync).  The call itself never waits for the
- * device.
+ * row-major (x fastest), complete in the order of the context's stream at
+ * the time of this call.  The field is read asynchronously on that stream,
+ * at the latest when the next synchronising call (dv_get_flips, dv_get_info,
+ * any getter, dv_sync) sends the queue: the caller keeps it alive and
+ * unmodified until that call returns.  The call never waits for the device;
+ * every max_batch-th push enqueues the launches of the queued frames.
  * The first accepted frame has no past and yields no flips.  A frame whose
  * component count exceeds K_max, or whose Delaunay degree exceeds the row
  * capacity, is rejected: the next synchronising call reports
@@ -142,7 +143,7 @@ dv_status dv_get_flips(dv_ctx *ctx, dv_flip *host_out, int32_t capacity, int32_t
  * status of that push (DV_OK or DV_ERR_CAPACITY); *info is filled either way. */
 dv_status dv_get_info(dv_ctx *ctx, dv_frame_info *info);
 
-/* Wait until every pushed frame has been processed. */
+/* Send any queued frames and wait until every pushed frame is processed. */
 dv_status dv_sync(dv_ctx *ctx);
 
 /* Release everything the context owns.  NULL is accepted. */
@@ -169,7 +170,8 @@ dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *
 
 /* Stages of the per-frame procedure, in launch order. */
 #define DV_N_STAGES 9
-/* Bracket every launch of one stage with HIP events on the stream it runs on.
+/* Bracket every launch of one stage with HIP events on the context's stream
+ * (one launch covers every frame of a batch).
  * stage: 0 .. DV_N_STAGES-1, or -1 to stop.  capacity: launches that can be
  * recorded before the next dv_get_profile (further launches are not timed).
  * Creates the events; returns DV_ERR_ARG for a bad stage or capacity. */

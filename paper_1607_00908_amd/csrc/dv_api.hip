@@ -1,17 +1,15 @@
 // Host side of libdv: the C ABI declared in include/dv.h.
 //
-// A context owns every device buffer, sized once from the lattice and K_max.
-// Frames go through a pipeline of `depth` slots: frame f uses slot f % depth
-// for everything up to its Delaunay couples (labelling, centres, colouring),
-// enqueued on that slot's stream, so consecutive frames overlap on the
-// device.  Its comparison with the last accepted frame (matching, diff,
-// commit) runs on one chain stream in frame order.  Events order the work:
-//   slot stream  waits for the caller's stream at the push (the field is
-//                ready) and for the chain of the slot's previous frame (its
-//                buffers are free again);
-//   chain        waits for the slot's stage of the frame.
-// No host synchronisation happens in a push.  Synchronising calls wait for the
-// chain and copy the sequence header (and the requested arrays) back.
+// A context owns every device buffer, sized once from the lattice, K_max and
+// the batch size.  Pushes are queued on the host; when `batch` frames are
+// queued, or at the next synchronising call, the queued frames go to the
+// device together: each stage is one launch over all of them (frame =
+// blockIdx.z, slot i holds the buffers of the batch's i-th frame), all on the
+// context's stream, so no cross-stream ordering is needed and the host pays
+// nine launches per batch.  The comparisons of a batch are independent: the
+// device knows each frame's past from the frame headers.  Synchronising
+// calls flush the queue, wait for the stream and copy the headers (and the
+// requested arrays) back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,26 +21,20 @@
 #include "dv.h"
 #include "dv_internal.h"
 
-#define DV_MAX_DEPTH 4
-
-struct Slot {
-    Bufs B;                  // slot buffers + the shared chain buffers
-    hipStream_t stream = nullptr;
-    hipEvent_t ev_in = nullptr, ev_s1 = nullptr, ev_done = nullptr;
-};
-
 struct dv_ctx {
     dv_config cfg;
     int device;
-    hipStream_t stream;      // the caller's (or owned) stream: input ordering
+    hipStream_t stream;
     bool own_stream;
-    hipStream_t chain;       // comparison chain
-    int depth;
-    Slot slot[DV_MAX_DEPTH];
-    int64_t pushes;          // frames pushed so far
-    int last;                // slot of the most recent push
+    int batch;               // frames per launch
+    Bufs h_tab[DV_MAX_BATCH];  // host copy of the slot table
+    Bufs *d_tab;             // device slot table
+    Fields pending;          // queued field pointers
+    int npending;
+    int last;                // slot of the most recent frame sent to the device
     std::vector<void *> allocs;
-    SeqState *h_state;       // pinned mirror of the sequence header
+    SeqState *h_state;       // pinned mirrors of the headers
+    FrameState *h_frame;
     int32_t *d_edge_scratch; // [2 * K_max] for the couple-list getter
     int32_t *d_edge_ab;      // [K_max * max_degree] pairs
     int32_t *d_edge_total;
@@ -79,35 +71,38 @@ void drop_events(dv_ctx *c) {
     c->prof = Prof();
 }
 
-// wait for every stream of the context
-bool drain(dv_ctx *c) {
-    bool ok = true;
-    for (int k = 0; k < c->depth; ++k)
-        if (c->slot[k].stream) ok = hipStreamSynchronize(c->slot[k].stream) == hipSuccess && ok;
-    if (c->chain) ok = hipStreamSynchronize(c->chain) == hipSuccess && ok;
-    if (c->stream) ok = hipStreamSynchronize(c->stream) == hipSuccess && ok;
-    return ok;
+// send the queued frames to the device
+dv_status flush(dv_ctx *c) {
+    const int n = c->npending;
+    if (n == 0) return DV_OK;
+    launch_label(c->h_tab[0], c->d_tab, n, c->pending, c->stream, c->prof);
+    launch_voronoi(c->h_tab[0], c->d_tab, n, c->stream, c->prof);
+    launch_compare(c->h_tab[0], c->d_tab, n, c->stream, c->prof);
+    c->npending = 0;
+    c->last = n - 1;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return DV_OK;
+}
+
+dv_status drain(dv_ctx *c) {
+    dv_status s = flush(c);
+    if (s != DV_OK) return s;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, DV_ERR_DEVICE, "stream error");
+    return DV_OK;
 }
 
 void release(dv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    (void)drain(c);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_events(c);
-    for (int k = 0; k < DV_MAX_DEPTH; ++k) {
-        Slot &S = c->slot[k];
-        if (S.ev_in) (void)hipEventDestroy(S.ev_in);
-        if (S.ev_s1) (void)hipEventDestroy(S.ev_s1);
-        if (S.ev_done) (void)hipEventDestroy(S.ev_done);
-        if (S.stream) (void)hipStreamDestroy(S.stream);
-        S = Slot();
-    }
-    if (c->chain) (void)hipStreamDestroy(c->chain);
-    c->chain = nullptr;
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_frame) (void)hipHostFree(c->h_frame);
     c->h_state = nullptr;
+    c->h_frame = nullptr;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
 }
@@ -129,16 +124,19 @@ dv_status check_cfg(const dv_config *cfg) {
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
     if (cfg->flags & ~DV_KEEP_MAPS) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
-    if (cfg->pipeline_depth < 0 || cfg->pipeline_depth > DV_MAX_DEPTH)
-        return fail(nullptr, DV_ERR_ARG, "pipeline_depth must be 0 or in [1, 4]");
+    if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
+        return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 8]");
     return DV_OK;
 }
 
 dv_status sync_state(dv_ctx *c) {
-    if (!drain(c) ||
-        hipMemcpyAsync(c->h_state, c->slot[0].B.st, sizeof(SeqState), hipMemcpyDeviceToHost,
-                       c->chain) != hipSuccess ||
-        hipStreamSynchronize(c->chain) != hipSuccess)
+    dv_status s = flush(c);
+    if (s != DV_OK) return s;
+    if (hipMemcpyAsync(c->h_state, c->h_tab[0].st, sizeof(SeqState), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->h_frame, c->h_tab[c->last].fs, sizeof(FrameState),
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
     return DV_OK;
 }
@@ -150,7 +148,7 @@ dv_status ready(dv_ctx *c) {
     (void)hipSetDevice(c->device);
     dv_status s = sync_state(c);
     if (s != DV_OK) return s;
-    if (c->h_state->status != 0) return fail(c, (dv_status)c->h_state->status, "most recent frame was rejected (capacity)");
+    if (c->h_frame->status != 0) return fail(c, (dv_status)c->h_frame->status, "most recent frame was rejected (capacity)");
     return DV_OK;
 }
 
@@ -174,13 +172,14 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     if (c->cfg.max_degree == 0) c->cfg.max_degree = 48;
     // row slots are read four at a time
     c->cfg.max_degree = (c->cfg.max_degree + 3) & ~3;
-    if (c->cfg.pipeline_depth == 0) c->cfg.pipeline_depth = 3;
-    c->depth = c->cfg.pipeline_depth;
+    if (c->cfg.max_batch == 0) c->cfg.max_batch = DV_DEFAULT_BATCH;
+    c->batch = c->cfg.max_batch;
     c->device = c->cfg.device;
-    c->chain = nullptr;
-    c->pushes = 0;
+    c->npending = 0;
     c->last = 0;
     c->h_state = nullptr;
+    c->h_frame = nullptr;
+    c->d_tab = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -195,21 +194,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
         }
         c->own_stream = true;
     }
-    bool ok = hipStreamCreateWithFlags(&c->chain, hipStreamNonBlocking) == hipSuccess;
-    for (int k = 0; ok && k < c->depth; ++k) {
-        Slot &S = c->slot[k];
-        ok = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&S.ev_s1, hipEventDisableTiming) == hipSuccess &&
-             hipEventCreateWithFlags(&S.ev_done, hipEventDisableTiming) == hipSuccess;
-    }
-    if (!ok) {
-        release(c);
-        delete c;
-        return fail(nullptr, DV_ERR_DEVICE, "stream or event creation failed");
-    }
 
-    // shared part of the buffer table
+    // shared part of the slot table
     Bufs B;
     std::memset(&B, 0, sizeof(B));
     B.lx = c->cfg.lx;
@@ -230,15 +216,12 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
                dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
                dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
     };
-    ok = dalloc(c, &B.phi, K) && dalloc(c, &B.trigger, K) && dalloc(c, &B.nb, K) &&
-         dalloc(c, &B.na, K) && dalloc(c, &B.ob, K) && dalloc(c, &B.oa, K) &&
-         dalloc(c, &B.flips, K * B.maxdeg * 6) && dalloc(c, &B.stage, K * B.maxdeg * 12) &&
-         dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
-         dalloc(c, &c->d_edge_scratch, 2 * K) && dalloc(c, &c->d_edge_ab, K * B.maxdeg) &&
-         dalloc(c, &c->d_edge_total, 1);
+    bool ok = dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
+              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
+              dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
     // per-slot buffers
-    for (int k = 0; ok && k < c->depth; ++k) {
-        Bufs &b = c->slot[k].B;
+    for (int k = 0; ok && k < c->batch; ++k) {
+        Bufs &b = c->h_tab[k];
         b = B;
         ok = dalloc(c, &b.parent, N) && dalloc(c, &b.lab16, N) &&
              dalloc(c, &b.pieces, tiles * DV_TILE_SITES) && dalloc(c, &b.npieces, tiles) &&
@@ -249,22 +232,29 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
              dalloc(c, &b.cell_start, tiles + 1) && dalloc(c, &b.cell_items, K) &&
              dalloc(c, &b.cell_q, K) && dalloc(c, &b.comp_cell, K) && dalloc(c, &b.comp_slot, K) &&
              dalloc(c, &b.cnt, K) && dalloc(c, &b.inv, K) && dalloc(c, &b.fs, 1) &&
-             comp_alloc(b.cur);
+             comp_alloc(b.cur) && dalloc(c, &b.phi, K) && dalloc(c, &b.trigger, K) &&
+             dalloc(c, &b.nb, K) && dalloc(c, &b.na, K) && dalloc(c, &b.ob, K) &&
+             dalloc(c, &b.oa, K) && dalloc(c, &b.flips, K * B.maxdeg * 6) &&
+             dalloc(c, &b.stage, K * B.maxdeg * 12);
         if (ok && B.keep_maps) ok = dalloc(c, &b.labels, N) && dalloc(c, &b.owner, N);
     }
-    if (ok && hipHostMalloc((void **)&c->h_state, sizeof(SeqState)) != hipSuccess) ok = false;
+    if (ok && (hipHostMalloc((void **)&c->h_state, sizeof(SeqState)) != hipSuccess ||
+               hipHostMalloc((void **)&c->h_frame, sizeof(FrameState)) != hipSuccess))
+        ok = false;
     if (!ok) {
         release(c);
         delete c;
         return fail(nullptr, DV_ERR_NOMEM, "device allocation failed");
     }
-    // initial contents: zero accumulators and headers, empty rows
-    hipStream_t s0 = c->chain;
-    bool z = hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
+    // initial contents: slot table, zero accumulators and headers, empty rows
+    hipStream_t s0 = c->stream;
+    bool z = hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(Bufs) * c->batch, hipMemcpyHostToDevice, s0) ==
+                 hipSuccess &&
+             hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
     for (int b = 0; z && b < 2; ++b)
         z = hipMemsetD32Async((hipDeviceptr_t)B.past[b].adj, DV_EMPTY, K * B.maxdeg, s0) == hipSuccess;
-    for (int k = 0; z && k < c->depth; ++k) {
-        const Bufs &b = c->slot[k].B;
+    for (int k = 0; z && k < c->batch; ++k) {
+        const Bufs &b = c->h_tab[k];
         z = hipMemsetAsync(b.acc_x, 0, K * sizeof(long long), s0) == hipSuccess &&
             hipMemsetAsync(b.acc_y, 0, K * sizeof(long long), s0) == hipSuccess &&
             hipMemsetAsync(b.acc_n, 0, K * sizeof(int), s0) == hipSuccess &&
@@ -286,34 +276,16 @@ dv_status dv_push_frame(dv_ctx *c, const float *field_device) {
     if (!c) return DV_ERR_ARG;
     if (!field_device) return fail(c, DV_ERR_ARG, "field is NULL");
     (void)hipSetDevice(c->device);
-    const int k = (int)(c->pushes % c->depth);
-    Slot &S = c->slot[k];
-    S.B.field = field_device;
-    bool ok = hipEventRecord(S.ev_in, c->stream) == hipSuccess &&
-              hipStreamWaitEvent(S.stream, S.ev_in, 0) == hipSuccess;
-    // the slot's previous frame must have left the chain (no-op before its first use)
-    if (ok && c->pushes >= c->depth) ok = hipStreamWaitEvent(S.stream, S.ev_done, 0) == hipSuccess;
-    if (!ok) return fail(c, DV_ERR_DEVICE, "event ordering failed");
-    launch_label(S.B, S.stream, c->prof);
-    launch_voronoi(S.B, S.stream, c->prof);
-    ok = hipEventRecord(S.ev_s1, S.stream) == hipSuccess &&
-         hipStreamWaitEvent(c->chain, S.ev_s1, 0) == hipSuccess;
-    if (!ok) return fail(c, DV_ERR_DEVICE, "event ordering failed");
-    launch_chain(S.B, c->chain, c->prof);
-    if (hipEventRecord(S.ev_done, c->chain) != hipSuccess) return fail(c, DV_ERR_DEVICE, "event record failed");
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
-    c->last = k;
-    c->pushes += 1;
+    c->pending.p[c->npending++] = field_device;
     c->pushed = true;
+    if (c->npending == c->batch) return flush(c);
     return DV_OK;
 }
 
 dv_status dv_sync(dv_ctx *c) {
     if (!c) return DV_ERR_ARG;
     (void)hipSetDevice(c->device);
-    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
-    return DV_OK;
+    return drain(c);
 }
 
 dv_status dv_get_info(dv_ctx *c, dv_frame_info *info) {
@@ -323,32 +295,33 @@ dv_status dv_get_info(dv_ctx *c, dv_frame_info *info) {
     dv_status s = sync_state(c);
     if (s != DV_OK) return s;
     const SeqState &h = *c->h_state;
+    const FrameState &f = *c->h_frame;
     dv_frame_info fi;
     std::memset(&fi, 0, sizeof(fi));
     fi.frame = h.frame;
-    fi.status = h.status;
-    fi.n_components = h.K_now;
-    fi.n_edges = h.status == 0 ? h.E[h.sel] : 0;
-    fi.n_flips = h.n_flips;
-    fi.n_breaking = h.n_break;
-    fi.n_excluded_past = h.n_excl_past;
-    fi.n_excluded_now = h.n_excl_now;
-    fi.n_ambiguous_centroids = h.n_amb;
-    fi.global_trigger = (uint32_t)h.global_trigger;
+    fi.status = f.status;
+    fi.n_components = f.K_now;
+    fi.n_edges = f.status == 0 ? f.E_now : 0;
+    fi.n_flips = f.n_flips;
+    fi.n_breaking = f.n_break;
+    fi.n_excluded_past = f.n_excl_past;
+    fi.n_excluded_now = f.n_excl_now;
+    fi.n_ambiguous_centroids = f.n_amb;
+    fi.global_trigger = (uint32_t)f.global_trigger;
     *info = fi;
-    return (dv_status)h.status;
+    return (dv_status)f.status;
 }
 
 dv_status dv_get_flips(dv_ctx *c, dv_flip *host_out, int32_t capacity, int32_t *n_out) {
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const int n = c->h_state->n_flips;
+    const int n = c->h_frame->n_flips;
     *n_out = n;
     if (n > capacity) return fail(c, DV_ERR_CAPACITY, "flip buffer too small");
     if (n > 0) {
         if (!host_out) return fail(c, DV_ERR_ARG, "host_out is NULL");
-        if (hipMemcpy(host_out, c->slot[0].B.flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(host_out, c->h_tab[c->last].flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, DV_ERR_DEVICE, "copy failed");
     }
     return DV_OK;
@@ -359,7 +332,7 @@ dv_status dv_get_labels(dv_ctx *c, int32_t *host_out) {
     if (!(c->cfg.flags & DV_KEEP_MAPS)) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const Bufs &B = c->slot[c->last].B;
+    const Bufs &B = c->h_tab[c->last];
     const size_t N = (size_t)B.lx * B.ly;
     if (hipMemcpy(host_out, B.labels, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
@@ -371,7 +344,7 @@ dv_status dv_get_owner(dv_ctx *c, int32_t *host_out) {
     if (!(c->cfg.flags & DV_KEEP_MAPS)) return fail(c, DV_ERR_STATE, "maps not kept (DV_KEEP_MAPS)");
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const Bufs &B = c->slot[c->last].B;
+    const Bufs &B = c->h_tab[c->last];
     const size_t N = (size_t)B.lx * B.ly;
     if (hipMemcpy(host_out, B.owner, N * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
@@ -388,7 +361,7 @@ dv_status dv_get_components(dv_ctx *c, int32_t *q8_xy, double *xy, int32_t *size
     *n_out = K;
     if (K > capacity) return fail(c, DV_ERR_CAPACITY, "component buffer too small");
     if (K == 0) return DV_OK;
-    const CompBuf &C = c->slot[0].B.past[h.sel];
+    const CompBuf &C = c->h_tab[0].past[h.sel];
     std::vector<int32_t> qx(K), qy(K);
     std::vector<double> fx(K), fy(K);
     bool ok = hipMemcpy(qx.data(), C.qx, K * 4, hipMemcpyDeviceToHost) == hipSuccess &&
@@ -408,10 +381,10 @@ dv_status dv_get_edges(dv_ctx *c, int32_t *ab, int32_t capacity, int32_t *n_out)
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    launch_edge_list(c->slot[c->last].B, c->d_edge_ab, c->d_edge_total, c->d_edge_scratch, c->chain);
+    launch_edge_list(c->h_tab[0], c->d_tab, c->d_edge_ab, c->d_edge_total, c->d_edge_scratch, c->stream);
     int32_t E = 0;
-    if (hipMemcpyAsync(&E, c->d_edge_total, 4, hipMemcpyDeviceToHost, c->chain) != hipSuccess ||
-        hipStreamSynchronize(c->chain) != hipSuccess)
+    if (hipMemcpyAsync(&E, c->d_edge_total, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "edge list failed");
     *n_out = E;
     if (E > capacity) return fail(c, DV_ERR_CAPACITY, "edge buffer too small");
@@ -427,15 +400,15 @@ dv_status dv_get_matching(dv_ctx *c, int32_t *phi, int32_t capacity, int32_t *n_
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const int KP = c->h_state->K_past_cmp;
+    const int KP = c->h_frame->K_past;
     *n_out = KP;
     if (KP > capacity) return fail(c, DV_ERR_CAPACITY, "matching buffer too small");
     if (KP == 0) return DV_OK;
     if (!phi) return fail(c, DV_ERR_ARG, "phi is NULL");
     // Phi with dropped past points as -1, written to scratch on the device
-    launch_phi_out(c->slot[c->last].B, c->d_edge_ab, c->chain);
-    if (hipMemcpyAsync(phi, c->d_edge_ab, (size_t)KP * 4, hipMemcpyDeviceToHost, c->chain) != hipSuccess ||
-        hipStreamSynchronize(c->chain) != hipSuccess)
+    launch_phi_out(c->h_tab[0], c->d_tab, c->last, c->d_edge_ab, c->stream);
+    if (hipMemcpyAsync(phi, c->d_edge_ab, (size_t)KP * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, DV_ERR_DEVICE, "copy failed");
     return DV_OK;
 }
@@ -458,7 +431,8 @@ dv_status dv_set_profile(dv_ctx *c, int32_t stage, int32_t capacity) {
     if (stage < -1 || stage >= ST_COUNT || (stage >= 0 && (capacity < 1 || capacity > (1 << 20))))
         return fail(c, DV_ERR_ARG, "bad stage or capacity");
     (void)hipSetDevice(c->device);
-    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
+    dv_status ds = drain(c);
+    if (ds != DV_OK) return ds;
     drop_events(c);
     if (stage < 0) return DV_OK;
     c->prof.ev = new hipEvent_t[2 * (size_t)capacity];
@@ -478,7 +452,8 @@ dv_status dv_set_profile(dv_ctx *c, int32_t stage, int32_t capacity) {
 dv_status dv_get_profile(dv_ctx *c, double *total_ms, int32_t *launches) {
     if (!c || !total_ms || !launches) return DV_ERR_ARG;
     (void)hipSetDevice(c->device);
-    if (!drain(c)) return fail(c, DV_ERR_DEVICE, "stream error");
+    dv_status ds = drain(c);
+    if (ds != DV_OK) return ds;
     double tot = 0.0;
     for (int i = 0; i < c->prof.used; ++i) {
         float ms = 0.f;

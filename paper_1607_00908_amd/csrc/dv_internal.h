@@ -9,43 +9,45 @@
 #define DV_TILE_SITES (DV_TILE * DV_TILE)
 #define DV_BLOCK 256               // threads per tile workgroup
 #define DV_EMPTY 0x77777777        // MAXLINK: empty row slot / no colour
-#define DV_CAND_CAP 512            // candidate centre images held in LDS per chunk
+#define DV_CAND_CAP 256            // candidate centre images held in LDS per chunk
 
 // error bits raised on the device during a frame
 #define DV_E_KMAX 1u               // more components than K_max
 #define DV_E_DEGREE 2u             // a Delaunay row overflowed max_degree
 
-// Per-frame header, one per pipeline slot (device memory).
+#define DV_MAX_BATCH 8             // frames processed by one launch of each stage
+#define DV_DEFAULT_BATCH 4         // what max_batch = 0 selects
+
+// Per-frame header, one per batch slot (device memory).
 struct FrameState {
     int32_t K_now;         // components found in the frame (raw, may exceed K_max)
     uint32_t err;          // DV_E_* bits of the frame
     int32_t rows_dirty;    // rows of the slot's adjacency that may hold entries
     int32_t n_amb;         // components crossing their own antipodal line
     int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
-    int32_t pad[3];
+    int32_t E2_acc;        // sum of now row lengths (2E)
+    int32_t excl_acc;      // now points dropped by the isomorphism
+    // outputs of the comparison with the past
+    int32_t status;        // 0 accepted, else DV_ERR_CAPACITY
+    int32_t n_flips;
+    int32_t n_break;
+    int32_t n_excl_past;
+    int32_t n_excl_now;
+    int32_t global_trigger;
+    int32_t K_past;        // K of the past frame it was compared with (0: none)
+    int32_t E_now;         // undirected couples of the frame
+    int32_t pad;
 };
 
-// Sequence header (device memory), touched only by the comparison chain.  Two
-// past buffers alternate: buffer `sel` holds the last accepted frame; the
-// comparison of a frame copies its components into buffer 1 - sel, which
-// becomes the past when the frame is accepted.
+// Sequence header (device memory).  Two past buffers alternate: buffer `sel`
+// holds the last accepted frame before the batch in flight; the batch's last
+// accepted frame is copied into buffer 1 - sel, and the commit flips `sel`.
 struct SeqState {
     int32_t sel;
     int32_t past_valid;
     int32_t K[2];          // components held by each past buffer
     int32_t E[2];          // undirected couples held by each past buffer
-    int32_t E2_acc;        // sum of now row lengths (2E), zeroed by the commit
-    int32_t excl_acc;      // now points dropped, zeroed by the commit
-    // outputs of the most recent frame
-    int32_t status;        // 0 accepted, else DV_ERR_CAPACITY
-    int32_t K_now;
-    int32_t n_flips;
-    int32_t n_break;
-    int32_t n_excl_past;
-    int32_t n_excl_now;
-    int32_t n_amb;
-    int32_t global_trigger;
-    int32_t K_past_cmp;    // K of the past frame used by the comparison
+    int32_t done_place;    // blocks of k_place that have finished (last one commits)
     int32_t pad;
     int64_t frame;         // accepted frames
 };
@@ -60,9 +62,10 @@ struct CompBuf {
     int32_t *adj;          // rows [K_max][max_degree]: unordered sets, DV_EMPTY padded
 };
 
-// Everything a kernel may touch: the buffers of one pipeline slot (one frame
-// in flight) and those of the comparison chain shared by all slots.  Passed
-// by value.
+// Everything a kernel may touch: the buffers of one batch slot (one frame)
+// and the past buffers shared by all slots.  The table of all slots lives in
+// device memory; a kernel takes its frame's entry (blockIdx.z) and, for the
+// comparison, the entry of the frame before it.
 struct Bufs {
     int32_t lx, ly, ntx, nty;
     float thr;
@@ -70,7 +73,7 @@ struct Bufs {
     int32_t kmax, maxdeg;
     int32_t ncells;        // bucket grid = tile grid
     int32_t keep_maps;     // write the label / owner maps
-    const float *field;
+    int32_t pad;
     int32_t *parent;       // [N] union-find over tile-border sites and piece roots
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
@@ -83,7 +86,7 @@ struct Bufs {
     // component accumulation (self-cleaning: finalize zeroes what it reads)
     long long *acc_x, *acc_y;
     int32_t *acc_n, *acc_amb, *acc_root;
-    // bucket grid of the now centres
+    // bucket grid of the frame's centres
     int32_t *cell_count;   // [ncells]
     int32_t *cell_start;   // [ncells + 1]
     int32_t *cell_items;   // [K_max] labels ordered by cell
@@ -93,16 +96,30 @@ struct Bufs {
     int32_t *inv;          // [K_max] now -> past (valid when cnt == 1)
     CompBuf cur;           // components and rows of the frame
     FrameState *fs;
-    // comparison chain (shared by the slots)
+    // comparison with the past
     int32_t *phi;          // [K_max] past -> now
     int32_t *trigger;      // [K_max] local trigger per kept past label
     int32_t *nb, *na;      // [K_max] breaking / arising count per now row
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
     int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
     int32_t *flips;        // [K_max * max_degree][6]
-    CompBuf past[2];
-    SeqState *st;
+    CompBuf past[2];       // shared by the slots
+    SeqState *st;          // shared by the slots
 };
+
+// Field pointers of the frames of one batch.
+struct Fields {
+    const float *p[DV_MAX_BATCH];
+};
+
+// Past of frame i of a batch (i = 0 .. n-1): the last earlier frame of the
+// batch whose stage errors are clear, else the shared past buffer.  Returns
+// the slot index, or -1 for the shared buffer.
+__device__ __forceinline__ int past_slot(const Bufs *D, int i) {
+    for (int j = i - 1; j >= 0; --j)
+        if (D[j].fs->err == 0) return j;
+    return -1;
+}
 
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
@@ -126,13 +143,15 @@ struct Prof {
     }
 };
 
-// launchers (k_label.hip)
-void launch_label(const Bufs &B, hipStream_t s, Prof &P);
-// launchers (k_voronoi.hip)
-void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P);
-// launchers (k_diff.hip): the comparison chain of a frame
-void launch_chain(const Bufs &B, hipStream_t s, Prof &P);
-// inspection helpers (k_diff.hip)
-void launch_phi_out(const Bufs &B, int32_t *d_out, hipStream_t s);
-void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,
-                      hipStream_t s);
+// Launchers.  H: host copy of a slot entry (sizes); D: device table of the
+// slot entries; n: frames in the batch (slots 0 .. n-1).
+// k_label.hip
+void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStream_t s, Prof &P);
+// k_voronoi.hip
+void launch_voronoi(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P);
+// k_diff.hip: comparison of every frame of the batch with its past, commit
+void launch_compare(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P);
+// inspection helpers (k_diff.hip); slot: the most recent frame
+void launch_phi_out(const Bufs &H, const Bufs *D, int slot, int32_t *d_out, hipStream_t s);
+void launch_edge_list(const Bufs &H, const Bufs *D, int32_t *d_out_ab, int32_t *d_count,
+                      int32_t *d_scratch, hipStream_t s);

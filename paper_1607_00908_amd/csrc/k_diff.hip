@@ -1,43 +1,67 @@
-// Comparison chain of a frame with the last accepted one (Sec. 3.2.3 and
-// 3.2.4).  It runs in frame order; everything before it (labelling, centres,
-// colouring) only touches the frame's own pipeline slot, so consecutive
-// frames overlap up to here.
+// Comparison of every frame of a batch with its past (Sec. 3.2.3 and 3.2.4),
+// one launch per step for the whole batch (frame = blockIdx.z).  The past of
+// a frame is the last earlier frame of the batch that passed its stage checks
+// (known on the device from the frame headers), else the shared past buffer,
+// so the comparisons of a batch are independent of each other.
 //
 //   k_match   Phi(p) = nearest now centre of every past centre p, one wave
-//             per point through the now bucket grid, exact, ties to the
+//             per point through the frame's bucket grid, exact, ties to the
 //             lowest label; preimage counts of the now points.
-//   k_diff    one wave per now label n: copies the components and row of n
-//             into the spare past buffer (the past of the next frame once
-//             this one is accepted); when n has exactly one preimage p, lane
-//             j holds slot j of the now row of n and slot j of the past row of
-//             p translated through Phi (kept entries only).  Rows are sets, so
-//             membership is tested with wave shuffles.  A couple of T(p)
-//             missing from R(n) is breaking, one of R(n) missing from T(p) is
-//             arising; each is reported once, from the row of its smaller now
-//             label, and staged in increasing order of the other end.  The
-//             local trigger of p is set when the two rows differ.
-//   k_place   (one block) scans the per-row counts, places the staged flips in
-//             canonical order (breaking first, then arising, each by (a, b))
-//             and commits: the spare past buffer becomes the past when the
-//             frame was accepted.  Kept past and now points correspond one to
+//   k_diff    one wave per now label n.  The batch's last accepted frame
+//             copies its components and rows into the spare past buffer (the
+//             past of the next batch).  When n has exactly one preimage p,
+//             lane j holds slot j of the now row of n and slot j of the past
+//             row of p translated through Phi (kept entries only).  Rows are
+//             sets, so membership is tested with wave shuffles.  A couple of
+//             T(p) missing from R(n) is breaking, one of R(n) missing from
+//             T(p) is arising; each is reported once, from the row of its
+//             smaller now label, and staged in increasing order of the other
+//             end.  The local trigger of p is set when the two rows differ.
+//   k_place   one block per frame: scans the per-row counts and places the
+//             staged flips in canonical order (breaking first, then arising,
+//             each by (a, b)).  Kept past and now points correspond one to
 //             one, so the number of dropped past points is
-//             K_past - (K_now - dropped now points).
+//             K_past - (K_now - dropped now points).  The last block to
+//             finish commits the batch: the spare past buffer becomes the
+//             past when any frame of the batch was accepted.
 #include "dv_device.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_match(Bufs B) {
-    const SeqState *st = B.st;
-    const FrameState *fs = B.fs;
-    if (fs->err || !st->past_valid) return;
-    const int past = st->sel;
-    const int KP = st->K[past], KN = fs->K_now;
-    const CompBuf P = B.past[past];
+// past components of frame i: slot j's frame, or the shared buffer
+struct PastOf {
+    CompBuf C;
+    int K;
+    bool valid;
+};
+
+__device__ __forceinline__ PastOf past_of(const Bufs *D, int i) {
+    PastOf r;
+    const int j = past_slot(D, i);
+    if (j >= 0) {
+        r.C = D[j].cur;
+        r.K = D[j].fs->K_now;
+        r.valid = true;
+    } else {
+        const SeqState *st = D[i].st;
+        r.C = D[i].past[st->sel];
+        r.K = st->past_valid ? st->K[st->sel] : 0;
+        r.valid = st->past_valid != 0;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
+    if (B.fs->err) return;
+    const PastOf P = past_of(D, blockIdx.z);
+    if (!P.valid) return;
+    const int KP = P.K, KN = B.fs->K_now;
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     for (int p = blockIdx.x * nw + (threadIdx.x >> 6); p < KP; p += gridDim.x * nw) {
         int n = -1;
-        if (KN > 0) n = wave_nearest(B, P.qx[p], P.qy[p]);
+        if (KN > 0) n = wave_nearest(B, P.C.qx[p], P.C.qy[p]);
         if (lane == 0) {
             B.phi[p] = n;
             if (n >= 0) {
@@ -48,31 +72,38 @@ __global__ __launch_bounds__(256) void k_match(Bufs B) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_diff(Bufs B) {
+__global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int nb_frames) {
     __shared__ int s_red[2][4];
-    SeqState *st = B.st;
-    if (B.fs->err) return;
+    const int i = blockIdx.z;
+    const Bufs &B = Dt[i];
+    FrameState *fs = B.fs;
+    if (fs->err) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int KN = B.fs->K_now;
-    const int past = st->sel;
-    const bool pv = st->past_valid != 0;
-    const CompBuf P = B.past[past], N = B.cur, Q = B.past[1 - past];
+    const int KN = fs->K_now;
+    const PastOf PO = past_of(Dt, i);
+    const bool pv = PO.valid;
+    const CompBuf P = PO.C, N = B.cur, Q = B.past[1 - B.st->sel];
+    // the batch's last accepted frame leaves its copy for the next batch
+    bool keep = true;
+    for (int q = i + 1; q < nb_frames; ++q)
+        if (Dt[q].fs->err == 0) keep = false;
     const int D = B.maxdeg;
     int e2 = 0, exn = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
     for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
         const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
-        // copy of component n for the next comparison
-        if (lane < D) Q.adj[(size_t)n * D + lane] = m;
-        switch (lane) {
-            case 0: Q.qx[n] = N.qx[n]; break;
-            case 1: Q.qy[n] = N.qy[n]; break;
-            case 2: Q.fx[n] = N.fx[n]; break;
-            case 3: Q.fy[n] = N.fy[n]; break;
-            case 4: Q.n[n] = N.n[n]; break;
-            case 5: Q.root[n] = N.root[n]; break;
-            case 6: Q.amb[n] = N.amb[n]; break;
-            default: break;
+        if (keep) {
+            if (lane < D) Q.adj[(size_t)n * D + lane] = m;
+            switch (lane) {
+                case 0: Q.qx[n] = N.qx[n]; break;
+                case 1: Q.qy[n] = N.qy[n]; break;
+                case 2: Q.fx[n] = N.fx[n]; break;
+                case 3: Q.fy[n] = N.fy[n]; break;
+                case 4: Q.n[n] = N.n[n]; break;
+                case 5: Q.root[n] = N.root[n]; break;
+                case 6: Q.amb[n] = N.amb[n]; break;
+                default: break;
+            }
         }
         const int cn = B.cnt[n];
         const int p = B.inv[n];
@@ -136,83 +167,97 @@ __global__ __launch_bounds__(256) void k_diff(Bufs B) {
             a += s_red[0][w];
             b += s_red[1][w];
         }
-        if (a) atomicAdd(&st->E2_acc, a);
-        if (b) atomicAdd(&st->excl_acc, b);
+        if (a) atomicAdd(&fs->E2_acc, a);
+        if (b) atomicAdd(&fs->excl_acc, b);
     }
 }
 
-__global__ __launch_bounds__(1024) void k_place(Bufs B) {
+__global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, int nb_frames) {
     __shared__ int wsum[16];
+    __shared__ int s_last;
+    const int i = blockIdx.z;
+    const Bufs &B = Dt[i];
+    FrameState *fs = B.fs;
     SeqState *st = B.st;
-    const FrameState *fs = B.fs;
     const int t = threadIdx.x;
     if (fs->err) {
         if (t == 0) {
-            st->status = 2;   // DV_ERR_CAPACITY; the past is kept
-            st->K_now = fs->K_now;
-            st->n_amb = fs->n_amb;
-            st->n_flips = 0;
-            st->n_break = 0;
-            st->n_excl_past = 0;
-            st->n_excl_now = 0;
-            st->global_trigger = 0;
-            st->E2_acc = 0;
-            st->excl_acc = 0;
+            fs->status = 2;   // DV_ERR_CAPACITY; the frame is not a past
+            fs->n_flips = 0;
+            fs->n_break = 0;
+            fs->n_excl_past = 0;
+            fs->n_excl_now = 0;
+            fs->global_trigger = 0;
+            fs->K_past = 0;
+            fs->E_now = 0;
         }
-        return;
+    } else {
+        const int KN = fs->K_now;
+        const PastOf PO = past_of(Dt, i);
+        const int D = B.maxdeg;
+        const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
+        __syncthreads();
+        const int nar = block_exclusive_scan(B.na, B.oa, KN, wsum);
+        __syncthreads();
+        for (int n = t; n < KN; n += blockDim.x) {
+            const int cb = B.nb[n], ca = B.na[n];
+            if (cb == 0 && ca == 0) continue;
+            const int *stg = B.stage + (size_t)n * (2 * D) * 6;
+            int *fb = B.flips + (size_t)6 * B.ob[n];
+            for (int j = 0; j < 6 * cb; ++j) fb[j] = stg[j];
+            int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
+            for (int j = 0; j < 6 * ca; ++j) fa[j] = stg[6 * D + j];
+        }
+        if (t == 0) {
+            const int KP = PO.valid ? PO.K : 0;
+            const int excl = fs->excl_acc;
+            fs->status = 0;
+            fs->K_past = KP;
+            fs->E_now = fs->E2_acc / 2;
+            fs->n_excl_now = excl;
+            fs->n_excl_past = PO.valid ? KP - (KN - excl) : 0;
+            fs->n_break = nbk;
+            fs->n_flips = nbk + nar;
+            fs->global_trigger = (nbk + nar) > 0 ? 1 : 0;
+        }
     }
-    const int KN = fs->K_now;
-    const int past = st->sel, now = 1 - past;
-    const bool pv = st->past_valid != 0;
-    const int D = B.maxdeg;
-    const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
-    __syncthreads();
-    const int nar = block_exclusive_scan(B.na, B.oa, KN, wsum);
-    __syncthreads();
-    for (int n = t; n < KN; n += blockDim.x) {
-        const int cb = B.nb[n], ca = B.na[n];
-        if (cb == 0 && ca == 0) continue;
-        const int *stg = B.stage + (size_t)n * (2 * D) * 6;
-        int *fb = B.flips + (size_t)6 * B.ob[n];
-        for (int j = 0; j < 6 * cb; ++j) fb[j] = stg[j];
-        int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
-        for (int j = 0; j < 6 * ca; ++j) fa[j] = stg[6 * D + j];
-    }
+    // the last block to finish commits the batch (every block has read the
+    // sequence header by now)
     __syncthreads();
     if (t == 0) {
-        const int KP = pv ? st->K[past] : 0;
-        const int excl = st->excl_acc;
-        st->K_now = KN;
-        st->n_amb = fs->n_amb;
-        st->n_excl_now = excl;
-        st->n_excl_past = pv ? KP - (KN - excl) : 0;
-        st->n_break = nbk;
-        st->n_flips = nbk + nar;
-        st->global_trigger = (nbk + nar) > 0 ? 1 : 0;
-        st->K_past_cmp = KP;
-        st->K[now] = KN;
-        st->E[now] = st->E2_acc / 2;
-        st->E2_acc = 0;
-        st->excl_acc = 0;
-        st->sel = now;
+        __threadfence();
+        s_last = atomicAdd(&st->done_place, 1) == nb_frames - 1;
+        if (s_last) __threadfence();
+    }
+    __syncthreads();
+    if (!s_last || t != 0) return;
+    st->done_place = 0;
+    int q = -1, acc = 0;
+    for (int k = 0; k < nb_frames; ++k)
+        if (Dt[k].fs->err == 0) { q = k; ++acc; }
+    if (q >= 0) {
+        const int nxt = 1 - st->sel;
+        st->K[nxt] = Dt[q].fs->K_now;
+        st->E[nxt] = Dt[q].fs->E2_acc / 2;
+        st->sel = nxt;
         st->past_valid = 1;
-        st->frame += 1;
-        st->status = 0;
+        st->frame += acc;
     }
 }
 
-// Phi of the last comparison with dropped past points as -1 (inspection).
-__global__ __launch_bounds__(256) void k_phi_out(Bufs B, int *out) {
-    const SeqState *st = B.st;
-    const int KP = st->K_past_cmp;
+// Phi of the most recent comparison with dropped past points as -1 (inspection).
+__global__ __launch_bounds__(256) void k_phi_out(const Bufs *__restrict__ D, int slot, int *out) {
+    const Bufs &B = D[slot];
+    const int KP = B.fs->K_past;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < KP; p += gridDim.x * blockDim.x) {
         const int n = B.phi[p];
         out[p] = (n >= 0 && B.cnt[n] == 1) ? n : -1;
     }
 }
 
-// ---- inspection: sorted couple list (a < b) of the current buffer ----------
-__global__ __launch_bounds__(256) void k_edge_count(Bufs B, int *cntv) {
+// ---- inspection: sorted couple list (a < b) of the past buffer -------------
+__global__ __launch_bounds__(256) void k_edge_count(const Bufs *__restrict__ D, int *cntv) {
+    const Bufs &B = D[0];
     const SeqState *st = B.st;
     const int cur = st->sel;
     const int K = st->K[cur];
@@ -225,15 +270,19 @@ __global__ __launch_bounds__(256) void k_edge_count(Bufs B, int *cntv) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_edge_scan(Bufs B, const int *cntv, int *offv, int *total) {
+__global__ __launch_bounds__(1024) void k_edge_scan(const Bufs *__restrict__ D, const int *cntv,
+                                                    int *offv, int *total) {
     __shared__ int wsum[16];
-    const int K = B.st->K[B.st->sel];
+    const SeqState *st = D[0].st;
+    const int K = st->K[st->sel];
     const int tot = block_exclusive_scan(cntv, offv, K, wsum);
     if (threadIdx.x == 0) *total = tot;
 }
 
 // entries above a, written in increasing order (rows are unordered sets)
-__global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int *ab) {
+__global__ __launch_bounds__(256) void k_edge_write(const Bufs *__restrict__ D, const int *offv,
+                                                     int *ab) {
+    const Bufs &B = D[0];
     const SeqState *st = B.st;
     const int cur = st->sel;
     const int K = st->K[cur];
@@ -255,29 +304,29 @@ __global__ __launch_bounds__(256) void k_edge_write(Bufs B, const int *offv, int
 
 }  // namespace
 
-void launch_chain(const Bufs &B, hipStream_t s, Prof &P) {
-    const int grid = (int)std::min<long long>((B.kmax + 3) / 4, 2048);
+void launch_compare(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P) {
+    const int grid = (int)std::min<long long>((H.kmax + 3) / 4, 2048);
     P.begin(ST_MATCH, s);
-    hipLaunchKernelGGL(k_match, dim3(grid), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(k_match, dim3(grid, 1, n), dim3(256), 0, s, D);
     P.end(ST_MATCH, s);
     P.begin(ST_DIFF, s);
-    hipLaunchKernelGGL(k_diff, dim3(grid), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(k_diff, dim3(grid, 1, n), dim3(256), 0, s, D, n);
     P.end(ST_DIFF, s);
     P.begin(ST_PLACE, s);
-    hipLaunchKernelGGL(k_place, dim3(1), dim3(1024), 0, s, B);
+    hipLaunchKernelGGL(k_place, dim3(1, 1, n), dim3(1024), 0, s, D, n);
     P.end(ST_PLACE, s);
 }
 
-void launch_phi_out(const Bufs &B, int32_t *d_out, hipStream_t s) {
-    const int grid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_phi_out, dim3(grid), dim3(256), 0, s, B, d_out);
+void launch_phi_out(const Bufs &H, const Bufs *D, int slot, int32_t *d_out, hipStream_t s) {
+    const int grid = (int)std::min<long long>((H.kmax + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_phi_out, dim3(grid), dim3(256), 0, s, D, slot, d_out);
 }
 
-void launch_edge_list(const Bufs &B, int32_t *d_out_ab, int32_t *d_count, int32_t *d_scratch,
-                      hipStream_t s) {
-    const int kgrid = (int)std::min<long long>((B.kmax + 255) / 256, 1024);
-    int *cntv = d_scratch, *offv = d_scratch + B.kmax;
-    hipLaunchKernelGGL(k_edge_count, dim3(kgrid), dim3(256), 0, s, B, cntv);
-    hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, s, B, (const int *)cntv, offv, d_count);
-    hipLaunchKernelGGL(k_edge_write, dim3(kgrid), dim3(256), 0, s, B, (const int *)offv, d_out_ab);
+void launch_edge_list(const Bufs &H, const Bufs *D, int32_t *d_out_ab, int32_t *d_count,
+                      int32_t *d_scratch, hipStream_t s) {
+    const int kgrid = (int)std::min<long long>((H.kmax + 255) / 256, 1024);
+    int *cntv = d_scratch, *offv = d_scratch + H.kmax;
+    hipLaunchKernelGGL(k_edge_count, dim3(kgrid), dim3(256), 0, s, D, cntv);
+    hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, s, D, (const int *)cntv, offv, d_count);
+    hipLaunchKernelGGL(k_edge_write, dim3(kgrid), dim3(256), 0, s, D, (const int *)offv, d_out_ab);
 }

@@ -132,14 +132,15 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 // responsibility column -- column x + 1 for every site, and additionally
 // columns a - 1 and a for the first site a of a run (8-connectivity), or
 // column x for every site (4-connectivity).
-__device__ void tile_ccl(const Bufs &B, int x0, int y0, int tw, int th, int *L, uint32_t *rowm) {
+__device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int tw, int th, int *L,
+                         uint32_t *rowm) {
     const int t = threadIdx.x, cx = t & 31, ry = t >> 5, lane = t & 63;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
         bool in = false;
         if (cx < tw && y < th)
-            in = is_in(B.field[(size_t)(y0 + y) * B.lx + x0 + cx], B.thr, B.phase);
+            in = is_in(field[(size_t)(y0 + y) * B.lx + x0 + cx], B.thr, B.phase);
         const unsigned long long bal = __ballot(in);
         const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (cx == 0) rowm[y] = m;
@@ -201,7 +202,8 @@ __device__ void tile_ccl(const Bufs &B, int x0, int y0, int tw, int th, int *L, 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
+__global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Fields F) {
+    const Bufs &B = D[blockIdx.z];
     __shared__ int L[DV_TILE_SITES];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ int npc;
@@ -216,6 +218,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
         fs->K_now = 0;
         fs->err = 0;
         fs->n_amb = 0;
+        fs->E2_acc = 0;
+        fs->excl_acc = 0;
     }
     if (t == 0) {
         B.cell_count[tile] = 0;
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
-    tile_ccl(B, x0, y0, tw, th, L, rowm);
+    tile_ccl(B, F.p[blockIdx.z], x0, y0, tw, th, L, rowm);
 
     const int cx = t & 31, ry = t >> 5;
 #pragma unroll
@@ -258,58 +262,85 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(Bufs B) {
 }
 
 // Unions between inside sites of neighbouring tiles (every tile-border site
-// holds its piece root in the parent array, or -1 when outside).  Thread j < 32 takes row
-// j of the tile's last column against the next column (periodic); thread
-// 32 + j takes column j of the last row against the next row.  Together they
-// cover every adjacent pair that crosses a tile border, including the
-// diagonal pairs at tile corners and the periodic seams.
-__global__ __launch_bounds__(64) void k_merge(Bufs B) {
+// holds an ancestor of its piece, at least its piece root, or -1 when
+// outside).  Thread j < 32 takes row j of the tile's last column against the
+// next column (periodic); thread 32 + j takes column j of the last row against
+// the next row.  Together they cover every adjacent pair that crosses a tile
+// border, including the diagonal pairs at tile corners and the periodic
+// seams.  Uniting two sites is uniting the values they hold, so the pairs of
+// held values are united, and a pair equal to one the previous thread of the
+// same line unites is skipped (two pieces usually touch along many sites).
+__device__ __forceinline__ void merge_line(int *P, int ps, const int pu[3], bool conn8, bool active,
+                                           int lane) {
+    // pairs of this thread: up to three (ps, pu[k])
+    int a[3], b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const bool use = active && ps >= 0 && pu[k] >= 0 && (conn8 || k == 1);
+        a[k] = use ? ps : -1;
+        b[k] = use ? pu[k] : -1;
+    }
+    // the previous thread's pairs (lanes 0 and 32 start a line)
+    int pa[3], pb[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pa[k] = __shfl_up(a[k], 1, 32);
+        pb[k] = __shfl_up(b[k], 1, 32);
+    }
+    const bool first = (lane & 31) == 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (a[k] < 0) continue;
+        bool dup = false;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            dup = dup || (!first && pa[q] == a[k] && pb[q] == b[k]);
+            if (q < k) dup = dup || (a[q] == a[k] && b[q] == b[k]);
+        }
+        if (!dup) gunite(P, a[k], b[k]);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_merge(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
     const int tx = blockIdx.x, ty = blockIdx.y;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int lx = B.lx, ly = B.ly;
-    int j = threadIdx.x;
-    if (j < 32) {
-        if (j >= th) return;
-        const int x = x0 + tw - 1, y = y0 + j;
-        const int s = y * lx + x;
-        const int xn = (x + 1 == lx) ? 0 : x + 1;
-        int u[3];
-        for (int k = 0; k < 3; ++k) {
-            int yn = y + k - 1;
-            yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
-            u[k] = yn * lx + xn;
-        }
-        // every border site holds its piece root, or -1 when outside
-        const int ps = B.parent[s];
-        const int pu0 = B.parent[u[0]], pu1 = B.parent[u[1]], pu2 = B.parent[u[2]];
-        if (ps < 0) return;
-        if (pu1 >= 0) gunite(B.parent, s, u[1]);
-        if (B.conn == 8) {
-            if (pu0 >= 0) gunite(B.parent, s, u[0]);
-            if (pu2 >= 0) gunite(B.parent, s, u[2]);
+    const int lane = threadIdx.x;
+    const int j = lane & 31;
+    int ps = -1, pu[3] = {-1, -1, -1};
+    bool active;
+    if (lane < 32) {
+        // row j of the last column against the next column
+        active = j < th;
+        if (active) {
+            const int x = x0 + tw - 1, y = y0 + j;
+            const int xn = (x + 1 == lx) ? 0 : x + 1;
+            ps = B.parent[y * lx + x];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int yn = y + k - 1;
+                yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
+                pu[k] = B.parent[yn * lx + xn];
+            }
         }
     } else {
-        j -= 32;
-        if (j >= tw) return;
-        const int x = x0 + j, y = y0 + th - 1;
-        const int s = y * lx + x;
-        const int yn = (y + 1 == ly) ? 0 : y + 1;
-        int u[3];
-        for (int k = 0; k < 3; ++k) {
-            int xn = x + k - 1;
-            xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
-            u[k] = yn * lx + xn;
-        }
-        const int ps = B.parent[s];
-        const int pu0 = B.parent[u[0]], pu1 = B.parent[u[1]], pu2 = B.parent[u[2]];
-        if (ps < 0) return;
-        if (pu1 >= 0) gunite(B.parent, s, u[1]);
-        if (B.conn == 8) {
-            if (pu0 >= 0) gunite(B.parent, s, u[0]);
-            if (pu2 >= 0) gunite(B.parent, s, u[2]);
+        // column j of the last row against the next row
+        active = j < tw;
+        if (active) {
+            const int x = x0 + j, y = y0 + th - 1;
+            const int yn = (y + 1 == ly) ? 0 : y + 1;
+            ps = B.parent[y * lx + x];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int xn = x + k - 1;
+                xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
+                pu[k] = B.parent[yn * lx + xn];
+            }
         }
     }
+    merge_line(B.parent, ps, pu, B.conn == 8, active, lane);
 }
 
 // One block per band of 32 rows: every piece of the band's tiles finds its
@@ -319,7 +350,8 @@ __global__ __launch_bounds__(64) void k_merge(Bufs B) {
 // before each segment within the band, band_sum the band's total.
 // Segment (y, tile column c) covers sites y*lx + 32c .. 32c+31, so raster
 // order of segments is the row-major order of the [ly][ntx] arrays.
-__global__ __launch_bounds__(1024) void k_resolve(Bufs B) {
+__global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
     __shared__ int pre[RES_TILES + 1];
     __shared__ int wsum[16];
     const int ty = blockIdx.x, t = threadIdx.x;
@@ -380,7 +412,8 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
     return v;
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
+__global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
     __shared__ int L[DV_TILE_SITES];
     __shared__ int prank[DV_TILE_SITES];
     __shared__ int prx[DV_TILE_SITES], pry[DV_TILE_SITES];
@@ -439,19 +472,20 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
     __syncthreads();
 
     const int hix = lx - 1 - (lx >> 1), hiy = ly - 1 - (ly >> 1);
+    const int lane = t & 63;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
-        if (cx >= tw || y >= th) continue;
         const int r = L[s];
+        const bool inside = r >= 0;
+        const unsigned long long bal = __ballot(inside);
+        const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
+        if (cx >= tw || y >= th) continue;
         const size_t g = (size_t)(y0 + y) * lx + x0 + cx;
-        if (B.keep_maps) B.labels[g] = r >= 0 ? prank[r] : -1;
-        if (r < 0) continue;
+        if (B.keep_maps) B.labels[g] = inside ? prank[r] : -1;
+        if (!inside) continue;
         const int dx = wrap_off(x0 + cx - prx[r], lx);
         const int dy = wrap_off(y0 + y - pry[r], ly);
-        atomicAdd(&psx[r], dx);
-        atomicAdd(&psy[r], dy);
-        atomicAdd(&pn[r], 1);
         // an adjacent inside site is a member; crossing the antipodal line of
         // the root makes the unwrapped coordinates jump by L - 1.  Sites on
         // that line are rare: their neighbours are read from the global map.
@@ -460,17 +494,31 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
             const int gx = x0 + cx, gy = y0 + y;
             const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
             const int yp = gy + 1 == ly ? 0 : gy + 1, ym = gy == 0 ? ly - 1 : gy - 1;
-            auto inside = [&](int xx, int yy) { return B.lab16[(size_t)yy * lx + xx] != 0xffff; };
+            auto inside_at = [&](int xx, int yy) { return B.lab16[(size_t)yy * lx + xx] != 0xffff; };
             if (dx == hix) {
-                amb = inside(xp, gy);
-                if (B.conn == 8) amb = amb || inside(xp, ym) || inside(xp, yp);
+                amb = inside_at(xp, gy);
+                if (B.conn == 8) amb = amb || inside_at(xp, ym) || inside_at(xp, yp);
             }
             if (dy == hiy) {
-                amb = amb || inside(gx, yp);
-                if (B.conn == 8) amb = amb || inside(xm, yp) || inside(xp, yp);
+                amb = amb || inside_at(gx, yp);
+                if (B.conn == 8) amb = amb || inside_at(xm, yp) || inside_at(xp, yp);
             }
         }
         if (amb && prank[r] < B.kmax) atomicOr(&B.acc_amb[prank[r]], 1);
+        // the first site of each horizontal run adds the whole run (one piece)
+        if (cx > 0 && ((m >> (cx - 1)) & 1u)) continue;
+        const int len = __builtin_ctzll(~(unsigned long long)(m >> cx));   // a full row is 32
+        const int dx_end = wrap_off(x0 + cx + len - 1 - prx[r], lx);
+        int sxr;
+        if (dx_end - dx == len - 1) {
+            sxr = (dx + dx_end) * len / 2;     // no wrap inside the run
+        } else {
+            sxr = 0;
+            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx[r], lx);
+        }
+        atomicAdd(&psx[r], sxr);
+        atomicAdd(&psy[r], dy * len);
+        atomicAdd(&pn[r], len);
     }
     __syncthreads();
 #pragma unroll
@@ -487,18 +535,18 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(Bufs B) {
 
 }  // namespace
 
-void launch_label(const Bufs &B, hipStream_t s, Prof &P) {
-    const dim3 tiles(B.ntx, B.nty);
+void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStream_t s, Prof &P) {
+    const dim3 tiles(H.ntx, H.nty, n);
     P.begin(ST_TILE_CCL, s);
-    hipLaunchKernelGGL(k_tile_ccl, tiles, dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_tile_ccl, tiles, dim3(DV_BLOCK), 0, s, D, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
-    hipLaunchKernelGGL(k_merge, tiles, dim3(64), 0, s, B);
+    hipLaunchKernelGGL(k_merge, tiles, dim3(64), 0, s, D);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
-    hipLaunchKernelGGL(k_resolve, dim3(B.nty), dim3(1024), 0, s, B);
+    hipLaunchKernelGGL(k_resolve, dim3(H.nty, 1, n), dim3(1024), 0, s, D);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), 0, s, D);
     P.end(ST_RELABEL, s);
 }

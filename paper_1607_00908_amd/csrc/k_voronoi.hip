@@ -25,7 +25,8 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
     return r < 0 ? r + m : r;
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(Bufs B) {
+__global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
     __shared__ int wsum[16];
     __shared__ int s_last;
     FrameState *fs = B.fs;
@@ -128,15 +129,17 @@ __device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, FrameSta
 #define WSITES 5      // ceil(34*34 / 256) window sites per thread
 #define RCAP 256      // item ranges held in LDS per batch
 #define IMG_MAX 9     // periodic images one centre can contribute (tiny lattices)
-#define CAND_BATCH 32 // centres appended per batch (room for IMG_MAX images each)
+#define CAND_BATCH 16 // centres appended per batch (room for IMG_MAX images each)
 
 // Shared state of one colouring tile.
 struct OwnerLds {
     int own[34 * 34];
-    // candidate centres: tile-relative Q.8 image positions, |c|^2, label
+    // candidate centres as appended: tile-relative Q.8 image positions, label
     int cx[DV_CAND_CAP], cy[DV_CAND_CAP];
-    double ck[DV_CAND_CAP];
     int lab[DV_CAND_CAP];
+    // the same, ordered by label for evaluation: x, y, |c|^2 as doubles
+    double sx[DV_CAND_CAP], sy[DV_CAND_CAP], sk[DV_CAND_CAP];
+    int sl[DV_CAND_CAP];
     int ncand;
     int nchunks;   // times the list was evaluated and emptied before the end
     // item ranges of the cell rectangle being visited
@@ -217,7 +220,8 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
     }
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
+__global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
     __shared__ OwnerLds S;
     FrameState *fs = B.fs;
     if (fs->err) return;
@@ -250,15 +254,47 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
     const int tcx = OX + 128 * (tw - 1), tcy = OY + 128 * (th - 1);
     const int wxlo = -256, wxhi = 256 * tw, wylo = -256, wyhi = 256 * th;
 
+    // Nearest candidate of every window site.  The chunk is first ordered by
+    // label, so that within it a strict comparison already sends ties to the
+    // lowest label; a later chunk (after an overflow) also compares labels.
     auto eval_owners = [&]() {
-        const int nc = S.ncand;
-        for (int c = 0; c < nc; ++c) {
-            const double cx = (double)S.cx[c], cy = (double)S.cy[c], kk = S.ck[c];
+        __syncthreads();
+        const int nc = min(S.ncand, DV_CAND_CAP);
+        for (int c = t; c < nc; c += DV_BLOCK) {
             const int lab = S.lab[c];
+            int r = 0;
+            for (int j = 0; j < nc; ++j) {
+                const int l2 = S.lab[j];
+                r += (l2 < lab || (l2 == lab && j < c)) ? 1 : 0;
+            }
+            const double x = (double)S.cx[c], y = (double)S.cy[c];
+            S.sx[r] = x;
+            S.sy[r] = y;
+            S.sk[r] = x * x + y * y;
+            S.sl[r] = lab;
+        }
+        __syncthreads();
+        if (S.nchunks == 0) {
+            for (int c = 0; c < nc; ++c) {
+                const double cx = S.sx[c], cy = S.sy[c], kk = S.sk[c];
+                const int lab = S.sl[c];
 #pragma unroll
-            for (int i = 0; i < WSITES; ++i) {
-                const double e = fma(m2x[i], cx, fma(m2y[i], cy, kk));
-                if (e < be[i] || (e == be[i] && lab < bl[i])) { be[i] = e; bl[i] = lab; }
+                for (int i = 0; i < WSITES; ++i) {
+                    const double e = fma(m2x[i], cx, fma(m2y[i], cy, kk));
+                    const bool lt = e < be[i];
+                    be[i] = lt ? e : be[i];
+                    bl[i] = lt ? lab : bl[i];
+                }
+            }
+        } else {
+            for (int c = 0; c < nc; ++c) {
+                const double cx = S.sx[c], cy = S.sy[c], kk = S.sk[c];
+                const int lab = S.sl[c];
+#pragma unroll
+                for (int i = 0; i < WSITES; ++i) {
+                    const double e = fma(m2x[i], cx, fma(m2y[i], cy, kk));
+                    if (e < be[i] || (e == be[i] && lab < bl[i])) { be[i] = e; bl[i] = lab; }
+                }
             }
         }
     };
@@ -279,7 +315,6 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
                 if (slot >= DV_CAND_CAP) continue;   // overflow: caller falls back
                 S.cx[slot] = cx;
                 S.cy[slot] = cy;
-                S.ck[slot] = (double)cx * cx + (double)cy * cy;
                 S.lab[slot] = lab;
             }
     };
@@ -449,10 +484,12 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
                     const double qx = -2.0 * (256.0 * qsx + inx(r)), qy = -2.0 * (256.0 * qsy + iny(r));
                     double bee = 1.0e300;
                     m = DV_EMPTY;
+                    // the single chunk is ordered by label: ties keep the first
                     for (int k = 0; k < ncl; ++k) {
-                        const double e = fma(qx, (double)S.cx[k], fma(qy, (double)S.cy[k], S.ck[k]));
-                        const int lab = S.lab[k];
-                        if (e < bee || (e == bee && lab < m)) { bee = e; m = lab; }
+                        const double e = fma(qx, S.sx[k], fma(qy, S.sy[k], S.sk[k]));
+                        const bool lt = e < bee;
+                        bee = lt ? e : bee;
+                        m = lt ? S.sl[k] : m;
                     }
                 } else {
                     int X = OX + 256 * qsx + inx(r), Y = OY + 256 * qsy + iny(r);
@@ -485,12 +522,12 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(Bufs B) {
 
 }  // namespace
 
-void launch_voronoi(const Bufs &B, hipStream_t s, Prof &P) {
-    const int fgrid = (int)std::min<long long>((B.kmax + 1023) / 1024, 256);
+void launch_voronoi(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P) {
+    const int fgrid = (int)std::min<long long>((H.kmax + 1023) / 1024, 256);
     P.begin(ST_FINALIZE, s);
-    hipLaunchKernelGGL(k_finalize, dim3(fgrid), dim3(1024), 0, s, B);
+    hipLaunchKernelGGL(k_finalize, dim3(fgrid, 1, n), dim3(1024), 0, s, D);
     P.end(ST_FINALIZE, s);
     P.begin(ST_OWNER_EDGES, s);
-    hipLaunchKernelGGL(k_owner_edges, dim3(B.ncells), dim3(DV_BLOCK), 0, s, B);
+    hipLaunchKernelGGL(k_owner_edges, dim3(H.ncells, 1, n), dim3(DV_BLOCK), 0, s, D);
     P.end(ST_OWNER_EDGES, s);
 }

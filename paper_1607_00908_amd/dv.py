@@ -30,7 +30,7 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
            "dv_status_str", "dv_last_error")
 
-DEFAULT_PIPELINE_DEPTH = 3   # what pipeline_depth = 0 selects
+DEFAULT_BATCH = 4   # what max_batch = 0 selects
 
 STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "match",
           "diff", "place")
@@ -41,7 +41,7 @@ class DVConfig(ctypes.Structure):
                 ("threshold", ctypes.c_float), ("phase", ctypes.c_int32),
                 ("connectivity", ctypes.c_int32), ("max_components", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("pipeline_depth", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("max_batch", ctypes.c_int32)]
 
 
 class DVFlip(ctypes.Structure):
@@ -137,18 +137,18 @@ class Detector:
     creates one.  Before each push that stream waits (on the device, without
     a host synchronisation) for the caller's current stream, and the frame's
     kernels start after it, so a field produced there is complete when they
-    read it.  ``pipeline_depth``: frames in flight on the device (0: the
-    library's default).
+    read it.  ``max_batch``: frames queued and sent to the device together
+    (0: the library's default).
     """
 
     def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
-                 device: int = 0, keep_maps: bool = True, stream=None, pipeline_depth: int = 0):
+                 device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
         cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
                        int(connectivity), int(max_components), int(max_degree), int(device),
-                       KEEP_MAPS if keep_maps else 0, int(pipeline_depth))
+                       KEEP_MAPS if keep_maps else 0, int(max_batch))
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))

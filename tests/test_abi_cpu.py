@@ -36,11 +36,11 @@ def test_struct_sizes_match_header_layout():
 
 def _cfg(**kw):
     base = dict(lx=64, ly=64, threshold=0.5, phase=0, connectivity=8, max_components=100,
-                max_degree=0, device=0, flags=1, pipeline_depth=0)
+                max_degree=0, device=0, flags=1, max_batch=0)
     base.update(kw)
     c = dv.DVConfig(ctypes.sizeof(dv.DVConfig), base["lx"], base["ly"], base["threshold"],
                     base["phase"], base["connectivity"], base["max_components"],
-                    base["max_degree"], base["device"], base["flags"], base["pipeline_depth"])
+                    base["max_degree"], base["device"], base["flags"], base["max_batch"])
     return c
 
 
@@ -48,7 +48,7 @@ def _cfg(**kw):
     dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
     dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
     dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=2),
-    dict(pipeline_depth=-1), dict(pipeline_depth=5)])
+    dict(max_batch=-1), dict(max_batch=9)])
 def test_invalid_config_is_rejected_on_the_host(bad):
     lib = dv.load()
     h = ctypes.c_void_p()

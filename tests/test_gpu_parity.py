@@ -181,35 +181,36 @@ def test_capacity_rejection_keeps_the_past():
     det.close()
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 4])
-def test_pipelined_bursts_match_the_oracle(depth):
-    """Frames pushed back to back with no synchronisation in between overlap on
-    the device; the state after each burst (flips against the previous frame,
-    labels, couples, matching) must equal the oracle's."""
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 8])
+def test_batched_bursts_match_the_oracle(depth):
+    """Frames pushed back to back with no synchronisation in between go to the
+    device in batches (each stage one launch over the batch, the comparisons
+    of a batch in parallel); the state after each burst (flips against the
+    previous frame, labels, couples, matching) must equal the oracle's."""
     lx, ly = 200, 160
     sim = synth.DiskSim(lx, ly, 30, 4.0, 7.0, 0.6, 3e-3, seed=91 + depth)
     frames = list(sim.frames(11))
     dev = [torch.from_numpy(f).cuda() for f in frames]
-    det = dv.Detector(lx, ly, 0.5, max_components=256, pipeline_depth=depth)
+    det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=depth)
     seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
     for k, f in enumerate(frames):
         now, ref = seq.push(f)
         det.push(dev[k])
         if k in (0, 4, 10):
-            say(f"  [pipe{depth}] burst ends at frame {k}")
+            say(f"  [batch{depth}] burst ends at frame {k}")
             check_frame(det, now, ref, lx, ly)
     assert det.info().frame == len(frames)
     det.close()
 
 
-def test_rejection_inside_a_pipelined_burst():
-    """A rejected frame in the middle of a burst: the frame after it is compared
-    with the last accepted one."""
+def test_rejection_inside_a_batch():
+    """A rejected frame in the middle of a batch: the frame after it is compared
+    with the last accepted one, inside the same batch and across batches."""
     sim = synth.DiskSim(120, 100, 12, 4.0, 6.0, 0.8, 2e-3, seed=78)
     a, b, c, d = list(sim.frames(4))
     noise = (synth.tiny_random_field(120, 100, 5) > 0.85).astype(np.float32)
     dev = [torch.from_numpy(x).cuda() for x in (a, b, noise, c)]
-    det = dv.Detector(120, 100, 0.5, max_components=64, pipeline_depth=3)
+    det = dv.Detector(120, 100, 0.5, max_components=64, max_batch=3)
     for x in dev:
         det.push(x)
     got = det.flips()
@@ -261,10 +262,9 @@ def test_disks1024_frames():
     run_sequence(list(sim.frames(6)), spec["threshold"], kmax=4096, tag="disks1024")
 
 
-def test_disks1024_pipelined_burst():
+def test_disks1024_batched_burst():
     """Twenty full-size frames pushed back to back in the benchmark's launch
-    configuration (default pipeline depth); the last comparison against the
-    oracle."""
+    configuration (default batch); the last comparison against the oracle."""
     sim, spec = synth.workload("disks1024")
     frames = list(sim.frames(20))
     dev = torch.from_numpy(np.stack(frames)).cuda()
