@@ -147,6 +147,25 @@ def counters_from(fetch_csv: str, write_csv: str, stage: str, workload: str, map
     print(json.dumps({"stage": stage, "bytes_per_dispatch": round(bytes_per), **res}))
 
 
+def unbatched_rate(dv, args, spec, lx, ly, kmax, maps, stream, ptrs, F, N):
+    """The same pushes with one frame per launch of each stage."""
+    det1 = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
+                       keep_maps=maps, max_batch=1, stream=stream)
+    for i in range(args.warmup):
+        det1.push(ptrs[i % F])
+    det1.sync()
+    n1 = min(args.steps, 500)
+    t1 = time.perf_counter()
+    for i in range(n1):
+        det1.push(ptrs[(args.warmup + i) % F])
+    det1.sync()
+    el1 = time.perf_counter() - t1
+    det1.close()
+    log(f"max_batch 1: {1e6 * el1 / n1:.1f} us/frame")
+    return {"max_batch": 1, "value": round(N * n1 / el1 / 1e6, 2), "unit": "Msites/s",
+            "ms_per_step": round(1e3 * el1 / n1, 5), "steps": n1}
+
+
 def make_frames(workload: str, frames: int | None):
     from paper_1607_00908_amd import synth
     sim, spec = synth.workload(workload)
@@ -177,8 +196,8 @@ def cpu_baseline(frames, spec, seconds: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1600)
+    ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--workload", default="disks1024")
     ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
     ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
@@ -188,6 +207,8 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-unbatched", action="store_true",
+                    help="skip the one-frame-per-launch comparison run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run the counter calibration copy of this size first")
     ap.add_argument("--counters-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -251,6 +272,11 @@ def main():
     msites = N * args.steps / elapsed / 1e6
     log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/frame, {msites:.0f} Msites/s")
 
+    # the same frames with one frame per launch (no batching), for comparison
+    unbatched = None
+    if not args.no_unbatched:
+        unbatched = unbatched_rate(dv, args, spec, lx, ly, kmax, maps, det.stream, ptrs, F, N)
+
     # latency: push -> flips returned, host-synchronous
     lat = []
     for i in range(args.latency_frames):
@@ -298,6 +324,7 @@ def main():
                         "p99": round(float(np.percentile(lat, 99)), 4),
                         "samples": len(lat)} if len(lat) else None),
         "roofline": roofline,
+        "unbatched": unbatched,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

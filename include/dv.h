@@ -81,8 +81,8 @@ typedef struct {
                                 4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
     uint32_t flags;          /* DV_KEEP_MAPS                                       */
-    int32_t max_batch;       /* frames sent to the device together, 1 .. 8; 0
-                                selects 4.  Each holds its own per-site buffers. */
+    int32_t max_batch;       /* frames sent to the device together, 1 .. 16; 0
+                                selects 16.  Each holds its own per-site buffers. */
 } dv_config;
 
 /* One edge flip (Sec. 3.2.4).  a < b are now labels; pa, pb the past labels
@@ -169,7 +169,7 @@ dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *
 /* ---- measurement ---- */
 
 /* Stages of the per-frame procedure, in launch order. */
-#define DV_N_STAGES 9
+#define DV_N_STAGES 10
 /* Bracket every launch of one stage with HIP events on the context's stream
  * (one launch covers every frame of a batch).
  * stage: 0 .. DV_N_STAGES-1, or -1 to stop.  capacity: launches that can be

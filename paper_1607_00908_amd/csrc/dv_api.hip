@@ -6,7 +6,7 @@
 // device together: each stage is one launch over all of them (frame =
 // blockIdx.z, slot i holds the buffers of the batch's i-th frame), all on the
 // context's stream, so no cross-stream ordering is needed and the host pays
-// nine launches per batch.  The comparisons of a batch are independent: the
+// ten launches per batch.  The comparisons of a batch are independent: the
 // device knows each frame's past from the frame headers.  Synchronising
 // calls flush the queue, wait for the stream and copy the headers (and the
 // requested arrays) back.
@@ -125,7 +125,7 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
     if (cfg->flags & ~DV_KEEP_MAPS) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
-        return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 8]");
+        return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 16]");
     return DV_OK;
 }
 
@@ -231,6 +231,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
              dalloc(c, &b.acc_root, K) && dalloc(c, &b.cell_count, tiles) &&
              dalloc(c, &b.cell_start, tiles + 1) && dalloc(c, &b.cell_items, K) &&
              dalloc(c, &b.cell_q, K) && dalloc(c, &b.comp_cell, K) && dalloc(c, &b.comp_slot, K) &&
+             dalloc(c, &b.tpairs, tiles * DV_TILE_PAIRS) && dalloc(c, &b.tpair_n, tiles) &&
              dalloc(c, &b.cnt, K) && dalloc(c, &b.inv, K) && dalloc(c, &b.fs, 1) &&
              comp_alloc(b.cur) && dalloc(c, &b.phi, K) && dalloc(c, &b.trigger, K) &&
              dalloc(c, &b.nb, K) && dalloc(c, &b.na, K) && dalloc(c, &b.ob, K) &&
@@ -420,7 +421,8 @@ void dv_destroy(dv_ctx *c) {
 }
 
 static const char *const STAGE_NAMES[ST_COUNT] = {
-    "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "match", "diff", "place"};
+    "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "rows", "match", "diff",
+    "place"};
 
 const char *dv_stage_name(int32_t stage) {
     return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;

@@ -10,13 +10,14 @@
 #define DV_BLOCK 256               // threads per tile workgroup
 #define DV_EMPTY 0x77777777        // MAXLINK: empty row slot / no colour
 #define DV_CAND_CAP 256            // candidate centre images held in LDS per chunk
+#define DV_TILE_PAIRS 128          // couples a colouring tile lists for the row build
 
 // error bits raised on the device during a frame
 #define DV_E_KMAX 1u               // more components than K_max
 #define DV_E_DEGREE 2u             // a Delaunay row overflowed max_degree
 
-#define DV_MAX_BATCH 8             // frames processed by one launch of each stage
-#define DV_DEFAULT_BATCH 4         // what max_batch = 0 selects
+#define DV_MAX_BATCH 16            // frames processed by one launch of each stage
+#define DV_DEFAULT_BATCH 16        // what max_batch = 0 selects
 
 // Per-frame header, one per batch slot (device memory).
 struct FrameState {
@@ -92,6 +93,8 @@ struct Bufs {
     int32_t *cell_items;   // [K_max] labels ordered by cell
     int2 *cell_q;          // [K_max] their Q.8 centres
     int32_t *comp_cell, *comp_slot;  // [K_max]
+    int2 *tpairs;          // [tiles][DV_TILE_PAIRS] distinct couples found by each tile
+    int32_t *tpair_n;      // [tiles]
     int32_t *cnt;          // [K_max] preimages of each now label
     int32_t *inv;          // [K_max] now -> past (valid when cnt == 1)
     CompBuf cur;           // components and rows of the frame
@@ -123,8 +126,8 @@ __device__ __forceinline__ int past_slot(const Bufs *D, int i) {
 
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
-    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_MATCH,
-    ST_DIFF, ST_PLACE, ST_COUNT
+    ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_ROWS,
+    ST_MATCH, ST_DIFF, ST_PLACE, ST_COUNT
 };
 
 // Optional event bracketing of one stage (measurement only).

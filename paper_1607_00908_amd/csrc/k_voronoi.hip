@@ -8,8 +8,9 @@
 //                   nearest centre of every site of the tile and its one-site
 //                   ring (LDS), owner map, frame-gap vertex test and the first /
 //                   second nearest-neighbour rules; the distinct couples of the
-//                   tile go into the adjacency rows with a lock-free set insert
-//                   (rows are unordered sets, MAXLINK padded)
+//                   tile go to the tile's couple list
+//   k_rows          the couple lists into the adjacency rows with a lock-free
+//                   set insert (rows are unordered sets, MAXLINK padded)
 #include "dv_device.h"
 
 namespace {
@@ -147,9 +148,13 @@ struct OwnerLds {
     int nranges;
     unsigned long long best;
     int wsum[16];
-    // centres seen in the first pass
+    // centres seen in the first pass: label, Q.8 centre, squared distance
+    // to the tile centre
     int tmp[TMP_CAP];
+    int2 tmpq[TMP_CAP];
+    long long tmpd[TMP_CAP];
     int ntmp;
+    int nout;      // distinct couples written to the tile's list
     // couples found by the tile, (a << 32 | b) with a < b
     unsigned long long pair[PAIR_CAP];
     int npair;
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
         be[i] = 1.0e300;
         bl[i] = DV_EMPTY;
     }
-    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; }
+    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; }
     __syncthreads();
 
     // tile centre (absolute Q.8) and the window's relative x / y extent
@@ -300,23 +305,29 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
     };
 
     // candidate list entry for centre e: every image of the centre that is the
-    // minimum image of some window point (relative offset within [-M/2, M/2])
-    auto add_images = [&](int e, int2 q) {
+    // minimum image of some window point (relative offset within [-M/2, M/2]).
+    // The offset rx lies in (-MX, MX) and the window is at most one lattice
+    // wide, so only the images k = -1 .. 2 can qualify.
+    auto add_images = [&](int lab, int2 q) {
         const int rx = q.x - OX, ry = q.y - OY;
-        const int kx0 = (int)ceil((double)(wxlo - rx - MX / 2) / MX);
-        const int kx1 = (int)floor((double)(wxhi - rx + MX / 2) / MX);
-        const int ky0 = (int)ceil((double)(wylo - ry - MY / 2) / MY);
-        const int ky1 = (int)floor((double)(wyhi - ry + MY / 2) / MY);
-        const int lab = B.cell_items[e];
-        for (int kx = kx0; kx <= kx1; ++kx)
-            for (int ky = ky0; ky <= ky1; ++ky) {
-                const int cx = rx + kx * MX, cy = ry + ky * MY;
+        unsigned mxk = 0, myk = 0;
+#pragma unroll
+        for (int k = -1; k <= 2; ++k) {
+            const int vx = rx + k * MX, vy = ry + k * MY;
+            if (vx >= wxlo - MX / 2 && vx <= wxhi + MX / 2) mxk |= 1u << (k + 1);
+            if (vy >= wylo - MY / 2 && vy <= wyhi + MY / 2) myk |= 1u << (k + 1);
+        }
+        for (unsigned a = mxk; a; a &= a - 1) {
+            const int cx = rx + (__ffs(a) - 2) * MX;
+            for (unsigned b = myk; b; b &= b - 1) {
+                const int cy = ry + (__ffs(b) - 2) * MY;
                 const int slot = atomicAdd(&S.ncand, 1);
                 if (slot >= DV_CAND_CAP) continue;   // overflow: caller falls back
                 S.cx[slot] = cx;
                 S.cy[slot] = cy;
                 S.lab[slot] = lab;
             }
+        }
     };
     // radius around the tile centre that holds every centre able to own a
     // window site or inner-frame point: bound + twice the window's half diagonal
@@ -332,9 +343,14 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
         visit_items(B, S, sx0, sy0, 1 << 30,
                     [&](int e) {
                         const int2 q = B.cell_q[e];
-                        atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
+                        const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
+                        atomicMin(&S.best, (unsigned long long)d);
                         const int slot = atomicAdd(&S.ntmp, 1);
-                        if (slot < TMP_CAP) S.tmp[slot] = e;
+                        if (slot < TMP_CAP) {
+                            S.tmp[slot] = B.cell_items[e];
+                            S.tmpq[slot] = q;
+                            S.tmpd[slot] = d;
+                        }
                     },
                     [](int) {});
         bool done = false;
@@ -346,11 +362,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
             if (rho <= cov_x && rho <= cov_y) {
                 const double rq2 = (256.0 * rho) * (256.0 * rho);
                 const int n = S.ntmp;
-                for (int j = t; j < n; j += DV_BLOCK) {
-                    const int e = S.tmp[j];
-                    const int2 q = B.cell_q[e];
-                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(e, q);
-                }
+                for (int j = t; j < n; j += DV_BLOCK)
+                    if ((double)S.tmpd[j] <= rq2) add_images(S.tmp[j], S.tmpq[j]);
                 __syncthreads();
                 done = S.ncand <= DV_CAND_CAP;
                 __syncthreads();
@@ -381,7 +394,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
                 B, S, sx, sy, CAND_BATCH,
                 [&](int e) {
                     const int2 q = B.cell_q[e];
-                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(e, q);
+                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(B.cell_items[e], q);
                 },
                 [&](int m) {
                     // evaluate and empty the list when this batch could overflow it
@@ -506,17 +519,43 @@ __global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict
         }
     }
     __syncthreads();
-    // --- distinct couples of the tile go into both rows, one thread each
+    // --- distinct couples of the tile go to its list (k_rows fills the rows);
+    // beyond the list's capacity they go into the rows directly
     const int np = min(S.npair, PAIR_CAP);
-    for (int i = t; i < 2 * np; i += DV_BLOCK) {
-        const unsigned long long key = S.pair[i >> 1];
+    const int tile = blockIdx.x;
+    for (int i = t; i < np; i += DV_BLOCK) {
+        const unsigned long long key = S.pair[i];
         bool first = true;
-        for (int j = 0; j < (i >> 1); ++j)
+        for (int j = 0; j < i; ++j)
             if (S.pair[j] == key) { first = false; break; }
         if (!first) continue;
         const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
-        if (i & 1) row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
-        else row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, fs);
+        const int slot = atomicAdd(&S.nout, 1);
+        if (slot < DV_TILE_PAIRS) {
+            B.tpairs[(size_t)tile * DV_TILE_PAIRS + slot] = make_int2(a, b);
+        } else {
+            row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, fs);
+            row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
+        }
+    }
+    __syncthreads();
+    if (t == 0) B.tpair_n[tile] = min(S.nout, DV_TILE_PAIRS);
+}
+
+// Rows from the tiles' couple lists: one wave per tile, one lane per couple
+// end.  Rows are sets: a couple found by several tiles is stored once.
+__global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D) {
+    const Bufs &B = D[blockIdx.z];
+    FrameState *fs = B.fs;
+    if (fs->err) return;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (tile >= B.ncells) return;
+    const int n = B.tpair_n[tile];
+    int *adj = B.cur.adj;
+    for (int j = lane; j < 2 * n; j += 64) {
+        const int2 p = B.tpairs[(size_t)tile * DV_TILE_PAIRS + (j >> 1)];
+        if (j & 1) row_insert(adj + (size_t)p.y * B.maxdeg, B.maxdeg, p.x, fs);
+        else row_insert(adj + (size_t)p.x * B.maxdeg, B.maxdeg, p.y, fs);
     }
 }
 
@@ -530,4 +569,7 @@ void launch_voronoi(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P)
     P.begin(ST_OWNER_EDGES, s);
     hipLaunchKernelGGL(k_owner_edges, dim3(H.ncells, 1, n), dim3(DV_BLOCK), 0, s, D);
     P.end(ST_OWNER_EDGES, s);
+    P.begin(ST_ROWS, s);
+    hipLaunchKernelGGL(k_rows, dim3((H.ncells + 3) / 4, 1, n), dim3(256), 0, s, D);
+    P.end(ST_ROWS, s);
 }

@@ -30,10 +30,10 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
            "dv_status_str", "dv_last_error")
 
-DEFAULT_BATCH = 4   # what max_batch = 0 selects
+DEFAULT_BATCH = 16   # what max_batch = 0 selects
 
-STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "match",
-          "diff", "place")
+STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "rows",
+          "match", "diff", "place")
 
 
 class DVConfig(ctypes.Structure):

@@ -181,7 +181,7 @@ def test_capacity_rejection_keeps_the_past():
     det.close()
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 8, 16])
 def test_batched_bursts_match_the_oracle(depth):
     """Frames pushed back to back with no synchronisation in between go to the
     device in batches (each stage one launch over the batch, the comparisons
