@@ -18,7 +18,6 @@
 #include "dv_device.h"
 
 #define RES_TILES 1024   // tiles of a band handled per pass of k_resolve
-#define RL_BANDS 2048    // bands whose offsets k_relabel keeps in LDS
 
 namespace {
 
@@ -415,11 +414,13 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
 __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D) {
     const Bufs &B = D[blockIdx.z];
     __shared__ int L[DV_TILE_SITES];
+    // per piece root (indexed by its tile-local site): rank, component root
+    // (x | y << 16), integer sums
     __shared__ int prank[DV_TILE_SITES];
-    __shared__ int prx[DV_TILE_SITES], pry[DV_TILE_SITES];
+    __shared__ uint32_t pxy[DV_TILE_SITES];
     __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
-    __shared__ int boff[RL_BANDS];
     __shared__ int wsum[16];
+    extern __shared__ int boff[];   // [nty] roots in the bands before each band
     FrameState *fs = B.fs;
     const int tx = blockIdx.x, ty = blockIdx.y;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
@@ -440,7 +441,6 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     }
     // roots in the bands before each band (exclusive prefix of band totals);
     // the first block publishes K and the capacity check
-    // (ly <= 65536, so there are at most RL_BANDS bands)
     const int K = block_exclusive_scan(B.band_sum, boff, B.nty, wsum);
     if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
         fs->K_now = K;
@@ -462,8 +462,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const uint32_t below = (1u << (gx & 31)) - 1u;
         const int rank = boff[gy / DV_TILE] + B.seg_prefix[seg] + __popc(B.seg_mask[seg] & below);
         prank[r] = rank;
-        prx[r] = gx;
-        pry[r] = gy;
+        pxy[r] = (uint32_t)gx | ((uint32_t)gy << 16);
         psx[r] = 0;
         psy[r] = 0;
         pn[r] = 0;
@@ -484,8 +483,9 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const size_t g = (size_t)(y0 + y) * lx + x0 + cx;
         if (B.keep_maps) B.labels[g] = inside ? prank[r] : -1;
         if (!inside) continue;
-        const int dx = wrap_off(x0 + cx - prx[r], lx);
-        const int dy = wrap_off(y0 + y - pry[r], ly);
+        const int prx = (int)(pxy[r] & 0xffffu), pry = (int)(pxy[r] >> 16);
+        const int dx = wrap_off(x0 + cx - prx, lx);
+        const int dy = wrap_off(y0 + y - pry, ly);
         // an adjacent inside site is a member; crossing the antipodal line of
         // the root makes the unwrapped coordinates jump by L - 1.  Sites on
         // that line are rare: their neighbours are read from the global map.
@@ -508,13 +508,13 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         // the first site of each horizontal run adds the whole run (one piece)
         if (cx > 0 && ((m >> (cx - 1)) & 1u)) continue;
         const int len = __builtin_ctzll(~(unsigned long long)(m >> cx));   // a full row is 32
-        const int dx_end = wrap_off(x0 + cx + len - 1 - prx[r], lx);
+        const int dx_end = wrap_off(x0 + cx + len - 1 - prx, lx);
         int sxr;
         if (dx_end - dx == len - 1) {
             sxr = (dx + dx_end) * len / 2;     // no wrap inside the run
         } else {
             sxr = 0;
-            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx[r], lx);
+            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx, lx);
         }
         atomicAdd(&psx[r], sxr);
         atomicAdd(&psy[r], dy * len);
@@ -547,6 +547,6 @@ void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStrea
     hipLaunchKernelGGL(k_resolve, dim3(H.nty, 1, n), dim3(1024), 0, s, D);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), H.nty * sizeof(int), s, D);
     P.end(ST_RELABEL, s);
 }

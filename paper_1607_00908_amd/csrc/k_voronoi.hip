@@ -225,7 +225,9 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
     }
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_owner_edges(const Bufs *__restrict__ D) {
+// Five resident blocks per CU (register budget 102): the block's gather and
+// insert phases are latency chains that other resident blocks fill.
+__global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restrict__ D) {
     const Bufs &B = D[blockIdx.z];
     __shared__ OwnerLds S;
     FrameState *fs = B.fs;
