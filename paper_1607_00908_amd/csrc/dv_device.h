@@ -4,6 +4,15 @@
 
 #include "dv_internal.h"
 
+// Global-memory view of a buffer pointer read from the slot table.  The table
+// lives in device memory, so the compiler cannot tell that its pointers are
+// global and would emit flat accesses, which also count against the LDS wait
+// counter; accesses through this view are global instructions.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // v in (-M, M) -> signed minimum image in [-M/2, M/2 - 1]  (M = 256 L, even)
 __device__ __forceinline__ int wrap_q(int v, int M) {
     const int h = M >> 1;

@@ -68,7 +68,9 @@ __device__ void lunite(int *L, int a, int b) {
 // Same path shortening as lfind.  gfind_ro walks without writing: it is the
 // find of a pass that also stores final roots, which a concurrent shortening
 // store could otherwise replace with an intermediate ancestor.
-__device__ __forceinline__ int gfind(int *P, int a) {
+using gint = __attribute__((address_space(1))) int;
+
+__device__ __forceinline__ int gfind(gint *P, int a) {
     int p = P[a];
     if (p == a) return a;
     int prev = a;
@@ -81,7 +83,7 @@ __device__ __forceinline__ int gfind(int *P, int a) {
     }
 }
 
-__device__ __forceinline__ int gfind_ro(const int *P, int a) {
+__device__ __forceinline__ int gfind_ro(const gint *P, int a) {
     int p = P[a];
     while (p != a) {
         a = p;
@@ -90,17 +92,17 @@ __device__ __forceinline__ int gfind_ro(const int *P, int a) {
     return a;
 }
 
-__device__ void gunite(int *P, int a, int b) {
+__device__ void gunite(gint *P, int a, int b) {
     bool done;
     do {
         a = gfind(P, a);
         b = gfind(P, b);
         if (a < b) {
-            const int old = atomicMin(&P[b], a);
+            const int old = __hip_atomic_fetch_min(P + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             done = (old == b);
             b = old;
         } else if (b < a) {
-            const int old = atomicMin(&P[a], b);
+            const int old = __hip_atomic_fetch_min(P + a, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             done = (old == a);
             a = old;
         } else {
@@ -134,12 +136,19 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int tw, int th, int *L,
                          uint32_t *rowm) {
     const int t = threadIdx.x, cx = t & 31, ry = t >> 5, lane = t & 63;
+    // the four loads are issued together (an out-of-tile lane reads the tile
+    // origin and ignores it)
+    float v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
-        bool in = false;
-        if (cx < tw && y < th)
-            in = is_in(field[(size_t)(y0 + y) * B.lx + x0 + cx], B.thr, B.phase);
+        const bool ok = cx < tw && y < th;
+        v[i] = field[ok ? (size_t)(y0 + y) * B.lx + x0 + cx : (size_t)y0 * B.lx + x0];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i;
+        const bool in = cx < tw && y < th && is_in(v[i], B.thr, B.phase);
         const unsigned long long bal = __ballot(in);
         const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (cx == 0) rowm[y] = m;
@@ -224,11 +233,11 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         B.cell_count[tile] = 0;
         npc = 0;
     }
-    if (t < th) B.seg_mask[(size_t)(y0 + t) * B.ntx + tx] = 0u;
+    if (t < th) gmem(B.seg_mask)[(size_t)(y0 + t) * B.ntx + tx] = 0u;
     {   // empty the rows this frame will fill
         const size_t total = (size_t)fs->rows_dirty * B.maxdeg;
         const size_t stride = (size_t)gridDim.x * gridDim.y * DV_BLOCK;
-        int *adj = B.cur.adj;
+        auto adj = gmem(B.cur.adj);
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
@@ -241,19 +250,19 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         const int r = L[s];
         const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
         if (cx < tw && y < th)
-            B.lab16[(size_t)(y0 + y) * B.lx + x0 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
+            gmem(B.lab16)[(size_t)(y0 + y) * B.lx + x0 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
         if (r < 0) {
             // an outside border site is marked so that merging needs no field
-            if (border && cx < tw && y < th) B.parent[(y0 + y) * B.lx + x0 + cx] = -1;
+            if (border && cx < tw && y < th) gmem(B.parent)[(y0 + y) * B.lx + x0 + cx] = -1;
             continue;
         }
         const int g = (y0 + y) * B.lx + x0 + cx;
         if (r == s) {
             const int slot = atomicAdd(&npc, 1);
-            B.pieces[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
-            B.parent[g] = g;
+            gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
+            gmem(B.parent)[g] = g;
         } else if (border) {
-            B.parent[g] = (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
+            gmem(B.parent)[g] = (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
         }
     }
     __syncthreads();
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
 // seams.  Uniting two sites is uniting the values they hold, so the pairs of
 // held values are united, and a pair equal to one the previous thread of the
 // same line unites is skipped (two pieces usually touch along many sites).
-__device__ __forceinline__ void merge_line(int *P, int ps, const int pu[3], bool conn8, bool active,
+__device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], bool conn8, bool active,
                                            int lane) {
     // pairs of this thread: up to three (ps, pu[k])
     int a[3], b[3];
@@ -316,12 +325,12 @@ __global__ __launch_bounds__(64) void k_merge(const Bufs *__restrict__ D) {
         if (active) {
             const int x = x0 + tw - 1, y = y0 + j;
             const int xn = (x + 1 == lx) ? 0 : x + 1;
-            ps = B.parent[y * lx + x];
+            ps = gmem(B.parent)[y * lx + x];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int yn = y + k - 1;
                 yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
-                pu[k] = B.parent[yn * lx + xn];
+                pu[k] = gmem(B.parent)[yn * lx + xn];
             }
         }
     } else {
@@ -330,16 +339,16 @@ __global__ __launch_bounds__(64) void k_merge(const Bufs *__restrict__ D) {
         if (active) {
             const int x = x0 + j, y = y0 + th - 1;
             const int yn = (y + 1 == ly) ? 0 : y + 1;
-            ps = B.parent[y * lx + x];
+            ps = gmem(B.parent)[y * lx + x];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int xn = x + k - 1;
                 xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
-                pu[k] = B.parent[yn * lx + xn];
+                pu[k] = gmem(B.parent)[yn * lx + xn];
             }
         }
     }
-    merge_line(B.parent, ps, pu, B.conn == 8, active, lane);
+    merge_line(gmem(B.parent), ps, pu, B.conn == 8, active, lane);
 }
 
 // One block per band of 32 rows: every piece of the band's tiles finds its
@@ -371,8 +380,8 @@ __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D) {
             const int tx = c0 + lo;
             const int r = B.pieces[(size_t)(tile0 + lo) * DV_TILE_SITES + (f - pre[lo])];
             const int g = (y0 + (r >> 5)) * B.lx + tx * DV_TILE + (r & 31);
-            const int root = gfind_ro(B.parent, g);
-            if (root != g) B.parent[g] = root;
+            const int root = gfind_ro(gmem(B.parent), g);
+            if (root != g) gmem(B.parent)[g] = root;
             else atomicOr(&B.seg_mask[(size_t)(y0 + (r >> 5)) * ntx + tx], 1u << (r & 31));
         }
         __syncthreads();
@@ -429,15 +438,17 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
 
     // tile-local roots of the tile, as written by k_tile_ccl
     const int cx = t & 31, ry = t >> 5;
+    uint16_t u[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
-        int v = -1;
-        if (cx < tw && y < th) {
-            const uint16_t u = B.lab16[(size_t)(y0 + y) * lx + x0 + cx];
-            v = u != 0xffff ? (int)u : -1;
-        }
-        L[y * 32 + cx] = v;
+        const bool ok = cx < tw && y < th;
+        u[i] = gmem(B.lab16)[ok ? (size_t)(y0 + y) * lx + x0 + cx : (size_t)y0 * lx + x0];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i;
+        L[y * 32 + cx] = (cx < tw && y < th && u[i] != 0xffff) ? (int)u[i] : -1;
     }
     // roots in the bands before each band (exclusive prefix of band totals);
     // the first block publishes K and the capacity check
@@ -456,17 +467,18 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const int y = ry + 8 * i, r = y * 32 + cx;
         if (L[r] != r) continue;
         const int g = (y0 + y) * lx + x0 + cx;
-        const int G = B.parent[g];          // component root (compressed)
+        const int G = gmem(B.parent)[g];    // component root (compressed)
         const int gx = G % lx, gy = G / lx;
         const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
         const uint32_t below = (1u << (gx & 31)) - 1u;
-        const int rank = boff[gy / DV_TILE] + B.seg_prefix[seg] + __popc(B.seg_mask[seg] & below);
+        const int rank = boff[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
+                         __popc(gmem(B.seg_mask)[seg] & below);
         prank[r] = rank;
         pxy[r] = (uint32_t)gx | ((uint32_t)gy << 16);
         psx[r] = 0;
         psy[r] = 0;
         pn[r] = 0;
-        if (G == g && rank < B.kmax) B.acc_root[rank] = G;
+        if (G == g && rank < B.kmax) gmem(B.acc_root)[rank] = G;
     }
     __syncthreads();
 
@@ -481,7 +493,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (cx >= tw || y >= th) continue;
         const size_t g = (size_t)(y0 + y) * lx + x0 + cx;
-        if (B.keep_maps) B.labels[g] = inside ? prank[r] : -1;
+        if (B.keep_maps) gmem(B.labels)[g] = inside ? prank[r] : -1;
         if (!inside) continue;
         const int prx = (int)(pxy[r] & 0xffffu), pry = (int)(pxy[r] >> 16);
         const int dx = wrap_off(x0 + cx - prx, lx);
@@ -494,7 +506,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
             const int gx = x0 + cx, gy = y0 + y;
             const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
             const int yp = gy + 1 == ly ? 0 : gy + 1, ym = gy == 0 ? ly - 1 : gy - 1;
-            auto inside_at = [&](int xx, int yy) { return B.lab16[(size_t)yy * lx + xx] != 0xffff; };
+            auto inside_at = [&](int xx, int yy) { return gmem(B.lab16)[(size_t)yy * lx + xx] != 0xffff; };
             if (dx == hix) {
                 amb = inside_at(xp, gy);
                 if (B.conn == 8) amb = amb || inside_at(xp, ym) || inside_at(xp, yp);
