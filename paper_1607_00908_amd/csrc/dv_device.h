@@ -12,6 +12,18 @@ template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
     return (__attribute__((address_space(1))) T *)p;
 }
+using gint = __attribute__((address_space(1))) int;
+typedef int dv_v4i __attribute__((ext_vector_type(4)));
+
+// int2 element i of a buffer, through a global 64-bit access
+__device__ __forceinline__ int2 ld_int2(const int2 *p, size_t i) {
+    const unsigned long long v = gmem(reinterpret_cast<const unsigned long long *>(p))[i];
+    return make_int2((int)(unsigned)v, (int)(unsigned)(v >> 32));
+}
+__device__ __forceinline__ void st_int2(int2 *p, size_t i, int a, int b) {
+    gmem(reinterpret_cast<unsigned long long *>(p))[i] =
+        (unsigned long long)(unsigned)a | ((unsigned long long)(unsigned)b << 32);
+}
 
 // v in (-M, M) -> signed minimum image in [-M/2, M/2 - 1]  (M = 256 L, even)
 __device__ __forceinline__ int wrap_q(int v, int M) {
@@ -89,7 +101,7 @@ __device__ __forceinline__ bool span_full(const Span &s, int ncell) {
 __device__ int point_nearest(const Bufs &B, int X, int Y) {
     const int MX = 256 * B.lx, MY = 256 * B.ly;
     const int cx = X >> 13, cy = Y >> 13;
-    const int *cs = B.cell_start;
+    const auto cs = gmem(B.cell_start);
     long long bd = LLONG_MAX;
     for (int R = 1;; R *= 2) {
         const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
@@ -98,7 +110,7 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
                 for (int rx = 0; rx < sx.n; ++rx) {
                     const int e0 = cs[row * B.ntx + sx.lo(rx)], e1 = cs[row * B.ntx + sx.hi(rx) + 1];
                     for (int e = e0; e < e1; ++e) {
-                        const int2 q = B.cell_q[e];
+                        const int2 q = ld_int2(B.cell_q, e);
                         const long long d = d2q(X, Y, q.x, q.y, MX, MY);
                         if (d < bd) bd = d;
                     }
@@ -117,9 +129,9 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
             for (int rx = 0; rx < sx.n; ++rx) {
                 const int e0 = cs[row * B.ntx + sx.lo(rx)], e1 = cs[row * B.ntx + sx.hi(rx) + 1];
                 for (int e = e0; e < e1; ++e) {
-                    const int2 q = B.cell_q[e];
+                    const int2 q = ld_int2(B.cell_q, e);
                     const long long d = d2q(X, Y, q.x, q.y, MX, MY);
-                    const int lab = B.cell_items[e];
+                    const int lab = gmem(B.cell_items)[e];
                     if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
                 }
             }
@@ -142,7 +154,7 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
     const int MX = 256 * B.lx, MY = 256 * B.ly;
     const int cx = X >> 13, cy = Y >> 13;
     const int lane = threadIdx.x & 63;
-    const int *cs = B.cell_start;
+    const auto cs = gmem(B.cell_start);
     long long bd = LLONG_MAX;
     int dummy = 0;
     for (int R = 1;; R *= 2) {
@@ -153,7 +165,7 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
             const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
             const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
             for (int e = e0; e < e1; ++e) {
-                const int2 q = B.cell_q[e];
+                const int2 q = ld_int2(B.cell_q, e);
                 const long long d = d2q(X, Y, q.x, q.y, MX, MY);
                 if (d < bd) bd = d;
             }
@@ -173,9 +185,9 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
         const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
         const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
         for (int e = e0; e < e1; ++e) {
-            const int2 q = B.cell_q[e];
+            const int2 q = ld_int2(B.cell_q, e);
             const long long d = d2q(X, Y, q.x, q.y, MX, MY);
-            const int lab = B.cell_items[e];
+            const int lab = gmem(B.cell_items)[e];
             if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
         }
     }

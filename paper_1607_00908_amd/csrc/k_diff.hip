@@ -61,12 +61,12 @@ __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D) {
     const int nw = blockDim.x >> 6;
     for (int p = blockIdx.x * nw + (threadIdx.x >> 6); p < KP; p += gridDim.x * nw) {
         int n = -1;
-        if (KN > 0) n = wave_nearest(B, P.C.qx[p], P.C.qy[p]);
+        if (KN > 0) n = wave_nearest(B, gmem(P.C.qx)[p], gmem(P.C.qy)[p]);
         if (lane == 0) {
-            B.phi[p] = n;
+            gmem(B.phi)[p] = n;
             if (n >= 0) {
                 atomicAdd(&B.cnt[n], 1);
-                B.inv[n] = p;
+                gmem(B.inv)[n] = p;
             }
         }
     }
@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int n
     int e2 = 0, exn = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
     for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
-        const int m = lane < D ? N.adj[(size_t)n * D + lane] : DV_EMPTY;
+        const int m = lane < D ? gmem(N.adj)[(size_t)n * D + lane] : DV_EMPTY;
         if (keep) {
-            if (lane < D) Q.adj[(size_t)n * D + lane] = m;
+            if (lane < D) gmem(Q.adj)[(size_t)n * D + lane] = m;
             switch (lane) {
                 case 0: Q.qx[n] = N.qx[n]; break;
                 case 1: Q.qy[n] = N.qy[n]; break;
@@ -105,21 +105,21 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int n
                 default: break;
             }
         }
-        const int cn = B.cnt[n];
-        const int p = B.inv[n];
+        const int cn = gmem(B.cnt)[n];
+        const int p = gmem(B.inv)[n];
         const int dR = __popcll(__ballot(m != DV_EMPTY));
         if (lane == 0) e2 += dR;
         int cb = 0, ca = 0;
         if (pv && cn != 1) {
             if (lane == 0) ++exn;
         } else if (pv) {
-            const int q = lane < D ? P.adj[(size_t)p * D + lane] : DV_EMPTY;
+            const int q = lane < D ? gmem(P.adj)[(size_t)p * D + lane] : DV_EMPTY;
             const int dT = __popcll(__ballot(q != DV_EMPTY));
-            const int mv = (m != DV_EMPTY && B.cnt[m] == 1) ? m : DV_EMPTY;
+            const int mv = (m != DV_EMPTY && gmem(B.cnt)[m] == 1) ? m : DV_EMPTY;
             int tv = DV_EMPTY;
             if (q != DV_EMPTY) {
-                const int nn = B.phi[q];
-                if (nn >= 0 && B.cnt[nn] == 1) tv = nn;
+                const int nn = gmem(B.phi)[q];
+                if (nn >= 0 && gmem(B.cnt)[nn] == 1) tv = nn;
             }
             // slots are filled from the front: the first dR (dT) lanes
             bool tin = false, min_ = false;
@@ -128,28 +128,28 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int n
             const bool brk = tv != DV_EMPTY && !tin;
             const bool ari = mv != DV_EMPTY && !min_;
             const unsigned long long dmask = __ballot(brk || ari);
-            if (lane == 0) B.trigger[p] = dmask ? 1 : 0;
+            if (lane == 0) gmem(B.trigger)[p] = dmask ? 1 : 0;
             // each couple once, from the row of its smaller now label
             const bool bo = brk && tv > n, ao = ari && mv > n;
             cb = __popcll(__ballot(bo));
             ca = __popcll(__ballot(ao));
-            int *stg = B.stage + (size_t)n * (2 * D) * 6;
+            gint *stg = gmem(B.stage) + (size_t)n * (2 * D) * 6;
             const int bv = bo ? tv : DV_EMPTY, av = ao ? mv : DV_EMPTY;
             int rb = 0, ra = 0;
             for (int k = 0; k < dT; ++k) rb += (__shfl(bv, k, 64) < bv) ? 1 : 0;
             for (int k = 0; k < dR; ++k) ra += (__shfl(av, k, 64) < av) ? 1 : 0;
             if (bo) {
-                int *r = stg + 6 * rb;
+                gint *r = stg + 6 * rb;
                 r[0] = n; r[1] = tv; r[2] = p; r[3] = q; r[4] = -1; r[5] = 0;
             }
             if (ao) {
-                int *r = stg + 6 * (D + ra);
-                r[0] = n; r[1] = mv; r[2] = p; r[3] = B.inv[mv]; r[4] = 1; r[5] = 0;
+                gint *r = stg + 6 * (D + ra);
+                r[0] = n; r[1] = mv; r[2] = p; r[3] = gmem(B.inv)[mv]; r[4] = 1; r[5] = 0;
             }
         }
         if (lane == 0) {
-            B.nb[n] = cb;
-            B.na[n] = ca;
+            gmem(B.nb)[n] = cb;
+            gmem(B.na)[n] = ca;
         }
     }
     for (int o = 32; o > 0; o >>= 1) {

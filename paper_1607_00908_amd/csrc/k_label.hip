@@ -68,8 +68,6 @@ __device__ void lunite(int *L, int a, int b) {
 // Same path shortening as lfind.  gfind_ro walks without writing: it is the
 // find of a pass that also stores final roots, which a concurrent shortening
 // store could otherwise replace with an intermediate ancestor.
-using gint = __attribute__((address_space(1))) int;
-
 __device__ __forceinline__ int gfind(gint *P, int a) {
     int p = P[a];
     if (p == a) return a;

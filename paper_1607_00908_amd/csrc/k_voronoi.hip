@@ -102,9 +102,9 @@ __device__ __forceinline__ int iny(int r) { return r >= 2 ? -128 : 128; }
 // Lock-free set insert into a row (slots fill from the front; DV_EMPTY marks
 // free slots).  Rows are 16-byte aligned (max_degree is a multiple of 4), so
 // four slots are read per load.
-__device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, FrameState *fs) {
+__device__ __forceinline__ void row_insert(gint *row, int maxdeg, int v, FrameState *fs) {
     for (int i = 0; i < maxdeg; i += 4) {
-        const int4 q = *reinterpret_cast<const int4 *>(row + i);
+        const dv_v4i q = *reinterpret_cast<const __attribute__((address_space(1))) dv_v4i *>(row + i);
         const int e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -112,7 +112,9 @@ __device__ __forceinline__ void row_insert(int *row, int maxdeg, int v, FrameSta
             if (e[j] == DV_EMPTY) {
                 // claim the first free slot; on a lost race re-examine it
                 for (int k = i + j; k < maxdeg; ++k) {
-                    const int old = atomicCAS(&row[k], DV_EMPTY, v);
+                    int old = DV_EMPTY;
+                    __hip_atomic_compare_exchange_strong(row + k, &old, v, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (old == DV_EMPTY || old == v) return;
                 }
                 atomicOr(&fs->err, DV_E_DEGREE);
@@ -171,7 +173,7 @@ template <class Fn, class Before>
 __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Span &sy, int batch,
                             Fn fn, Before before) {
     const int t = threadIdx.x;
-    const int *cs = B.cell_start;
+    const auto cs = gmem(B.cell_start);
     // rows of the rectangle, enumerated in order
     int nrows = 0;
     for (int i = 0; i < sy.n; ++i) nrows += sy.hi(i) - sy.lo(i) + 1;
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
     FrameState *fs = B.fs;
     if (fs->err) return;
     const int K = fs->K_now;
-    int *adj = B.cur.adj;
+    gint *adj = gmem(B.cur.adj);
     const int tx = blockIdx.x % B.ntx, ty = blockIdx.x / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
@@ -344,12 +346,12 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
         const Span sx0 = span_cells(tx, R0, B.ntx), sy0 = span_cells(ty, R0, B.nty);
         visit_items(B, S, sx0, sy0, 1 << 30,
                     [&](int e) {
-                        const int2 q = B.cell_q[e];
+                        const int2 q = ld_int2(B.cell_q, e);
                         const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
                         atomicMin(&S.best, (unsigned long long)d);
                         const int slot = atomicAdd(&S.ntmp, 1);
                         if (slot < TMP_CAP) {
-                            S.tmp[slot] = B.cell_items[e];
+                            S.tmp[slot] = gmem(B.cell_items)[e];
                             S.tmpq[slot] = q;
                             S.tmpd[slot] = d;
                         }
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
                 const Span sx = span_cells(tx, 2 * R, B.ntx), sy = span_cells(ty, 2 * R, B.nty);
                 visit_items(B, S, sx, sy, 1 << 30,
                             [&](int e) {
-                                const int2 q = B.cell_q[e];
+                                const int2 q = ld_int2(B.cell_q, e);
                                 atomicMin(&S.best, (unsigned long long)d2q(tcx, tcy, q.x, q.y, MX, MY));
                             },
                             [](int) {});
@@ -395,8 +397,8 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
             visit_items(
                 B, S, sx, sy, CAND_BATCH,
                 [&](int e) {
-                    const int2 q = B.cell_q[e];
-                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(B.cell_items[e], q);
+                    const int2 q = ld_int2(B.cell_q, e);
+                    if ((double)d2q(tcx, tcy, q.x, q.y, MX, MY) <= rq2) add_images(gmem(B.cell_items)[e], q);
                 },
                 [&](int m) {
                     // evaluate and empty the list when this batch could overflow it
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
         if (cx >= tw || y >= th) continue;
         const int c = (y + 1) * 34 + cx + 1;
         const int ckk = S.own[c];
-        if (B.keep_maps) B.owner[(size_t)(y0 + y) * lx + x0 + cx] = ckk;
+        if (B.keep_maps) gmem(B.owner)[(size_t)(y0 + y) * lx + x0 + cx] = ckk;
         if (ckk == DV_EMPTY) continue;
         int f[8];
 #pragma unroll
@@ -534,14 +536,14 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
         const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
         const int slot = atomicAdd(&S.nout, 1);
         if (slot < DV_TILE_PAIRS) {
-            B.tpairs[(size_t)tile * DV_TILE_PAIRS + slot] = make_int2(a, b);
+            st_int2(B.tpairs, (size_t)tile * DV_TILE_PAIRS + slot, a, b);
         } else {
             row_insert(adj + (size_t)a * B.maxdeg, B.maxdeg, b, fs);
             row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
         }
     }
     __syncthreads();
-    if (t == 0) B.tpair_n[tile] = min(S.nout, DV_TILE_PAIRS);
+    if (t == 0) gmem(B.tpair_n)[tile] = min(S.nout, DV_TILE_PAIRS);
 }
 
 // Rows from the tiles' couple lists: one wave per tile, one lane per couple
@@ -552,10 +554,10 @@ __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D) {
     if (fs->err) return;
     const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (tile >= B.ncells) return;
-    const int n = B.tpair_n[tile];
-    int *adj = B.cur.adj;
+    const int n = gmem(B.tpair_n)[tile];
+    gint *adj = gmem(B.cur.adj);
     for (int j = lane; j < 2 * n; j += 64) {
-        const int2 p = B.tpairs[(size_t)tile * DV_TILE_PAIRS + (j >> 1)];
+        const int2 p = ld_int2(B.tpairs, (size_t)tile * DV_TILE_PAIRS + (j >> 1));
         if (j & 1) row_insert(adj + (size_t)p.y * B.maxdeg, B.maxdeg, p.x, fs);
         else row_insert(adj + (size_t)p.x * B.maxdeg, B.maxdeg, p.y, fs);
     }
