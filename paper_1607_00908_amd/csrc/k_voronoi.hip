@@ -344,19 +344,30 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
         // every candidate as well
         const int R0 = 3;
         const Span sx0 = span_cells(tx, R0, B.ntx), sy0 = span_cells(ty, R0, B.nty);
-        visit_items(B, S, sx0, sy0, 1 << 30,
-                    [&](int e) {
-                        const int2 q = ld_int2(B.cell_q, e);
-                        const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
-                        atomicMin(&S.best, (unsigned long long)d);
-                        const int slot = atomicAdd(&S.ntmp, 1);
-                        if (slot < TMP_CAP) {
-                            S.tmp[slot] = gmem(B.cell_items)[e];
-                            S.tmpq[slot] = q;
-                            S.tmpd[slot] = d;
-                        }
-                    },
-                    [](int) {});
+        {   // one thread per cell of the square walks the cell's centres
+            const int n0x = sx0.hi0 - sx0.lo0 + 1, ncx = n0x + (sx0.n == 2 ? sx0.hi1 - sx0.lo1 + 1 : 0);
+            const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
+            if (t < ncx * ncy) {
+                const int ix = t % ncx, iy = t / ncx;
+                const int cellx = ix < n0x ? sx0.lo0 + ix : sx0.lo1 + (ix - n0x);
+                const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
+                const auto cs = gmem(B.cell_start);
+                const int e0 = cs[celly * B.ntx + cellx], e1 = cs[celly * B.ntx + cellx + 1];
+                for (int e = e0; e < e1; ++e) {
+                    const int2 q = ld_int2(B.cell_q, e);
+                    const int lab = gmem(B.cell_items)[e];
+                    const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
+                    atomicMin(&S.best, (unsigned long long)d);
+                    const int slot = atomicAdd(&S.ntmp, 1);
+                    if (slot < TMP_CAP) {
+                        S.tmp[slot] = lab;
+                        S.tmpq[slot] = q;
+                        S.tmpd[slot] = d;
+                    }
+                }
+            }
+            __syncthreads();
+        }
         bool done = false;
         if (S.best != ~0ull && S.ntmp <= TMP_CAP) {
             const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
@@ -434,19 +445,26 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
             row_insert(adj + (size_t)b * B.maxdeg, B.maxdeg, a, fs);
         }
     };
+    // thread t takes column t & 31 and the four rows 4 (t >> 5) .. + 3, so the
+    // colours around its sites are one 6 x 3 block of the window
     const int cx = t & 31, ry = t >> 5, lane = t & 63;
+    const int ys = 4 * ry;
+    int g[6][3];
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) g[a][b] = S.own[(ys + a) * 34 + cx + b];
     unsigned pend = 0;   // bit 4i + r: site i needs the colour of inner-frame point r
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i;
+        const int y = ys + i;
         if (cx >= tw || y >= th) continue;
-        const int c = (y + 1) * 34 + cx + 1;
-        const int ckk = S.own[c];
+        const int ckk = g[i + 1][1];
         if (B.keep_maps) gmem(B.owner)[(size_t)(y0 + y) * lx + x0 + cx] = ckk;
         if (ckk == DV_EMPTY) continue;
         int f[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k] = S.own[c + fry(k) * 34 + frx(k)];
+        for (int k = 0; k < 8; ++k) f[k] = g[i + 1 + fry(k)][1 + frx(k)];
         int gaps = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -488,7 +506,7 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
                 rest &= rest - 1;
                 if (j >= c0 && j < c0 + QCAP) {
                     const int i = bit >> 2, r = bit & 3;
-                    S.q[j - c0] = (((ry + 8 * i) * 32 + cx) << 2) | r;
+                    S.q[j - c0] = (((ys + i) * 32 + cx) << 2) | r;
                 }
             }
             __syncthreads();
