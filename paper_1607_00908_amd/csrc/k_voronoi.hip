@@ -227,9 +227,9 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
     }
 }
 
-// Five resident blocks per CU (register budget 102): the block's gather and
-// insert phases are latency chains that other resident blocks fill.
-__global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restrict__ D) {
+// Six resident blocks per CU (register budget 85): the block's gather and
+// barrier-bounded phases are latency chains that other resident blocks fill.
+__global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D) {
     const Bufs &B = D[blockIdx.z];
     __shared__ OwnerLds S;
     FrameState *fs = B.fs;
@@ -245,14 +245,14 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
     const int OX = 256 * x0, OY = 256 * y0;   // tile origin (Q.8); coordinates below are relative
 
     // window sites of this thread: exact tile-relative Q.8 coordinates
-    double m2x[WSITES], m2y[WSITES], be[WSITES];
+    // (best value, owner) of the thread's window sites w = t + 256 i; the
+    // site coordinates are rebuilt where needed (w / W by a multiply: w <
+    // 1280 and W <= 34, so the 16-bit reciprocal is exact)
+    double be[WSITES];
     int bl[WSITES];
+    const int wmagic = (65536 + W - 1) / W;
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
-        const int w = t + i * DV_BLOCK;
-        const int wx = w % W - 1, wy = w / W - 1;
-        m2x[i] = -2.0 * (256.0 * wx);
-        m2y[i] = -2.0 * (256.0 * wy);
         be[i] = 1.0e300;
         bl[i] = DV_EMPTY;
     }
@@ -267,6 +267,14 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
     // label, so that within it a strict comparison already sends ties to the
     // lowest label; a later chunk (after an overflow) also compares labels.
     auto eval_owners = [&]() {
+        double m2x[WSITES], m2y[WSITES];
+#pragma unroll
+        for (int i = 0; i < WSITES; ++i) {
+            const int w = t + i * DV_BLOCK;
+            const int wy = (w * wmagic) >> 16, wx = w - wy * W;
+            m2x[i] = -512.0 * (wx - 1);
+            m2y[i] = -512.0 * (wy - 1);
+        }
         __syncthreads();
         const int nc = min(S.ncand, DV_CAND_CAP);
         for (int c = t; c < nc; c += DV_BLOCK) {
@@ -426,7 +434,8 @@ __global__ __launch_bounds__(DV_BLOCK, 5) void k_owner_edges(const Bufs *__restr
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
         const int w = t + i * DV_BLOCK;
-        if (w < W * H) S.own[(w / W) * 34 + (w % W)] = bl[i];
+        const int wy = (w * wmagic) >> 16, wx = w - wy * W;
+        if (w < W * H) S.own[wy * 34 + wx] = bl[i];
     }
     __syncthreads();
 
