@@ -305,7 +305,9 @@ __global__ __launch_bounds__(256) void k_edge_write(const Bufs *__restrict__ D, 
 }  // namespace
 
 void launch_compare(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P) {
-    const int grid = (int)std::min<long long>((H.kmax + 3) / 4, 2048);
+    // one wave per point / row, grid-stride: a quarter of K_max waves per frame
+    // (K is usually well below K_max; a batch has up to 16 frames of them)
+    const int grid = (int)std::max<long long>(1, std::min<long long>((H.kmax + 15) / 16, 512));
     P.begin(ST_MATCH, s);
     hipLaunchKernelGGL(k_match, dim3(grid, 1, n), dim3(256), 0, s, D);
     P.end(ST_MATCH, s);

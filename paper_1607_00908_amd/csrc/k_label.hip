@@ -269,11 +269,11 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
 
 // Unions between inside sites of neighbouring tiles (every tile-border site
 // holds an ancestor of its piece, at least its piece root, or -1 when
-// outside).  Thread j < 32 takes row j of the tile's last column against the
-// next column (periodic); thread 32 + j takes column j of the last row against
-// the next row.  Together they cover every adjacent pair that crosses a tile
-// border, including the diagonal pairs at tile corners and the periodic
-// seams.  Uniting two sites is uniting the values they hold, so the pairs of
+// outside).  One wave per tile: lane j < 32 takes row j of the tile's last
+// column against the next column (periodic); lane 32 + j takes column j of
+// the last row against the next row.  Together they cover every adjacent
+// pair that crosses a tile border, including the diagonal pairs at tile
+// corners and the periodic seams.  Uniting two sites is uniting the values they hold, so the pairs of
 // held values are united, and a pair equal to one the previous thread of the
 // same line unites is skipped (two pieces usually touch along many sites).
 __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], bool conn8, bool active,
@@ -307,13 +307,16 @@ __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], boo
     }
 }
 
-__global__ __launch_bounds__(64) void k_merge(const Bufs *__restrict__ D) {
+__global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D) {
     const Bufs &B = D[blockIdx.z];
-    const int tx = blockIdx.x, ty = blockIdx.y;
+    // one wave per tile, four tiles per block
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= B.ncells) return;
+    const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int lx = B.lx, ly = B.ly;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int j = lane & 31;
     int ps = -1, pu[3] = {-1, -1, -1};
     bool active;
@@ -551,7 +554,7 @@ void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStrea
     hipLaunchKernelGGL(k_tile_ccl, tiles, dim3(DV_BLOCK), 0, s, D, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
-    hipLaunchKernelGGL(k_merge, tiles, dim3(64), 0, s, D);
+    hipLaunchKernelGGL(k_merge, dim3((H.ncells + 3) / 4, 1, n), dim3(256), 0, s, D);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, dim3(H.nty, 1, n), dim3(1024), 0, s, D);
