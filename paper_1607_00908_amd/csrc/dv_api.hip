@@ -223,7 +223,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     for (int k = 0; ok && k < c->batch; ++k) {
         Bufs &b = c->h_tab[k];
         b = B;
-        ok = dalloc(c, &b.parent, N) && dalloc(c, &b.lab16, N) &&
+        ok = dalloc(c, &b.parent, N) && dalloc(c, &b.lab16, tiles * DV_TILE_SITES) &&
              dalloc(c, &b.pieces, tiles * DV_TILE_SITES) && dalloc(c, &b.npieces, tiles) &&
              dalloc(c, &b.seg_mask, segs) && dalloc(c, &b.seg_prefix, segs) &&
              dalloc(c, &b.band_sum, (size_t)B.nty) && dalloc(c, &b.acc_x, K) &&

@@ -248,7 +248,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         const int r = L[s];
         const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
         if (cx < tw && y < th)
-            gmem(B.lab16)[(size_t)(y0 + y) * B.lx + x0 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
+            gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
         if (r < 0) {
             // an outside border site is marked so that merging needs no field
             if (border && cx < tw && y < th) gmem(B.parent)[(y0 + y) * B.lx + x0 + cx] = -1;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     __shared__ int wsum[16];
     extern __shared__ int boff[];   // [nty] roots in the bands before each band
     FrameState *fs = B.fs;
-    const int tx = blockIdx.x, ty = blockIdx.y;
+    const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
         const bool ok = cx < tw && y < th;
-        u[i] = gmem(B.lab16)[ok ? (size_t)(y0 + y) * lx + x0 + cx : (size_t)y0 * lx + x0];
+        u[i] = gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + (ok ? y * 32 + cx : 0)];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -507,7 +507,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
             const int gx = x0 + cx, gy = y0 + y;
             const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
             const int yp = gy + 1 == ly ? 0 : gy + 1, ym = gy == 0 ? ly - 1 : gy - 1;
-            auto inside_at = [&](int xx, int yy) { return gmem(B.lab16)[(size_t)yy * lx + xx] != 0xffff; };
+            auto inside_at = [&](int xx, int yy) {
+                const size_t tl = (size_t)(yy >> 5) * B.ntx + (xx >> 5);
+                return gmem(B.lab16)[tl * DV_TILE_SITES + (yy & 31) * 32 + (xx & 31)] != 0xffff;
+            };
             if (dx == hix) {
                 amb = inside_at(xp, gy);
                 if (B.conn == 8) amb = amb || inside_at(xp, ym) || inside_at(xp, yp);
