@@ -29,6 +29,8 @@ struct dv_ctx {
     int batch;               // frames per launch
     Bufs h_tab[DV_MAX_BATCH];  // host copy of the slot table
     Bufs *d_tab;             // device slot table
+    int *d_tbase, *d_bbase;  // prefix sums of tiles / bands over the slots
+    int h_tbase[DV_MAX_BATCH + 1], h_bbase[DV_MAX_BATCH + 1];
     Fields pending;          // queued field pointers
     int npending;
     int last;                // slot of the most recent frame sent to the device
@@ -75,9 +77,21 @@ void drop_events(dv_ctx *c) {
 dv_status flush(dv_ctx *c) {
     const int n = c->npending;
     if (n == 0) return DV_OK;
-    launch_label(c->h_tab[0], c->d_tab, n, c->pending, c->stream, c->prof);
-    launch_voronoi(c->h_tab[0], c->d_tab, n, c->stream, c->prof);
-    launch_compare(c->h_tab[0], c->d_tab, n, c->stream, c->prof);
+    const Bufs &H = c->h_tab[0];
+    Batch G;
+    G.D = c->d_tab;
+    G.tbase = c->d_tbase;
+    G.bbase = c->d_bbase;
+    G.n = n;
+    G.tiles = n * H.ncells;
+    G.bands = n * H.nty;
+    G.tpe = H.ncells;
+    G.bpe = H.nty;
+    G.kmax = H.kmax;
+    G.nty = H.nty;
+    launch_label(G, c->pending, c->stream, c->prof);
+    launch_voronoi(G, c->stream, c->prof);
+    launch_compare(G, c->stream, c->prof);
     c->npending = 0;
     c->last = n - 1;
     const hipError_t e = hipGetLastError();
@@ -180,6 +194,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     c->h_state = nullptr;
     c->h_frame = nullptr;
     c->d_tab = nullptr;
+    c->d_tbase = nullptr;
+    c->d_bbase = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -217,7 +233,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
                dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
     };
     bool ok = dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
-              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
+              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_tbase, DV_MAX_BATCH + 1) &&
+              dalloc(c, &c->d_bbase, DV_MAX_BATCH + 1) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
               dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
     // per-slot buffers
     for (int k = 0; ok && k < c->batch; ++k) {
@@ -249,7 +266,15 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     }
     // initial contents: slot table, zero accumulators and headers, empty rows
     hipStream_t s0 = c->stream;
+    for (int k = 0; k <= DV_MAX_BATCH; ++k) {
+        c->h_tbase[k] = k * B.ncells;
+        c->h_bbase[k] = k * B.nty;
+    }
     bool z = hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(Bufs) * c->batch, hipMemcpyHostToDevice, s0) ==
+                 hipSuccess &&
+             hipMemcpyAsync(c->d_tbase, c->h_tbase, sizeof(c->h_tbase), hipMemcpyHostToDevice, s0) ==
+                 hipSuccess &&
+             hipMemcpyAsync(c->d_bbase, c->h_bbase, sizeof(c->h_bbase), hipMemcpyHostToDevice, s0) ==
                  hipSuccess &&
              hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
     for (int b = 0; z && b < 2; ++b)

@@ -16,7 +16,8 @@
 #define DV_E_KMAX 1u               // more components than K_max
 #define DV_E_DEGREE 2u             // a Delaunay row overflowed max_degree
 
-#define DV_MAX_BATCH 16            // frames processed by one launch of each stage
+#define DV_MAX_BATCH 16            // frames of one sequence processed by one launch
+#define DV_MAX_ENTRIES 64          // frames (of one or several sequences) in one launch
 #define DV_DEFAULT_BATCH 16        // what max_batch = 0 selects
 
 // Per-frame header, one per batch slot (device memory).
@@ -68,6 +69,7 @@ struct CompBuf {
 // device memory; a kernel takes its frame's entry (blockIdx.z) and, for the
 // comparison, the entry of the frame before it.
 struct Bufs {
+    int32_t seq;           // sequence of the entry within a launch (past and commit)
     int32_t lx, ly, ntx, nty;
     float thr;
     int32_t phase, conn;
@@ -111,17 +113,46 @@ struct Bufs {
     SeqState *st;          // shared by the slots
 };
 
-// Field pointers of the frames of one batch.
+// Field pointers of the frames of one launch.
 struct Fields {
-    const float *p[DV_MAX_BATCH];
+    const float *p[DV_MAX_ENTRIES];
 };
 
-// Past of frame i of a batch (i = 0 .. n-1): the last earlier frame of the
-// batch whose stage errors are clear, else the shared past buffer.  Returns
-// the slot index, or -1 for the shared buffer.
+// One launch's work: entries 0 .. n-1 of the device slot table D (frames of
+// one or several sequences, each with its own lattice), and the prefix sums
+// of their tile and band counts, so that a flat block index finds its entry.
+// The table itself is a separate kernel argument (const, restrict: slot
+// fields are loaded once, not after every store).
+struct Batch {
+    const Bufs *D;
+    const int *tbase;      // [n + 1] first flat tile of each entry
+    const int *bbase;      // [n + 1] first flat band (32 rows) of each entry
+    int n;
+    int tiles, bands;      // totals over the entries
+    int tpe, bpe;          // tiles / bands of every entry when all are alike, else 0
+    int kmax, nty;         // largest K_max and band count (launch shapes)
+};
+
+// Entry holding flat index idx (base: prefix sums, n + 1 values; per: the
+// common count when every entry has the same, else 0).
+__device__ __forceinline__ int entry_of(const int *base, int per, int n, int idx) {
+    if (per > 0) return idx / per;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Past of entry i of a launch: the last earlier entry of the same sequence
+// whose stage errors are clear, else the sequence's past buffer.  Returns the
+// entry index, or -1 for the past buffer.
 __device__ __forceinline__ int past_slot(const Bufs *D, int i) {
+    const int q = D[i].seq;
     for (int j = i - 1; j >= 0; --j)
-        if (D[j].fs->err == 0) return j;
+        if (D[j].seq == q && D[j].fs->err == 0) return j;
     return -1;
 }
 
@@ -147,14 +178,13 @@ struct Prof {
     }
 };
 
-// Launchers.  H: host copy of a slot entry (sizes); D: device table of the
-// slot entries; n: frames in the batch (slots 0 .. n-1).
+// Launchers (all on stream s).
 // k_label.hip
-void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStream_t s, Prof &P);
+void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P);
 // k_voronoi.hip
-void launch_voronoi(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P);
-// k_diff.hip: comparison of every frame of the batch with its past, commit
-void launch_compare(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P);
+void launch_voronoi(const Batch &G, hipStream_t s, Prof &P);
+// k_diff.hip: comparison of every entry with its past, commit per sequence
+void launch_compare(const Batch &G, hipStream_t s, Prof &P);
 // inspection helpers (k_diff.hip); slot: the most recent frame
 void launch_phi_out(const Bufs &H, const Bufs *D, int slot, int32_t *d_out, hipStream_t s);
 void launch_edge_list(const Bufs &H, const Bufs *D, int32_t *d_out_ab, int32_t *d_count,

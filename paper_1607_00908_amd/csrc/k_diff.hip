@@ -22,8 +22,8 @@
 //             each by (a, b)).  Kept past and now points correspond one to
 //             one, so the number of dropped past points is
 //             K_past - (K_now - dropped now points).  The last block to
-//             finish commits the batch: the spare past buffer becomes the
-//             past when any frame of the batch was accepted.
+//             finish commits every sequence of the launch: its spare past
+//             buffer becomes the past when any of its frames was accepted.
 #include "dv_device.h"
 
 namespace {
@@ -51,7 +51,7 @@ __device__ __forceinline__ PastOf past_of(const Bufs *D, int i) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D) {
+__global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch G) {
     const Bufs &B = D[blockIdx.z];
     if (B.fs->err) return;
     const PastOf P = past_of(D, blockIdx.z);
@@ -72,8 +72,9 @@ __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int nb_frames) {
+__global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int s_red[2][4];
+    const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[i];
     FrameState *fs = B.fs;
@@ -83,10 +84,11 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int n
     const PastOf PO = past_of(Dt, i);
     const bool pv = PO.valid;
     const CompBuf P = PO.C, N = B.cur, Q = B.past[1 - B.st->sel];
-    // the batch's last accepted frame leaves its copy for the next batch
+    // the sequence's last accepted frame of the launch leaves its copy for the
+    // next launch
     bool keep = true;
     for (int q = i + 1; q < nb_frames; ++q)
-        if (Dt[q].fs->err == 0) keep = false;
+        if (Dt[q].seq == B.seq && Dt[q].fs->err == 0) keep = false;
     const int D = B.maxdeg;
     int e2 = 0, exn = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -172,13 +174,13 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, int n
     }
 }
 
-__global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, int nb_frames) {
+__global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int wsum[16];
     __shared__ int s_last;
+    const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[i];
     FrameState *fs = B.fs;
-    SeqState *st = B.st;
     const int t = threadIdx.x;
     if (fs->err) {
         if (t == 0) {
@@ -221,27 +223,39 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, int
             fs->global_trigger = (nbk + nar) > 0 ? 1 : 0;
         }
     }
-    // the last block to finish commits the batch (every block has read the
-    // sequence header by now)
+    // the last block to finish commits every sequence of the launch (every
+    // block has read the sequence headers by now); the ticket is kept in the
+    // first entry's header
     __syncthreads();
+    SeqState *tk = Dt[0].st;
     if (t == 0) {
         __threadfence();
-        s_last = atomicAdd(&st->done_place, 1) == nb_frames - 1;
+        s_last = atomicAdd(&tk->done_place, 1) == nb_frames - 1;
         if (s_last) __threadfence();
     }
     __syncthreads();
-    if (!s_last || t != 0) return;
-    st->done_place = 0;
-    int q = -1, acc = 0;
-    for (int k = 0; k < nb_frames; ++k)
-        if (Dt[k].fs->err == 0) { q = k; ++acc; }
-    if (q >= 0) {
-        const int nxt = 1 - st->sel;
-        st->K[nxt] = Dt[q].fs->K_now;
-        st->E[nxt] = Dt[q].fs->E2_acc / 2;
-        st->sel = nxt;
-        st->past_valid = 1;
-        st->frame += acc;
+    if (!s_last) return;
+    if (t == 0) tk->done_place = 0;
+    // thread k commits the sequence whose last entry in the launch is k
+    if (t < nb_frames) {
+        const int k = t, q = Dt[k].seq;
+        bool last = true;
+        for (int j = k + 1; j < nb_frames; ++j)
+            if (Dt[j].seq == q) last = false;
+        if (last) {
+            int a = -1, acc = 0;
+            for (int j = 0; j <= k; ++j)
+                if (Dt[j].seq == q && Dt[j].fs->err == 0) { a = j; ++acc; }
+            if (a >= 0) {
+                SeqState *sq = Dt[k].st;
+                const int nxt = 1 - sq->sel;
+                sq->K[nxt] = Dt[a].fs->K_now;
+                sq->E[nxt] = Dt[a].fs->E2_acc / 2;
+                sq->sel = nxt;
+                sq->past_valid = 1;
+                sq->frame += acc;
+            }
+        }
     }
 }
 
@@ -304,18 +318,18 @@ __global__ __launch_bounds__(256) void k_edge_write(const Bufs *__restrict__ D, 
 
 }  // namespace
 
-void launch_compare(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P) {
+void launch_compare(const Batch &G, hipStream_t s, Prof &P) {
     // one wave per point / row, grid-stride: a quarter of K_max waves per frame
-    // (K is usually well below K_max; a batch has up to 16 frames of them)
-    const int grid = (int)std::max<long long>(1, std::min<long long>((H.kmax + 15) / 16, 512));
+    // (K is usually well below K_max)
+    const int grid = (int)std::max<long long>(1, std::min<long long>((G.kmax + 15) / 16, 512));
     P.begin(ST_MATCH, s);
-    hipLaunchKernelGGL(k_match, dim3(grid, 1, n), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_match, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);
     P.end(ST_MATCH, s);
     P.begin(ST_DIFF, s);
-    hipLaunchKernelGGL(k_diff, dim3(grid, 1, n), dim3(256), 0, s, D, n);
+    hipLaunchKernelGGL(k_diff, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);
     P.end(ST_DIFF, s);
     P.begin(ST_PLACE, s);
-    hipLaunchKernelGGL(k_place, dim3(1, 1, n), dim3(1024), 0, s, D, n);
+    hipLaunchKernelGGL(k_place, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_PLACE, s);
 }
 

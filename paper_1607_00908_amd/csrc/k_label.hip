@@ -208,12 +208,14 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Fields F) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
+    const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
+    const Bufs &B = D[e];
     __shared__ int L[DV_TILE_SITES];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ int npc;
-    const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
+    const int tile = blockIdx.x - G.tbase[e];
+    const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x;
@@ -234,12 +236,12 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
     if (t < th) gmem(B.seg_mask)[(size_t)(y0 + t) * B.ntx + tx] = 0u;
     {   // empty the rows this frame will fill
         const size_t total = (size_t)fs->rows_dirty * B.maxdeg;
-        const size_t stride = (size_t)gridDim.x * gridDim.y * DV_BLOCK;
+        const size_t stride = (size_t)B.ncells * DV_BLOCK;
         auto adj = gmem(B.cur.adj);
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
-    tile_ccl(B, F.p[blockIdx.z], x0, y0, tw, th, L, rowm);
+    tile_ccl(B, F.p[e], x0, y0, tw, th, L, rowm);
 
     const int cx = t & 31, ry = t >> 5;
 #pragma unroll
@@ -307,11 +309,13 @@ __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], boo
     }
 }
 
-__global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch G) {
     // one wave per tile, four tiles per block
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= B.ncells) return;
+    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gt >= G.tiles) return;
+    const int e = entry_of(G.tbase, G.tpe, G.n, gt);
+    const Bufs &B = D[e];
+    const int tile = gt - G.tbase[e];
     const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
@@ -359,11 +363,12 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D) {
 // before each segment within the band, band_sum the band's total.
 // Segment (y, tile column c) covers sites y*lx + 32c .. 32c+31, so raster
 // order of segments is the row-major order of the [ly][ntx] arrays.
-__global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Batch G) {
+    const int e = entry_of(G.bbase, G.bpe, G.n, blockIdx.x);
+    const Bufs &B = D[e];
     __shared__ int pre[RES_TILES + 1];
     __shared__ int wsum[16];
-    const int ty = blockIdx.x, t = threadIdx.x;
+    const int ty = blockIdx.x - G.bbase[e], t = threadIdx.x;
     const int y0 = ty * DV_TILE, th = min(DV_TILE, B.ly - y0);
     const int ntx = B.ntx;
     for (int c0 = 0; c0 < ntx; c0 += RES_TILES) {
@@ -421,8 +426,9 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
     return v;
 }
 
-__global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
+    const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
+    const Bufs &B = D[e];
     __shared__ int L[DV_TILE_SITES];
     // per piece root (indexed by its tile-local site): rank, component root
     // (x | y << 16), integer sums
@@ -432,7 +438,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     __shared__ int wsum[16];
     extern __shared__ int boff[];   // [nty] roots in the bands before each band
     FrameState *fs = B.fs;
-    const int tx = blockIdx.x, ty = blockIdx.y, tile = ty * B.ntx + tx;
+    const int tile = blockIdx.x - G.tbase[e];
+    const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
@@ -454,7 +461,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     // roots in the bands before each band (exclusive prefix of band totals);
     // the first block publishes K and the capacity check
     const int K = block_exclusive_scan(B.band_sum, boff, B.nty, wsum);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+    if (tile == 0 && t == 0) {
         fs->K_now = K;
         if (K > B.kmax) atomicOr(&fs->err, DV_E_KMAX);
         fs->rows_dirty = min(K, B.kmax);
@@ -551,18 +558,17 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
 
 }  // namespace
 
-void launch_label(const Bufs &H, const Bufs *D, int n, const Fields &F, hipStream_t s, Prof &P) {
-    const dim3 tiles(H.ntx, H.nty, n);
+void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     P.begin(ST_TILE_CCL, s);
-    hipLaunchKernelGGL(k_tile_ccl, tiles, dim3(DV_BLOCK), 0, s, D, F);
+    hipLaunchKernelGGL(k_tile_ccl, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
-    hipLaunchKernelGGL(k_merge, dim3((H.ncells + 3) / 4, 1, n), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_merge, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
-    hipLaunchKernelGGL(k_resolve, dim3(H.nty, 1, n), dim3(1024), 0, s, D);
+    hipLaunchKernelGGL(k_resolve, dim3(G.bands), dim3(1024), 0, s, G.D, G);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    hipLaunchKernelGGL(k_relabel, tiles, dim3(DV_BLOCK), H.nty * sizeof(int), s, D);
+    hipLaunchKernelGGL(k_relabel, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
     P.end(ST_RELABEL, s);
 }

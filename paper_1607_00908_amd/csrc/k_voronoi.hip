@@ -26,7 +26,7 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
     return r < 0 ? r + m : r;
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D) {
+__global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, Batch G) {
     const Bufs &B = D[blockIdx.z];
     __shared__ int wsum[16];
     __shared__ int s_last;
@@ -229,14 +229,16 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
 
 // Six resident blocks per CU (register budget 85): the block's gather and
 // barrier-bounded phases are latency chains that other resident blocks fill.
-__global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
+    const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
+    const Bufs &B = D[e];
+    const int tile = blockIdx.x - G.tbase[e];
     __shared__ OwnerLds S;
     FrameState *fs = B.fs;
     if (fs->err) return;
     const int K = fs->K_now;
     gint *adj = gmem(B.cur.adj);
-    const int tx = blockIdx.x % B.ntx, ty = blockIdx.x / B.ntx;
+    const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int W = tw + 2, H = th + 2;
@@ -553,7 +555,6 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     // --- distinct couples of the tile go to its list (k_rows fills the rows);
     // beyond the list's capacity they go into the rows directly
     const int np = min(S.npair, PAIR_CAP);
-    const int tile = blockIdx.x;
     for (int i = t; i < np; i += DV_BLOCK) {
         const unsigned long long key = S.pair[i];
         bool first = true;
@@ -575,12 +576,14 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
 
 // Rows from the tiles' couple lists: one wave per tile, one lane per couple
 // end.  Rows are sets: a couple found by several tiles is stored once.
-__global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D) {
-    const Bufs &B = D[blockIdx.z];
+__global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D, Batch G) {
+    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (gt >= G.tiles) return;
+    const int e = entry_of(G.tbase, G.tpe, G.n, gt);
+    const Bufs &B = D[e];
+    const int tile = gt - G.tbase[e];
     FrameState *fs = B.fs;
     if (fs->err) return;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (tile >= B.ncells) return;
     const int n = gmem(B.tpair_n)[tile];
     gint *adj = gmem(B.cur.adj);
     for (int j = lane; j < 2 * n; j += 64) {
@@ -592,15 +595,15 @@ __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D) {
 
 }  // namespace
 
-void launch_voronoi(const Bufs &H, const Bufs *D, int n, hipStream_t s, Prof &P) {
-    const int fgrid = (int)std::min<long long>((H.kmax + 1023) / 1024, 256);
+void launch_voronoi(const Batch &G, hipStream_t s, Prof &P) {
+    const int fgrid = (int)std::min<long long>((G.kmax + 1023) / 1024, 256);
     P.begin(ST_FINALIZE, s);
-    hipLaunchKernelGGL(k_finalize, dim3(fgrid, 1, n), dim3(1024), 0, s, D);
+    hipLaunchKernelGGL(k_finalize, dim3(fgrid, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_FINALIZE, s);
     P.begin(ST_OWNER_EDGES, s);
-    hipLaunchKernelGGL(k_owner_edges, dim3(H.ncells, 1, n), dim3(DV_BLOCK), 0, s, D);
+    hipLaunchKernelGGL(k_owner_edges, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
     P.end(ST_OWNER_EDGES, s);
     P.begin(ST_ROWS, s);
-    hipLaunchKernelGGL(k_rows, dim3((H.ncells + 3) / 4, 1, n), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_rows, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
     P.end(ST_ROWS, s);
 }
