@@ -166,6 +166,27 @@ dv_status dv_get_edges(dv_ctx *ctx, int32_t *ab, int32_t capacity, int32_t *n_ou
  * past points; *n_out = K of the past frame (0 for the first frame). */
 dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *n_out);
 
+/* ---- groups: many independent fields in one launch per stage ---- */
+
+/* A group sends one frame of each of its members to the device together:
+ * every stage is one launch over all members' frames, whatever their lattice
+ * sizes (a flat work list of tiles).  Members are contexts made by dv_create
+ * with the same device and the same hip_stream; each keeps its own past,
+ * outputs and getters, which see the group's frames like pushed ones.
+ * 1 <= n <= 64.  The group borrows the members: they must outlive it.  On
+ * failure *out is NULL and nothing is allocated. */
+typedef struct dv_group dv_group;
+dv_status dv_group_create(dv_ctx *const *members, int32_t n, dv_group **out);
+
+/* Push fields_device[i] (lx*ly float32 of member i, device memory) into member
+ * i for every member, and send them to the device at once (frames a member
+ * had queued go first).  Asynchronous like dv_push_frame; the fields follow
+ * the same lifetime rule (until the next synchronising call on the member). */
+dv_status dv_group_push(dv_group *g, const float *const *fields_device);
+
+/* Release the group (not its members).  NULL is accepted. */
+void dv_group_destroy(dv_group *g);
+
 /* ---- measurement ---- */
 
 /* Stages of the per-frame procedure, in launch order. */

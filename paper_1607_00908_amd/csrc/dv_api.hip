@@ -494,6 +494,110 @@ dv_status dv_get_profile(dv_ctx *c, double *total_ms, int32_t *launches) {
     return DV_OK;
 }
 
+// ---- groups -----------------------------------------------------------------
+
+struct dv_group {
+    int n;
+    int device;
+    hipStream_t stream;
+    dv_ctx *m[DV_MAX_ENTRIES];
+    Bufs *d_tab;             // members' slot 0, sequence i for member i
+    int *d_tbase, *d_bbase;
+    Batch G;                 // launch descriptor (without the field pointers)
+    Prof prof;               // never enabled
+};
+
+dv_status dv_group_create(dv_ctx *const *members, int32_t n, dv_group **out) {
+    if (!out) return fail(nullptr, DV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!members || n < 1 || n > DV_MAX_ENTRIES)
+        return fail(nullptr, DV_ERR_ARG, "a group has 1 .. 64 members");
+    for (int i = 0; i < n; ++i) {
+        if (!members[i]) return fail(nullptr, DV_ERR_ARG, "member is NULL");
+        if (members[i]->device != members[0]->device || members[i]->stream != members[0]->stream)
+            return fail(nullptr, DV_ERR_ARG, "members must share the device and the stream");
+    }
+    dv_group *g = new dv_group();
+    g->n = n;
+    g->device = members[0]->device;
+    g->stream = members[0]->stream;
+    (void)hipSetDevice(g->device);
+    std::vector<Bufs> tab(n);
+    std::vector<int> tb(n + 1), bb(n + 1);
+    int kmax = 0, nty = 0;
+    tb[0] = bb[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        g->m[i] = members[i];
+        tab[i] = members[i]->h_tab[0];
+        tab[i].seq = i;
+        tb[i + 1] = tb[i] + tab[i].ncells;
+        bb[i + 1] = bb[i] + tab[i].nty;
+        kmax = std::max(kmax, tab[i].kmax);
+        nty = std::max(nty, tab[i].nty);
+    }
+    bool ok = hipMalloc(&g->d_tab, sizeof(Bufs) * n) == hipSuccess &&
+              hipMalloc(&g->d_tbase, sizeof(int) * (n + 1)) == hipSuccess &&
+              hipMalloc(&g->d_bbase, sizeof(int) * (n + 1)) == hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(g->d_tab, tab.data(), sizeof(Bufs) * n, hipMemcpyHostToDevice, g->stream) == hipSuccess &&
+         hipMemcpyAsync(g->d_tbase, tb.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, g->stream) == hipSuccess &&
+         hipMemcpyAsync(g->d_bbase, bb.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, g->stream) == hipSuccess &&
+         hipStreamSynchronize(g->stream) == hipSuccess;
+    if (!ok) {
+        dv_group_destroy(g);
+        return fail(nullptr, DV_ERR_NOMEM, "group allocation failed");
+    }
+    bool alike = true;
+    for (int i = 1; i < n; ++i) alike = alike && tab[i].ncells == tab[0].ncells && tab[i].nty == tab[0].nty;
+    Batch &G = g->G;
+    G.D = g->d_tab;
+    G.tbase = g->d_tbase;
+    G.bbase = g->d_bbase;
+    G.n = n;
+    G.tiles = tb[n];
+    G.bands = bb[n];
+    G.tpe = alike ? tab[0].ncells : 0;
+    G.bpe = alike ? tab[0].nty : 0;
+    G.kmax = kmax;
+    G.nty = nty;
+    *out = g;
+    return DV_OK;
+}
+
+dv_status dv_group_push(dv_group *g, const float *const *fields) {
+    if (!g || !fields) return DV_ERR_ARG;
+    for (int i = 0; i < g->n; ++i)
+        if (!fields[i]) return fail(g->m[i], DV_ERR_ARG, "field is NULL");
+    (void)hipSetDevice(g->device);
+    Fields F;
+    std::memset(&F, 0, sizeof(F));
+    for (int i = 0; i < g->n; ++i) {
+        dv_status s = flush(g->m[i]);
+        if (s != DV_OK) return s;
+        F.p[i] = fields[i];
+    }
+    launch_label(g->G, F, g->stream, g->prof);
+    launch_voronoi(g->G, g->stream, g->prof);
+    launch_compare(g->G, g->stream, g->prof);
+    const hipError_t e = hipGetLastError();
+    for (int i = 0; i < g->n; ++i) {
+        g->m[i]->last = 0;
+        g->m[i]->pushed = true;
+        if (e != hipSuccess) fail(g->m[i], DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    }
+    return e == hipSuccess ? DV_OK : DV_ERR_DEVICE;
+}
+
+void dv_group_destroy(dv_group *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    (void)hipStreamSynchronize(g->stream);
+    if (g->d_tab) (void)hipFree(g->d_tab);
+    if (g->d_tbase) (void)hipFree(g->d_tbase);
+    if (g->d_bbase) (void)hipFree(g->d_bbase);
+    delete g;
+}
+
 const char *dv_status_str(dv_status s) {
     switch (s) {
         case DV_OK: return "ok";

@@ -66,6 +66,16 @@ __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, B
             B.inv[k] = -1;
         }
         if (namb) atomicAdd(&fs->n_amb, namb);
+    } else {
+        // a rejected frame still leaves the sums it accumulated (ranks below
+        // K_max) empty for the next frame
+        const int KK = min(K, B.kmax);
+        for (int k = blockIdx.x * blockDim.x + t; k < KK; k += gridDim.x * blockDim.x) {
+            B.acc_n[k] = 0;
+            B.acc_x[k] = 0;
+            B.acc_y[k] = 0;
+            B.acc_amb[k] = 0;
+        }
     }
     // the last block to finish sees every count and builds the grid
     // release: the barrier completes the block's stores, one thread writes

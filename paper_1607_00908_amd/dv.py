@@ -27,8 +27,8 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 # every entry point declared in include/dv.h
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
-           "dv_get_matching", "dv_set_profile", "dv_get_profile", "dv_stage_name",
-           "dv_status_str", "dv_last_error")
+           "dv_get_matching", "dv_group_create", "dv_group_push", "dv_group_destroy",
+           "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
 DEFAULT_BATCH = 16   # what max_batch = 0 selects
 
@@ -98,6 +98,12 @@ def load(path: str = LIB_PATH):
     lib.dv_get_edges.argtypes = [vp, vp, i32, i32p]
     lib.dv_get_matching.restype = i32
     lib.dv_get_matching.argtypes = [vp, vp, i32, i32p]
+    lib.dv_group_create.restype = i32
+    lib.dv_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.dv_group_push.restype = i32
+    lib.dv_group_push.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.dv_group_destroy.restype = None
+    lib.dv_group_destroy.argtypes = [vp]
     lib.dv_set_profile.restype = i32
     lib.dv_set_profile.argtypes = [vp, i32, i32]
     lib.dv_get_profile.restype = i32
@@ -286,3 +292,57 @@ class Detector:
         out = np.zeros(max(n.value, 1), dtype=np.int32)
         self._check(self.lib.dv_get_matching(self.h, _ptr(out), n.value, ctypes.byref(n)))
         return out[:n.value]
+
+
+class Group:
+    """Frames of several detectors sent to the device together: one launch per
+    stage for all of them, whatever their lattice sizes.  The detectors must be
+    on one device and share one stream (pass the same ``stream`` to each);
+    each keeps its own past and getters."""
+
+    def __init__(self, detectors):
+        self.lib = load()
+        self.members = list(detectors)
+        n = len(self.members)
+        arr = (ctypes.c_void_p * n)(*[d.h.value for d in self.members])
+        h = ctypes.c_void_p()
+        st = self.lib.dv_group_create(arr, n, ctypes.byref(h))
+        if st != OK:
+            raise DVError(st, self.lib.dv_last_error(None).decode())
+        self.h = h
+
+    def push(self, fields) -> None:
+        """One float32 device tensor [ly, lx] (contiguous) per member, or raw
+        device pointers (int)."""
+        if len(fields) != len(self.members):
+            raise ValueError("one field per member")
+        ptrs = []
+        for d, f in zip(self.members, fields):
+            if isinstance(f, int):
+                ptrs.append(f)
+                continue
+            if not (f.is_cuda and f.dtype == d._torch.float32):
+                raise TypeError("fields must be float32 device tensors")
+            if tuple(f.shape) != (d.ly, d.lx) or not f.is_contiguous():
+                raise ValueError(f"field must be contiguous with shape ({d.ly}, {d.lx})")
+            cur = d._torch.cuda.current_stream(d.device)
+            if cur.cuda_stream != d.stream.cuda_stream:
+                d.stream.wait_stream(cur)
+                f.record_stream(d.stream)
+            d._field_refs.append(f)
+            ptrs.append(f.data_ptr())
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        st = self.lib.dv_group_push(self.h, arr)
+        if st != OK:
+            raise DVError(st, self.lib.dv_last_error(self.members[0].h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dv_group_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -74,3 +74,17 @@ def test_null_arguments():
     assert lib.dv_get_flips(None, None, 0, ctypes.byref(n)) == dv.ERR_ARG
     lib.dv_destroy(None)   # NULL-safe
     assert lib.dv_status_str(2) == b"capacity exceeded"
+
+
+def test_group_arguments_are_checked_on_the_host():
+    lib = dv.load()
+    h = ctypes.c_void_p()
+    assert lib.dv_group_create(None, 1, ctypes.byref(h)) == dv.ERR_ARG
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.dv_group_create(arr, 1, ctypes.byref(h)) == dv.ERR_ARG
+    assert lib.dv_group_create(arr, 0, ctypes.byref(h)) == dv.ERR_ARG
+    assert lib.dv_group_create(arr, 65, ctypes.byref(h)) == dv.ERR_ARG
+    assert lib.dv_group_create(arr, 1, None) == dv.ERR_ARG
+    assert not h.value
+    assert lib.dv_group_push(None, None) == dv.ERR_ARG
+    lib.dv_group_destroy(None)

@@ -178,6 +178,8 @@ def test_capacity_rejection_keeps_the_past():
     ref = oracle.compare(fa, fc)
     assert np.array_equal(got, ref.flips)
     assert det.info().frame == 2
+    # the rejected frame leaves no trace in the next frame's sums
+    check_frame(det, fc, ref, 120, 100)
     det.close()
 
 
@@ -225,6 +227,83 @@ def test_rejection_inside_a_batch():
     ref = oracle.compare(oracle.frame(d, 0.5), oracle.frame(b, 0.5))
     assert np.array_equal(det.flips(), ref.flips)
     det.close()
+
+
+def _group(sizes, kmax=512, max_batch=2):
+    stream = torch.cuda.Stream()
+    dets = [dv.Detector(lx, ly, 0.5, max_components=kmax, max_batch=max_batch, stream=stream)
+            for lx, ly in sizes]
+    return dets, dv.Group(dets)
+
+
+def test_group_of_uneven_lattices_matches_the_oracle():
+    """Five sequences of different lattice sizes go through one launch per
+    stage; every member's frame equals the oracle's."""
+    sizes = [(64, 64), (100, 70), (200, 160), (33, 97), (256, 256)]
+    sims = [synth.DiskSim(lx, ly, max(3, lx * ly // 2500), 3.0, 6.0, 0.6, 3e-3, seed=700 + i)
+            for i, (lx, ly) in enumerate(sizes)]
+    frames = [list(sm.frames(4)) for sm in sims]
+    dets, grp = _group(sizes)
+    seqs = [oracle.Sequence(0.5, 0, 8, NTHREADS) for _ in sizes]
+    for k in range(4):
+        say(f"  [group] frame {k}")
+        grp.push([torch.from_numpy(frames[i][k]).cuda() for i in range(len(sizes))])
+        for i, (lx, ly) in enumerate(sizes):
+            now, ref = seqs[i].push(frames[i][k])
+            check_frame(dets[i], now, ref, lx, ly)
+    grp.close()
+    for d in dets:
+        d.close()
+
+
+def test_group_bursts_and_single_pushes_mix():
+    """Group pushes without synchronisation, interleaved with pushes of single
+    members; each member's last comparison equals the oracle's."""
+    sizes = [(96, 80), (130, 150), (64, 200)]
+    sims = [synth.DiskSim(lx, ly, 10, 3.0, 6.0, 0.6, 3e-3, seed=800 + i)
+            for i, (lx, ly) in enumerate(sizes)]
+    frames = [list(sm.frames(6)) for sm in sims]
+    dev = [[torch.from_numpy(f).cuda() for f in fr] for fr in frames]
+    dets, grp = _group(sizes, max_batch=3)
+    for k in range(3):
+        grp.push([dev[i][k] for i in range(3)])
+    dets[1].push(dev[1][3])                 # member 1 alone
+    for k in (4, 5):
+        grp.push([dev[0][k], dev[1][k], dev[2][k]])
+    for i, (lx, ly) in enumerate(sizes):
+        order = [0, 1, 2, 3, 4, 5] if i == 1 else [0, 1, 2, 4, 5]
+        seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
+        for k in order:
+            now, ref = seq.push(frames[i][k])
+        check_frame(dets[i], now, ref, lx, ly)
+        assert dets[i].info().frame == len(order)
+    grp.close()
+    for d in dets:
+        d.close()
+
+
+def test_group_member_rejection_is_isolated():
+    """A frame over one member's K_max is rejected for that member only."""
+    sizes = [(120, 100), (120, 100), (90, 110)]
+    sims = [synth.DiskSim(lx, ly, 12, 4.0, 6.0, 0.8, 2e-3, seed=900 + i)
+            for i, (lx, ly) in enumerate(sizes)]
+    frames = [list(sm.frames(3)) for sm in sims]
+    noise = (synth.tiny_random_field(120, 100, 6) > 0.85).astype(np.float32)
+    dets, grp = _group(sizes, kmax=64)
+    grp.push([torch.from_numpy(frames[i][0]).cuda() for i in range(3)])
+    grp.push([torch.from_numpy(frames[0][1]).cuda(), torch.from_numpy(noise).cuda(),
+              torch.from_numpy(frames[2][1]).cuda()])
+    assert dets[0].info().status == 0 and dets[2].info().status == 0
+    assert dets[1].info().status == dv.ERR_CAPACITY
+    grp.push([torch.from_numpy(frames[i][2]).cuda() for i in range(3)])
+    for i in range(3):
+        past = frames[i][0] if i == 1 else frames[i][1]
+        ref = oracle.compare(oracle.frame(past, 0.5), oracle.frame(frames[i][2], 0.5))
+        assert np.array_equal(dets[i].flips(), ref.flips), i
+    assert dets[1].info().frame == 2 and dets[0].info().frame == 3
+    grp.close()
+    for d in dets:
+        d.close()
 
 
 def test_degree_overflow_is_reported():
