@@ -1,6 +1,7 @@
 """Benchmark of the per-frame detection path on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload disks1024]
+python bench.py --workload mixed64 [--fields 64] [--frames 5] [--steps 20]
 
 A step is one frame through the whole path (threshold, labelling, centres,
 digital Voronoi, Delaunay couples, matching, flips) on synthetic input of the
@@ -166,6 +167,93 @@ def unbatched_rate(dv, args, spec, lx, ly, kmax, maps, stream, ptrs, F, N):
             "ms_per_step": round(1e3 * el1 / n1, 5), "steps": n1}
 
 
+def _mixed_frames(args):
+    """Frames of field i of the mixed batch (runs in a worker process)."""
+    i, n, nf = args
+    from paper_1607_00908_amd import synth
+    sim, spec = synth.mixed_fields(n)[i]
+    return list(sim.frames(nf)), spec
+
+
+def bench_mixed(args):
+    """Batching of many independent fields: one group launch per stage for all
+    fields against the same frames pushed field by field with one launch per
+    stage each.  Prints one JSON line."""
+    import concurrent.futures as cf
+    import torch
+    from paper_1607_00908_amd import dv
+    n, nf = args.fields, args.frames or 5
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(_mixed_frames, [(i, n, nf) for i in range(n)]))
+    log(f"generated {n} fields x {nf} frames in {time.perf_counter() - t0:.1f} s")
+    specs = [sp for _, sp in res]
+    sites = sum(sp["lx"] * sp["ly"] for sp in specs)
+    rings = [torch.from_numpy(np.stack(fr)).cuda() for fr, _ in res]
+    torch.cuda.synchronize()
+    ptrs = [[r[k].data_ptr() for k in range(nf)] for r in rings]
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    def make():
+        return [dv.Detector(sp["lx"], sp["ly"], sp["threshold"], sp["phase"], 8,
+                            max_components=4 * sp["k_expect"] + 256, keep_maps=True,
+                            max_batch=1, stream=stream) for sp in specs]
+
+    # one launch per stage for all fields
+    dets = make()
+    grp = dv.Group(dets)
+    for w in range(args.warmup):
+        grp.push([p[w % nf] for p in ptrs])
+    for d in dets:
+        d.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        grp.push([p[(args.warmup + k) % nf] for p in ptrs])
+    for d in dets:
+        d.sync()
+    el_g = time.perf_counter() - t1
+    infos = [d.info() for d in dets]
+    assert all(fi.status == 0 for fi in infos), [fi.status for fi in infos]
+    grp.close()
+    for d in dets:
+        d.close()
+    # the same frames, field by field (one launch per stage per field)
+    dets = make()
+    for w in range(args.warmup):
+        for d, p in zip(dets, ptrs):
+            d.push(p[w % nf])
+    for d in dets:
+        d.sync()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        for d, p in zip(dets, ptrs):
+            d.push(p[(args.warmup + k) % nf])
+    for d in dets:
+        d.sync()
+    el_s = time.perf_counter() - t1
+    for d in dets:
+        d.close()
+    v_g = sites * args.steps / el_g / 1e6
+    v_s = sites * args.steps / el_s / 1e6
+    print(json.dumps({
+        "metric": f"Msites/s, {n} independent fields of uneven sizes, one launch per stage for all",
+        "value": round(v_g, 2), "unit": "Msites/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el_g / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32->int64",
+        "data": "synthetic",
+        "config": {"workload": f"mixed{n}", "fields": n, "frames_in_ring": nf,
+                   "sites_per_step": sites, "side_min": min(sp["lx"] for sp in specs),
+                   "side_max": max(sp["lx"] for sp in specs),
+                   "disk_fields": sum(1 for sp in specs if sp["kind"] == "disks"),
+                   "components": sum(fi.n_components for fi in infos),
+                   "parallelism": "single-gpu"},
+        "field_by_field": {"value": round(v_s, 2), "unit": "Msites/s",
+                           "ms_per_step": round(1e3 * el_s / args.steps, 4)},
+        "speedup": round(v_g / v_s, 3)}))
+
+
 def make_frames(workload: str, frames: int | None):
     from paper_1607_00908_amd import synth
     sim, spec = synth.workload(workload)
@@ -200,6 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--workload", default="disks1024")
     ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
+    ap.add_argument("--fields", type=int, default=64, help="fields of the mixed workload")
     ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
     ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
     ap.add_argument("--max-batch", type=int, default=0,
@@ -224,6 +313,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("bench.py measures one GPU only (no multi-GPU path in this build)")
         sys.exit(2)
+    if args.workload.startswith("mixed"):
+        if args.steps == 1600:
+            args.steps = 20
+        bench_mixed(args)
+        return
 
     import torch
     from paper_1607_00908_amd import dv

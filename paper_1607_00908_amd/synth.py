@@ -34,6 +34,7 @@ __all__ = [
     "disk_field",
     "workload",
     "WORKLOADS",
+    "mixed_fields",
 ]
 
 
@@ -258,3 +259,26 @@ def workload(name: str, **override):
     else:
         raise ValueError(spec["kind"])
     return sim, spec
+
+
+def mixed_fields(n: int = 64, seed: int = 4, l_min: int = 256, l_max: int = 2048):
+    """Independent sequences of uneven sizes for one batch: square sides
+    log-uniform in [l_min, l_max], half disk emulsions (1000 disks per 1024^2,
+    radii U(10,16), jitter 0.2, shear 5e-4, threshold 0.5), half random fields
+    (smoothing 6, AR(1) 0.98, threshold +1 std).  Returns [(sim, spec)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = int(round(np.exp(rng.uniform(np.log(l_min), np.log(l_max)))))
+        if rng.random() < 0.5:
+            nd = max(4, int(round(1000 * L * L / 1024 ** 2)))
+            spec = dict(kind="disks", lx=L, ly=L, n_disks=nd, r_min=10.0, r_max=16.0, sigma=0.2,
+                        shear=5e-4, seed=seed * 1000 + i, threshold=0.5, phase=0,
+                        k_expect=nd)
+            sim = DiskSim(L, L, nd, 10.0, 16.0, 0.2, 5e-4, spec["seed"])
+        else:
+            spec = dict(kind="grf", lx=L, ly=L, sigma=6.0, rho=0.98, seed=seed * 1000 + i,
+                        threshold=1.0, phase=0, k_expect=int(9000 * L * L / 4096 ** 2) + 16)
+            sim = GRFSim(L, L, 6.0, 0.98, spec["seed"])
+        out.append((sim, spec))
+    return out

@@ -256,6 +256,28 @@ def test_group_of_uneven_lattices_matches_the_oracle():
         d.close()
 
 
+def test_group_of_mixed_fields_matches_the_oracle():
+    """The batching workload's generator at small sides: disk and random-field
+    sequences with their own thresholds in one group, three frames."""
+    fields = synth.mixed_fields(6, seed=5, l_min=64, l_max=200)
+    stream = torch.cuda.Stream()
+    dets = [dv.Detector(sp["lx"], sp["ly"], sp["threshold"], sp["phase"], 8,
+                        max_components=4 * sp["k_expect"] + 256, max_batch=1, stream=stream)
+            for _, sp in fields]
+    grp = dv.Group(dets)
+    frames = [list(sm.frames(3)) for sm, _ in fields]
+    seqs = [oracle.Sequence(sp["threshold"], sp["phase"], 8, NTHREADS) for _, sp in fields]
+    for k in range(3):
+        say(f"  [mixed group] frame {k}")
+        grp.push([torch.from_numpy(frames[i][k]).cuda() for i in range(len(fields))])
+        for i, (_, sp) in enumerate(fields):
+            now, ref = seqs[i].push(frames[i][k])
+            check_frame(dets[i], now, ref, sp["lx"], sp["ly"])
+    grp.close()
+    for d in dets:
+        d.close()
+
+
 def test_group_bursts_and_single_pushes_mix():
     """Group pushes without synchronisation, interleaved with pushes of single
     members; each member's last comparison equals the oracle's."""
