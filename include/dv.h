@@ -184,6 +184,13 @@ dv_status dv_group_create(dv_ctx *const *members, int32_t n, dv_group **out);
  * the same lifetime rule (until the next synchronising call on the member). */
 dv_status dv_group_push(dv_group *g, const float *const *fields_device);
 
+/* Push fields_device[i] into member members[i] for i < n (distinct members,
+ * 1 <= n <= group size, any order) and send them at once: a launch over the
+ * members that have a frame, the others untouched (continuous batching of
+ * streams whose frames arrive at different times). */
+dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *const *fields_device,
+                             int32_t n);
+
 /* Release the group (not its members).  NULL is accepted. */
 void dv_group_destroy(dv_group *g);
 

@@ -29,8 +29,6 @@ struct dv_ctx {
     int batch;               // frames per launch
     Bufs h_tab[DV_MAX_BATCH];  // host copy of the slot table
     Bufs *d_tab;             // device slot table
-    int *d_tbase, *d_bbase;  // prefix sums of tiles / bands over the slots
-    int h_tbase[DV_MAX_BATCH + 1], h_bbase[DV_MAX_BATCH + 1];
     Fields pending;          // queued field pointers
     int npending;
     int last;                // slot of the most recent frame sent to the device
@@ -79,10 +77,14 @@ dv_status flush(dv_ctx *c) {
     if (n == 0) return DV_OK;
     const Bufs &H = c->h_tab[0];
     Batch G;
+    std::memset(&G, 0, sizeof(G));
     G.D = c->d_tab;
-    G.tbase = c->d_tbase;
-    G.bbase = c->d_bbase;
     G.n = n;
+    for (int i = 0; i < n; ++i) G.idx[i] = i;
+    for (int i = 0; i <= n; ++i) {
+        G.tbase[i] = i * H.ncells;
+        G.bbase[i] = i * H.nty;
+    }
     G.tiles = n * H.ncells;
     G.bands = n * H.nty;
     G.tpe = H.ncells;
@@ -194,8 +196,6 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     c->h_state = nullptr;
     c->h_frame = nullptr;
     c->d_tab = nullptr;
-    c->d_tbase = nullptr;
-    c->d_bbase = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -233,8 +233,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
                dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
     };
     bool ok = dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
-              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_tbase, DV_MAX_BATCH + 1) &&
-              dalloc(c, &c->d_bbase, DV_MAX_BATCH + 1) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
+              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
               dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
     // per-slot buffers
     for (int k = 0; ok && k < c->batch; ++k) {
@@ -266,15 +265,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     }
     // initial contents: slot table, zero accumulators and headers, empty rows
     hipStream_t s0 = c->stream;
-    for (int k = 0; k <= DV_MAX_BATCH; ++k) {
-        c->h_tbase[k] = k * B.ncells;
-        c->h_bbase[k] = k * B.nty;
-    }
     bool z = hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(Bufs) * c->batch, hipMemcpyHostToDevice, s0) ==
-                 hipSuccess &&
-             hipMemcpyAsync(c->d_tbase, c->h_tbase, sizeof(c->h_tbase), hipMemcpyHostToDevice, s0) ==
-                 hipSuccess &&
-             hipMemcpyAsync(c->d_bbase, c->h_bbase, sizeof(c->h_bbase), hipMemcpyHostToDevice, s0) ==
                  hipSuccess &&
              hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
     for (int b = 0; z && b < 2; ++b)
@@ -501,10 +492,9 @@ struct dv_group {
     int device;
     hipStream_t stream;
     dv_ctx *m[DV_MAX_ENTRIES];
-    Bufs *d_tab;             // members' slot 0, sequence i for member i
-    int *d_tbase, *d_bbase;
-    Batch G;                 // launch descriptor (without the field pointers)
-    Prof prof;               // never enabled
+    Bufs h_tab[DV_MAX_ENTRIES];  // members' slot 0, sequence i for member i
+    Bufs *d_tab;
+    Prof prof;                   // never enabled
 };
 
 dv_status dv_group_create(dv_ctx *const *members, int32_t n, dv_group **out) {
@@ -521,71 +511,78 @@ dv_status dv_group_create(dv_ctx *const *members, int32_t n, dv_group **out) {
     g->n = n;
     g->device = members[0]->device;
     g->stream = members[0]->stream;
+    g->d_tab = nullptr;
     (void)hipSetDevice(g->device);
-    std::vector<Bufs> tab(n);
-    std::vector<int> tb(n + 1), bb(n + 1);
-    int kmax = 0, nty = 0;
-    tb[0] = bb[0] = 0;
     for (int i = 0; i < n; ++i) {
         g->m[i] = members[i];
-        tab[i] = members[i]->h_tab[0];
-        tab[i].seq = i;
-        tb[i + 1] = tb[i] + tab[i].ncells;
-        bb[i + 1] = bb[i] + tab[i].nty;
-        kmax = std::max(kmax, tab[i].kmax);
-        nty = std::max(nty, tab[i].nty);
+        g->h_tab[i] = members[i]->h_tab[0];
+        g->h_tab[i].seq = i;
     }
-    bool ok = hipMalloc(&g->d_tab, sizeof(Bufs) * n) == hipSuccess &&
-              hipMalloc(&g->d_tbase, sizeof(int) * (n + 1)) == hipSuccess &&
-              hipMalloc(&g->d_bbase, sizeof(int) * (n + 1)) == hipSuccess;
-    ok = ok &&
-         hipMemcpyAsync(g->d_tab, tab.data(), sizeof(Bufs) * n, hipMemcpyHostToDevice, g->stream) == hipSuccess &&
-         hipMemcpyAsync(g->d_tbase, tb.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, g->stream) == hipSuccess &&
-         hipMemcpyAsync(g->d_bbase, bb.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, g->stream) == hipSuccess &&
-         hipStreamSynchronize(g->stream) == hipSuccess;
+    const bool ok = hipMalloc(&g->d_tab, sizeof(Bufs) * n) == hipSuccess &&
+                    hipMemcpyAsync(g->d_tab, g->h_tab, sizeof(Bufs) * n, hipMemcpyHostToDevice,
+                                   g->stream) == hipSuccess &&
+                    hipStreamSynchronize(g->stream) == hipSuccess;
     if (!ok) {
         dv_group_destroy(g);
         return fail(nullptr, DV_ERR_NOMEM, "group allocation failed");
     }
-    bool alike = true;
-    for (int i = 1; i < n; ++i) alike = alike && tab[i].ncells == tab[0].ncells && tab[i].nty == tab[0].nty;
-    Batch &G = g->G;
-    G.D = g->d_tab;
-    G.tbase = g->d_tbase;
-    G.bbase = g->d_bbase;
-    G.n = n;
-    G.tiles = tb[n];
-    G.bands = bb[n];
-    G.tpe = alike ? tab[0].ncells : 0;
-    G.bpe = alike ? tab[0].nty : 0;
-    G.kmax = kmax;
-    G.nty = nty;
     *out = g;
     return DV_OK;
 }
 
-dv_status dv_group_push(dv_group *g, const float *const *fields) {
-    if (!g || !fields) return DV_ERR_ARG;
-    for (int i = 0; i < g->n; ++i)
-        if (!fields[i]) return fail(g->m[i], DV_ERR_ARG, "field is NULL");
+dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *const *fields,
+                             int32_t n) {
+    if (!g || !members || !fields || n < 1 || n > g->n) return DV_ERR_ARG;
+    bool seen[DV_MAX_ENTRIES] = {false};
+    for (int i = 0; i < n; ++i) {
+        const int k = members[i];
+        if (k < 0 || k >= g->n || seen[k]) return DV_ERR_ARG;
+        seen[k] = true;
+        if (!fields[i]) return fail(g->m[k], DV_ERR_ARG, "field is NULL");
+    }
     (void)hipSetDevice(g->device);
     Fields F;
     std::memset(&F, 0, sizeof(F));
-    for (int i = 0; i < g->n; ++i) {
-        dv_status s = flush(g->m[i]);
+    Batch G;
+    std::memset(&G, 0, sizeof(G));
+    G.D = g->d_tab;
+    G.n = n;
+    bool alike = true;
+    for (int i = 0; i < n; ++i) {
+        const int k = members[i];
+        dv_status s = flush(g->m[k]);
         if (s != DV_OK) return s;
+        const Bufs &b = g->h_tab[k];
         F.p[i] = fields[i];
+        G.idx[i] = k;
+        G.tbase[i + 1] = G.tbase[i] + b.ncells;
+        G.bbase[i + 1] = G.bbase[i] + b.nty;
+        G.kmax = std::max(G.kmax, b.kmax);
+        G.nty = std::max(G.nty, b.nty);
+        alike = alike && b.ncells == g->h_tab[members[0]].ncells && b.nty == g->h_tab[members[0]].nty;
     }
-    launch_label(g->G, F, g->stream, g->prof);
-    launch_voronoi(g->G, g->stream, g->prof);
-    launch_compare(g->G, g->stream, g->prof);
+    G.tiles = G.tbase[n];
+    G.bands = G.bbase[n];
+    G.tpe = alike ? g->h_tab[members[0]].ncells : 0;
+    G.bpe = alike ? g->h_tab[members[0]].nty : 0;
+    launch_label(G, F, g->stream, g->prof);
+    launch_voronoi(G, g->stream, g->prof);
+    launch_compare(G, g->stream, g->prof);
     const hipError_t e = hipGetLastError();
-    for (int i = 0; i < g->n; ++i) {
-        g->m[i]->last = 0;
-        g->m[i]->pushed = true;
-        if (e != hipSuccess) fail(g->m[i], DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    for (int i = 0; i < n; ++i) {
+        dv_ctx *c = g->m[members[i]];
+        c->last = 0;
+        c->pushed = true;
+        if (e != hipSuccess) fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     }
     return e == hipSuccess ? DV_OK : DV_ERR_DEVICE;
+}
+
+dv_status dv_group_push(dv_group *g, const float *const *fields) {
+    if (!g || !fields) return DV_ERR_ARG;
+    int32_t all[DV_MAX_ENTRIES];
+    for (int i = 0; i < g->n; ++i) all[i] = i;
+    return dv_group_push_some(g, all, fields, g->n);
 }
 
 void dv_group_destroy(dv_group *g) {
@@ -593,8 +590,6 @@ void dv_group_destroy(dv_group *g) {
     (void)hipSetDevice(g->device);
     (void)hipStreamSynchronize(g->stream);
     if (g->d_tab) (void)hipFree(g->d_tab);
-    if (g->d_tbase) (void)hipFree(g->d_tbase);
-    if (g->d_bbase) (void)hipFree(g->d_bbase);
     delete g;
 }
 

@@ -121,16 +121,19 @@ struct Fields {
 // One launch's work: entries 0 .. n-1 of the device slot table D (frames of
 // one or several sequences, each with its own lattice), and the prefix sums
 // of their tile and band counts, so that a flat block index finds its entry.
-// The table itself is a separate kernel argument (const, restrict: slot
-// fields are loaded once, not after every store).
+// Entry e of a launch is row idx[e] of a device slot table, which is a
+// separate kernel argument (const, restrict: slot fields are loaded once,
+// not after every store).  Everything else travels in the kernel arguments,
+// so a launch over any subset of a table needs no upload.
 struct Batch {
-    const Bufs *D;
-    const int *tbase;      // [n + 1] first flat tile of each entry
-    const int *bbase;      // [n + 1] first flat band (32 rows) of each entry
+    const Bufs *D;         // the table (host side only; kernels take it separately)
     int n;
     int tiles, bands;      // totals over the entries
     int tpe, bpe;          // tiles / bands of every entry when all are alike, else 0
     int kmax, nty;         // largest K_max and band count (launch shapes)
+    int idx[DV_MAX_ENTRIES];        // table row of each entry
+    int tbase[DV_MAX_ENTRIES + 1];  // first flat tile of each entry
+    int bbase[DV_MAX_ENTRIES + 1];  // first flat band (32 rows) of each entry
 };
 
 // Entry holding flat index idx (base: prefix sums, n + 1 values; per: the
@@ -149,10 +152,10 @@ __device__ __forceinline__ int entry_of(const int *base, int per, int n, int idx
 // Past of entry i of a launch: the last earlier entry of the same sequence
 // whose stage errors are clear, else the sequence's past buffer.  Returns the
 // entry index, or -1 for the past buffer.
-__device__ __forceinline__ int past_slot(const Bufs *D, int i) {
-    const int q = D[i].seq;
+__device__ __forceinline__ int past_slot(const Bufs *D, const Batch &G, int i) {
+    const int q = D[G.idx[i]].seq;
     for (int j = i - 1; j >= 0; --j)
-        if (D[j].seq == q && D[j].fs->err == 0) return j;
+        if (D[G.idx[j]].seq == q && D[G.idx[j]].fs->err == 0) return j;
     return -1;
 }
 

@@ -35,16 +35,16 @@ struct PastOf {
     bool valid;
 };
 
-__device__ __forceinline__ PastOf past_of(const Bufs *D, int i) {
+__device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) {
     PastOf r;
-    const int j = past_slot(D, i);
+    const int j = past_slot(D, G, i);
     if (j >= 0) {
-        r.C = D[j].cur;
-        r.K = D[j].fs->K_now;
+        r.C = D[G.idx[j]].cur;
+        r.K = D[G.idx[j]].fs->K_now;
         r.valid = true;
     } else {
-        const SeqState *st = D[i].st;
-        r.C = D[i].past[st->sel];
+        const SeqState *st = D[G.idx[i]].st;
+        r.C = D[G.idx[i]].past[st->sel];
         r.K = st->past_valid ? st->K[st->sel] : 0;
         r.valid = st->past_valid != 0;
     }
@@ -52,9 +52,9 @@ __device__ __forceinline__ PastOf past_of(const Bufs *D, int i) {
 }
 
 __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[blockIdx.z];
+    const Bufs &B = D[G.idx[blockIdx.z]];
     if (B.fs->err) return;
-    const PastOf P = past_of(D, blockIdx.z);
+    const PastOf P = past_of(D, G, blockIdx.z);
     if (!P.valid) return;
     const int KP = P.K, KN = B.fs->K_now;
     const int lane = threadIdx.x & 63;
@@ -76,19 +76,19 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
     __shared__ int s_red[2][4];
     const int nb_frames = G.n;
     const int i = blockIdx.z;
-    const Bufs &B = Dt[i];
+    const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
     if (fs->err) return;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int KN = fs->K_now;
-    const PastOf PO = past_of(Dt, i);
+    const PastOf PO = past_of(Dt, G, i);
     const bool pv = PO.valid;
     const CompBuf P = PO.C, N = B.cur, Q = B.past[1 - B.st->sel];
     // the sequence's last accepted frame of the launch leaves its copy for the
     // next launch
     bool keep = true;
     for (int q = i + 1; q < nb_frames; ++q)
-        if (Dt[q].seq == B.seq && Dt[q].fs->err == 0) keep = false;
+        if (Dt[G.idx[q]].seq == B.seq && Dt[G.idx[q]].fs->err == 0) keep = false;
     const int D = B.maxdeg;
     int e2 = 0, exn = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     __shared__ int s_last;
     const int nb_frames = G.n;
     const int i = blockIdx.z;
-    const Bufs &B = Dt[i];
+    const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
     const int t = threadIdx.x;
     if (fs->err) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
         }
     } else {
         const int KN = fs->K_now;
-        const PastOf PO = past_of(Dt, i);
+        const PastOf PO = past_of(Dt, G, i);
         const int D = B.maxdeg;
         const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
         __syncthreads();
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     // block has read the sequence headers by now); the ticket is kept in the
     // first entry's header
     __syncthreads();
-    SeqState *tk = Dt[0].st;
+    SeqState *tk = Dt[G.idx[0]].st;
     if (t == 0) {
         __threadfence();
         s_last = atomicAdd(&tk->done_place, 1) == nb_frames - 1;
@@ -238,19 +238,19 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     if (t == 0) tk->done_place = 0;
     // thread k commits the sequence whose last entry in the launch is k
     if (t < nb_frames) {
-        const int k = t, q = Dt[k].seq;
+        const int k = t, q = Dt[G.idx[k]].seq;
         bool last = true;
         for (int j = k + 1; j < nb_frames; ++j)
-            if (Dt[j].seq == q) last = false;
+            if (Dt[G.idx[j]].seq == q) last = false;
         if (last) {
             int a = -1, acc = 0;
             for (int j = 0; j <= k; ++j)
-                if (Dt[j].seq == q && Dt[j].fs->err == 0) { a = j; ++acc; }
+                if (Dt[G.idx[j]].seq == q && Dt[G.idx[j]].fs->err == 0) { a = j; ++acc; }
             if (a >= 0) {
-                SeqState *sq = Dt[k].st;
+                SeqState *sq = Dt[G.idx[k]].st;
                 const int nxt = 1 - sq->sel;
-                sq->K[nxt] = Dt[a].fs->K_now;
-                sq->E[nxt] = Dt[a].fs->E2_acc / 2;
+                sq->K[nxt] = Dt[G.idx[a]].fs->K_now;
+                sq->E[nxt] = Dt[G.idx[a]].fs->E2_acc / 2;
                 sq->sel = nxt;
                 sq->past_valid = 1;
                 sq->frame += acc;

@@ -210,7 +210,7 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
 
 __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     __shared__ int L[DV_TILE_SITES];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ int npc;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
     const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (gt >= G.tiles) return;
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     const int tile = gt - G.tbase[e];
     const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
 // order of segments is the row-major order of the [ly][ntx] arrays.
 __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.bbase, G.bpe, G.n, blockIdx.x);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     __shared__ int pre[RES_TILES + 1];
     __shared__ int wsum[16];
     const int ty = blockIdx.x - G.bbase[e], t = threadIdx.x;
@@ -428,7 +428,7 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
 
 __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     __shared__ int L[DV_TILE_SITES];
     // per piece root (indexed by its tile-local site): rank, component root
     // (x | y << 16), integer sums

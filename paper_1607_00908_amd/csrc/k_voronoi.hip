@@ -27,7 +27,7 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[blockIdx.z];
+    const Bufs &B = D[G.idx[blockIdx.z]];
     __shared__ int wsum[16];
     __shared__ int s_last;
     FrameState *fs = B.fs;
@@ -241,7 +241,7 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
 // barrier-bounded phases are latency chains that other resident blocks fill.
 __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     const int tile = blockIdx.x - G.tbase[e];
     __shared__ OwnerLds S;
     FrameState *fs = B.fs;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D, Batch 
     const int gt = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (gt >= G.tiles) return;
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
-    const Bufs &B = D[e];
+    const Bufs &B = D[G.idx[e]];
     const int tile = gt - G.tbase[e];
     FrameState *fs = B.fs;
     if (fs->err) return;

@@ -27,7 +27,8 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 # every entry point declared in include/dv.h
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
-           "dv_get_matching", "dv_group_create", "dv_group_push", "dv_group_destroy",
+           "dv_get_matching", "dv_group_create", "dv_group_push", "dv_group_push_some",
+           "dv_group_destroy",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
 DEFAULT_BATCH = 16   # what max_batch = 0 selects
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.dv_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     lib.dv_group_push.restype = i32
     lib.dv_group_push.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.dv_group_push_some.restype = i32
+    lib.dv_group_push_some.argtypes = [vp, i32p, ctypes.POINTER(vp), i32]
     lib.dv_group_destroy.restype = None
     lib.dv_group_destroy.argtypes = [vp]
     lib.dv_set_profile.restype = i32
@@ -311,30 +314,39 @@ class Group:
             raise DVError(st, self.lib.dv_last_error(None).decode())
         self.h = h
 
+    def _ptr(self, d, f) -> int:
+        if isinstance(f, int):
+            return f
+        if not (f.is_cuda and f.dtype == d._torch.float32):
+            raise TypeError("fields must be float32 device tensors")
+        if tuple(f.shape) != (d.ly, d.lx) or not f.is_contiguous():
+            raise ValueError(f"field must be contiguous with shape ({d.ly}, {d.lx})")
+        cur = d._torch.cuda.current_stream(d.device)
+        if cur.cuda_stream != d.stream.cuda_stream:
+            d.stream.wait_stream(cur)
+            f.record_stream(d.stream)
+        d._field_refs.append(f)
+        return f.data_ptr()
+
     def push(self, fields) -> None:
         """One float32 device tensor [ly, lx] (contiguous) per member, or raw
         device pointers (int)."""
         if len(fields) != len(self.members):
             raise ValueError("one field per member")
-        ptrs = []
-        for d, f in zip(self.members, fields):
-            if isinstance(f, int):
-                ptrs.append(f)
-                continue
-            if not (f.is_cuda and f.dtype == d._torch.float32):
-                raise TypeError("fields must be float32 device tensors")
-            if tuple(f.shape) != (d.ly, d.lx) or not f.is_contiguous():
-                raise ValueError(f"field must be contiguous with shape ({d.ly}, {d.lx})")
-            cur = d._torch.cuda.current_stream(d.device)
-            if cur.cuda_stream != d.stream.cuda_stream:
-                d.stream.wait_stream(cur)
-                f.record_stream(d.stream)
-            d._field_refs.append(f)
-            ptrs.append(f.data_ptr())
+        self.push_some(range(len(self.members)), fields)
+
+    def push_some(self, members, fields) -> None:
+        """Frames for the listed members only (distinct indices), in one launch
+        per stage; the other members are untouched."""
+        members = [int(k) for k in members]
+        if len(fields) != len(members) or not members:
+            raise ValueError("one field per listed member")
+        ptrs = [self._ptr(self.members[k], f) for k, f in zip(members, fields)]
+        idx = (ctypes.c_int32 * len(members))(*members)
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
-        st = self.lib.dv_group_push(self.h, arr)
+        st = self.lib.dv_group_push_some(self.h, idx, arr, len(members))
         if st != OK:
-            raise DVError(st, self.lib.dv_last_error(self.members[0].h).decode())
+            raise DVError(st, self.lib.dv_last_error(self.members[members[0]].h).decode())
 
     def close(self):
         if getattr(self, "h", None):

@@ -88,3 +88,10 @@ def test_group_arguments_are_checked_on_the_host():
     assert not h.value
     assert lib.dv_group_push(None, None) == dv.ERR_ARG
     lib.dv_group_destroy(None)
+
+
+def test_group_subset_arguments_are_checked_on_the_host():
+    lib = dv.load()
+    idx = (ctypes.c_int32 * 1)(0)
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.dv_group_push_some(None, idx, arr, 1) == dv.ERR_ARG

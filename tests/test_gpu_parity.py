@@ -304,6 +304,31 @@ def test_group_bursts_and_single_pushes_mix():
         d.close()
 
 
+def test_group_subsets_as_frames_arrive():
+    """Continuous batching: each push carries the members that have a new
+    frame, in any order; every member's results equal the oracle's for its own
+    sequence, whatever it was batched with."""
+    sizes = [(80, 64), (128, 96), (64, 128), (150, 150)]
+    sims = [synth.DiskSim(lx, ly, 8, 3.0, 6.0, 0.6, 3e-3, seed=1100 + i)
+            for i, (lx, ly) in enumerate(sizes)]
+    frames = [list(sm.frames(5)) for sm in sims]
+    dets, grp = _group(sizes, max_batch=1)
+    seqs = [oracle.Sequence(0.5, 0, 8, NTHREADS) for _ in sizes]
+    nxt = [0] * len(sizes)
+    schedule = [[0, 1, 2, 3], [2, 0], [3], [1, 3, 0], [0], [2, 1], [3, 2, 1], [1, 0]]
+    for step, members in enumerate(schedule):
+        members = [m for m in members if nxt[m] < 5]
+        say(f"  [subsets] step {step} members {members}")
+        grp.push_some(members, [torch.from_numpy(frames[m][nxt[m]]).cuda() for m in members])
+        for m in members:
+            now, ref = seqs[m].push(frames[m][nxt[m]])
+            nxt[m] += 1
+            check_frame(dets[m], now, ref, *sizes[m])
+    grp.close()
+    for d in dets:
+        d.close()
+
+
 def test_group_member_rejection_is_isolated():
     """A frame over one member's K_max is rejected for that member only."""
     sizes = [(120, 100), (120, 100), (90, 110)]
