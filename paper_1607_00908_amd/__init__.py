@@ -2,13 +2,14 @@
 diagrams (Bernaschi, Lulli, Sbragaglia, arXiv:1607.00908).
 
 * ``dv``     -- binding of the HIP library libdv.so (C ABI in include/dv.h)
+* ``serve``  -- continuous batching of frames from many streams (groups)
 * ``synth``  -- seeded synthetic workloads (input generation only)
 
 Submodules are imported on demand so that the workload generators can be used
 without loading the GPU library.
 """
 
-__all__ = ["dv", "synth"]
+__all__ = ["dv", "serve", "synth"]
 
 
 def __getattr__(name):

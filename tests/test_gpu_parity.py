@@ -430,3 +430,42 @@ def test_sparse_cluster_exercises_candidate_overflow():
     g[10:90:2, 20:100:2] = 0.0
     g[11:91:2, 21:101:2] = 1.0          # the whole cluster moves by (1, 1)
     run_sequence([f, g], 0.5, kmax=2048, tag="cluster")
+
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    """Frames of six streams arriving in a random order are served in mixed
+    batches; every frame's flips and counts equal those of the same stream run
+    alone, frame by frame."""
+    from paper_1607_00908_amd import serve
+    rng = np.random.default_rng(12)
+    fields = synth.mixed_fields(6, seed=6, l_min=48, l_max=160)
+    nf = 5
+    frames = [list(sm.frames(nf)) for sm, _ in fields]
+    srv = serve.Server(reserve_bytes=0)
+    sids = [srv.admit(sp["lx"], sp["ly"], sp["threshold"], sp["phase"],
+                      max_components=4 * sp["k_expect"] + 256) for _, sp in fields]
+    assert all(s is not None for s in sids)
+    # arrivals: a random interleaving of the streams' frames, in per-stream order
+    order = [i for i in range(len(fields)) for _ in range(nf)]
+    rng.shuffle(order)
+    nxt = [0] * len(fields)
+    mixed = {}
+    for step_i, i in enumerate(order):
+        srv.submit(sids[i], torch.from_numpy(frames[i][nxt[i]]).cuda(), tag=(i, nxt[i]))
+        nxt[i] += 1
+        if rng.random() < 0.5 or step_i == len(order) - 1:
+            while srv.pending():
+                for sid, tag, ta, td, info, fl in srv.step():
+                    mixed[tag] = (info.n_components, info.n_edges, info.n_flips, fl)
+    srv.close()
+    assert len(mixed) == len(order)
+    for i, (_, sp) in enumerate(fields):
+        det = dv.Detector(sp["lx"], sp["ly"], sp["threshold"], sp["phase"], 8,
+                          max_components=4 * sp["k_expect"] + 256, max_batch=1)
+        for k in range(nf):
+            det.push(torch.from_numpy(frames[i][k]).cuda())
+            info, fl = det.info(), det.flips()
+            K, E, F, got = mixed[(i, k)]
+            assert (K, E, F) == (info.n_components, info.n_edges, info.n_flips), (i, k)
+            assert np.array_equal(got, fl), (i, k)
+        det.close()
