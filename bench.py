@@ -2,6 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload disks1024]
 python bench.py --workload mixed64 [--fields 64] [--frames 5] [--steps 20]
+python bench.py --workload serve32 [--fields 32] [--gap-ms 2] [--steps 10000]
 
 A step is one frame through the whole path (threshold, labelling, centres,
 digital Voronoi, Delaunay couples, matching, flips) on synthetic input of the
@@ -254,6 +255,88 @@ def bench_mixed(args):
         "speedup": round(v_g / v_s, 3)}))
 
 
+def _serve_frames(args):
+    i, n, nf, seed, lmin, lmax = args
+    from paper_1607_00908_amd import synth
+    sim, spec = synth.mixed_fields(n, seed=seed, l_min=lmin, l_max=lmax)[i]
+    return list(sim.frames(nf)), spec
+
+
+def bench_serve(args):
+    """Continuous batching under Poisson arrivals: `fields` streams, sides
+    log-uniform in [512, 4096], frames arriving with exponential gaps of mean
+    `gap_ms` per stream until `steps` frames in all.  Throughput and latency
+    (arrival to results ready) of the served frames.  Prints one JSON line."""
+    import concurrent.futures as cf
+    import torch
+    from paper_1607_00908_amd import serve
+    n, nf = args.fields, args.frames or 3
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(_serve_frames, [(i, n, nf, 5, 512, 4096) for i in range(n)]))
+    log(f"generated {n} streams x {nf} frames in {time.perf_counter() - t0:.1f} s")
+    specs = [sp for _, sp in res]
+    rings = [torch.from_numpy(np.stack(fr)).cuda() for fr, _ in res]
+    torch.cuda.synchronize()
+    srv = serve.Server(reserve_bytes=8 << 30)
+    sids = [srv.admit(sp["lx"], sp["ly"], sp["threshold"], sp["phase"],
+                      max_components=4 * sp["k_expect"] + 256) for sp in specs]
+    admitted = [i for i, s in enumerate(sids) if s is not None]
+    # warm-up: every stream's first frames
+    for w in range(2):
+        for i in admitted:
+            srv.submit(sids[i], rings[i][w % nf])
+        while srv.pending():
+            srv.step(collect=False)
+    # arrival times (seconds from the start), per stream a Poisson process
+    rng = np.random.default_rng(17)
+    arrivals = []
+    per = -(-args.steps // len(admitted))
+    for i in admitted:
+        t = np.cumsum(rng.exponential(args.gap_ms * 1e-3, per))
+        arrivals += [(float(tt), i, k) for k, tt in enumerate(t)]
+    arrivals.sort()
+    arrivals = arrivals[:args.steps]
+    lat, sites, batches, served = [], 0, 0, 0
+    j = 0
+    start = time.perf_counter()
+    while served < len(arrivals):
+        now = time.perf_counter() - start
+        while j < len(arrivals) and arrivals[j][0] <= now:
+            ta, i, k = arrivals[j]
+            srv.submit(sids[i], rings[i][(k + 2) % nf], tag=i, t_arrival=start + ta)
+            j += 1
+        if not srv.pending():
+            time.sleep(max(0.0, min(arrivals[j][0] - now, 1e-3)))
+            continue
+        out = srv.step(collect=False)
+        batches += 1
+        for sid, i, ta, td, _, _ in out:
+            lat.append(td - ta)
+            sites += specs[i]["lx"] * specs[i]["ly"]
+            served += 1
+    elapsed = time.perf_counter() - start
+    ok = all(d.info().status == 0 for d in srv.dets)
+    srv.close()
+    lat = np.array(lat) * 1e3
+    offered = sum(specs[i]["lx"] * specs[i]["ly"] for i in admitted) / (args.gap_ms * 1e-3) / 1e6
+    print(json.dumps({
+        "metric": "Msites/s served, continuous batching of Poisson frame arrivals; p50/p99 latency",
+        "value": round(sites / elapsed / 1e6, 2), "unit": "Msites/s", "n_gpus": 1,
+        "steps": len(arrivals), "warmup": 2, "ms_per_step": round(1e3 * elapsed / len(arrivals), 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32->int64",
+        "data": "synthetic",
+        "config": {"workload": f"serve{n}", "streams": n, "admitted": len(admitted),
+                   "gap_ms": args.gap_ms, "offered_msites_s": round(offered, 1),
+                   "side_min": min(sp["lx"] for sp in specs), "side_max": max(sp["lx"] for sp in specs),
+                   "mean_sites_per_frame": round(float(np.mean([sp["lx"] * sp["ly"] for sp in specs]))),
+                   "parallelism": "single-gpu"},
+        "frames_per_s": round(len(arrivals) / elapsed, 1), "batches": batches,
+        "mean_batch": round(len(arrivals) / max(batches, 1), 2), "all_accepted": ok,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3), "samples": len(lat)}}))
+
+
 def make_frames(workload: str, frames: int | None):
     from paper_1607_00908_amd import synth
     sim, spec = synth.workload(workload)
@@ -288,7 +371,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--workload", default="disks1024")
     ap.add_argument("--frames", type=int, default=None, help="frames in the ring (default: all)")
-    ap.add_argument("--fields", type=int, default=64, help="fields of the mixed workload")
+    ap.add_argument("--fields", type=int, default=64,
+                    help="fields of the mixed workload (streams of the serving one: 32)")
+    ap.add_argument("--gap-ms", type=float, default=2.0,
+                    help="mean gap between frame arrivals of one stream (serving)")
     ap.add_argument("--flips-only", action="store_true", help="do not write label / owner maps")
     ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
     ap.add_argument("--max-batch", type=int, default=0,
@@ -317,6 +403,13 @@ def main():
         if args.steps == 1600:
             args.steps = 20
         bench_mixed(args)
+        return
+    if args.workload.startswith("serve"):
+        if args.steps == 1600:
+            args.steps = 10000
+        if args.fields == 64:
+            args.fields = 32
+        bench_serve(args)
         return
 
     import torch
