@@ -9,6 +9,7 @@ chain the steps in the paper's order:
 
 * ``frame(field, ...)``  -- Sec. 3.1 and 3.2.1-3.2.2 on one field
 * ``Sequence``           -- keeps the past frame and applies Sec. 3.2.3-3.2.4
+* ``classify``           -- event flags of the flips (Sec. 3.2.4, optional)
 
 Each function's docstring names the section it follows; the readings of the
 paper that the oracle fixes are stated in ``oracle.cpp``.
@@ -191,6 +192,59 @@ def diff(KP: int, past_edges, phi, KN: int, now_edges, cnt):
         cap = F
 
 
+def classify(past_edges, phi, now_edges, cnt, flips) -> np.ndarray:
+    """Event flags of the flips (Sec. 3.2.4, extraction of topology change
+    events), written out with plain sets; returns int32 [F].
+
+    Both graphs keep only points with exactly one preimage (the exclusion of
+    Sec. 3.2.3), the past one translated through Phi.  The active points are
+    the endpoints of the flips (the points whose rows changed, the local
+    trigger).  For each active point count the other active points it is
+    connected to in either graph.  A couple of a graph is a boundary couple
+    when its two ends share fewer than two neighbours in that graph, and a
+    point with a boundary couple is a boundary point.  Flag bit 0 (bulk): both
+    ends have at least three active neighbours.  Flag bit 1 (boundary): both
+    ends are boundary points of the graph that holds the couple (past graph
+    for a breaking couple, now graph for an arising one).
+    """
+    phi = np.asarray(phi)
+    cnt = np.asarray(cnt)
+
+    def kept_now(n):
+        return 0 <= n < len(cnt) and cnt[n] == 1
+
+    adjP, adjN = {}, {}
+    for a, b in np.asarray(past_edges).reshape(-1, 2):
+        ta, tb = int(phi[a]), int(phi[b])
+        if kept_now(ta) and kept_now(tb) and ta != tb:
+            adjP.setdefault(ta, set()).add(tb)
+            adjP.setdefault(tb, set()).add(ta)
+    for a, b in np.asarray(now_edges).reshape(-1, 2):
+        a, b = int(a), int(b)
+        if kept_now(a) and kept_now(b):
+            adjN.setdefault(a, set()).add(b)
+            adjN.setdefault(b, set()).add(a)
+    flips = np.asarray(flips).reshape(-1, 6)
+    active = set(int(v) for v in flips[:, :2].ravel())
+    count = {}
+    for p in active:
+        nb = adjP.get(p, set()) | adjN.get(p, set())
+        count[p] = len(nb & active)
+
+    def boundary_point(adj, p):
+        return any(len(adj.get(p, set()) & adj.get(q, set())) < 2 for q in adj.get(p, set()))
+
+    out = np.zeros(len(flips), dtype=np.int32)
+    for i, (a, b, _, _, kind, _) in enumerate(flips):
+        a, b = int(a), int(b)
+        f = 1 if (count[a] >= 3 and count[b] >= 3) else 0
+        g = adjP if kind == -1 else adjN
+        if boundary_point(g, a) and boundary_point(g, b):
+            f |= 2
+        out[i] = f
+    return out
+
+
 # -------------------------------------------------------------- whole frames
 @dataclass
 class FrameResult:
@@ -226,19 +280,22 @@ class DiffResult:
 class Sequence:
     """Frame-to-frame driver: the past triangulation is kept between calls."""
 
-    def __init__(self, threshold: float, phase: int = 0, conn: int = 8, nthreads: int = 0):
+    def __init__(self, threshold: float, phase: int = 0, conn: int = 8, nthreads: int = 0,
+                 classify_events: bool = False):
         self.threshold, self.phase, self.conn, self.nthreads = threshold, phase, conn, nthreads
+        self.classify_events = classify_events
         self.past: FrameResult | None = None
 
     def push(self, field: np.ndarray):
         now = frame(field, self.threshold, self.phase, self.conn, self.nthreads)
-        res = compare(self.past, now)
+        res = compare(self.past, now, self.classify_events)
         self.past = now
         return now, res
 
 
-def compare(past: FrameResult | None, now: FrameResult) -> DiffResult:
-    """Diff of two frames; with no past frame there is nothing to compare."""
+def compare(past: FrameResult | None, now: FrameResult, classify_events: bool = False) -> DiffResult:
+    """Diff of two frames; with no past frame there is nothing to compare.
+    classify_events: fill the flags column of the flips (``classify``)."""
     if past is None:
         z = np.zeros(0, dtype=np.int32)
         return DiffResult(np.zeros((0, 6), np.int32), z, np.zeros(now.K, np.int32), z, 0, 0, 0)
@@ -246,4 +303,7 @@ def compare(past: FrameResult | None, now: FrameResult) -> DiffResult:
     phi, cnt = match(lx, ly, past.comps["qx"], past.comps["qy"], now.comps["qx"],
                      now.comps["qy"])
     fl, lt, (exP, exN, g) = diff(past.K, past.edges, phi, now.K, now.edges, cnt)
+    if classify_events and len(fl):
+        fl = fl.copy()
+        fl[:, 5] = classify(past.edges, phi, now.edges, cnt, fl)
     return DiffResult(fl, phi, cnt, lt, exP, exN, g)
