@@ -55,6 +55,17 @@ extern "C" {
 
 /* flags */
 #define DV_KEEP_MAPS 1u  /* label / owner maps stay readable after each push */
+#define DV_CLASSIFY 2u   /* fill dv_flip.flags with the event classification */
+
+/* dv_flip.flags bits (with DV_CLASSIFY; Sec. 3.2.4, extraction of events).
+ * Active points are the ends of the flips.  BULK: both ends are connected to
+ * at least three active points (counted over the past graph translated by Phi
+ * and the now graph).  BOUNDARY: both ends are boundary points of the graph
+ * holding the couple (past graph for breaking, now graph for arising), a
+ * boundary point having a couple whose ends share fewer than two neighbours.
+ * A flip with neither bit is not part of a bulk or boundary event. */
+#define DV_FLIP_BULK 1u
+#define DV_FLIP_BOUNDARY 2u
 
 typedef enum {
     DV_OK = 0,
@@ -80,16 +91,16 @@ typedef struct {
     int32_t max_degree;      /* row capacity of the adjacency (Delaunay degree),
                                 4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
-    uint32_t flags;          /* DV_KEEP_MAPS                                       */
+    uint32_t flags;          /* DV_KEEP_MAPS | DV_CLASSIFY                         */
     int32_t max_batch;       /* frames sent to the device together, 1 .. 16; 0
                                 selects 16.  Each holds its own per-site buffers. */
 } dv_config;
 
 /* One edge flip (Sec. 3.2.4).  a < b are now labels; pa, pb the past labels
  * with Phi(pa) = a and Phi(pb) = b.  kind = -1 breaking (couple only in the
- * past triangulation), +1 arising (only in the now triangulation).  flags is
- * reserved and 0.  Flips are ordered breaking first, then arising, each by
- * (a, b) ascending. */
+ * past triangulation), +1 arising (only in the now triangulation).  flags:
+ * DV_FLIP_* bits when the context has DV_CLASSIFY, else 0.  Flips are ordered
+ * breaking first, then arising, each by (a, b) ascending. */
 typedef struct {
     int32_t a, b;
     int32_t pa, pb;
@@ -197,7 +208,7 @@ void dv_group_destroy(dv_group *g);
 /* ---- measurement ---- */
 
 /* Stages of the per-frame procedure, in launch order. */
-#define DV_N_STAGES 10
+#define DV_N_STAGES 11
 /* Bracket every launch of one stage with HIP events on the context's stream
  * (one launch covers every frame of a batch).
  * stage: 0 .. DV_N_STAGES-1, or -1 to stop.  capacity: launches that can be

@@ -91,6 +91,7 @@ dv_status flush(dv_ctx *c) {
     G.bpe = H.nty;
     G.kmax = H.kmax;
     G.nty = H.nty;
+    G.classify = H.classify;
     launch_label(G, c->pending, c->stream, c->prof);
     launch_voronoi(G, c->stream, c->prof);
     launch_compare(G, c->stream, c->prof);
@@ -139,7 +140,7 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->max_degree != 0 && (cfg->max_degree < 4 || cfg->max_degree > 64))
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
-    if (cfg->flags & ~DV_KEEP_MAPS) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
+    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY)) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
         return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 16]");
     return DV_OK;
@@ -225,6 +226,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     B.maxdeg = c->cfg.max_degree;
     B.ncells = B.ntx * B.nty;
     B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
+    B.classify = (c->cfg.flags & DV_CLASSIFY) ? 1 : 0;
     const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
     const size_t segs = (size_t)B.ly * B.ntx;
     auto comp_alloc = [&](CompBuf &C) {
@@ -252,6 +254,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
              comp_alloc(b.cur) && dalloc(c, &b.phi, K) && dalloc(c, &b.trigger, K) &&
              dalloc(c, &b.nb, K) && dalloc(c, &b.na, K) && dalloc(c, &b.ob, K) &&
              dalloc(c, &b.oa, K) && dalloc(c, &b.flips, K * B.maxdeg * 6) &&
+             dalloc(c, &b.act, K) && dalloc(c, &b.ecnt, K) && dalloc(c, &b.ebnd, K) &&
              dalloc(c, &b.stage, K * B.maxdeg * 12);
         if (ok && B.keep_maps) ok = dalloc(c, &b.labels, N) && dalloc(c, &b.owner, N);
     }
@@ -438,7 +441,7 @@ void dv_destroy(dv_ctx *c) {
 
 static const char *const STAGE_NAMES[ST_COUNT] = {
     "tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "rows", "match", "diff",
-    "place"};
+    "events", "place"};
 
 const char *dv_stage_name(int32_t stage) {
     return (stage >= 0 && stage < ST_COUNT) ? STAGE_NAMES[stage] : nullptr;
@@ -559,6 +562,7 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
         G.bbase[i + 1] = G.bbase[i] + b.nty;
         G.kmax = std::max(G.kmax, b.kmax);
         G.nty = std::max(G.nty, b.nty);
+        G.classify |= b.classify;
         alike = alike && b.ncells == g->h_tab[members[0]].ncells && b.nty == g->h_tab[members[0]].nty;
     }
     G.tiles = G.tbase[n];

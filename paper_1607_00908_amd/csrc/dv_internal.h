@@ -76,7 +76,7 @@ struct Bufs {
     int32_t kmax, maxdeg;
     int32_t ncells;        // bucket grid = tile grid
     int32_t keep_maps;     // write the label / owner maps
-    int32_t pad;
+    int32_t classify;      // fill the flips' event flags
     int32_t *parent;       // [N] union-find over tile-border sites and piece roots
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
@@ -109,6 +109,10 @@ struct Bufs {
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
     int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
     int32_t *flips;        // [K_max * max_degree][6]
+    // event classification (when classify): per now label
+    int32_t *act;          // [K_max] the row changed (an end of a flip)
+    int32_t *ecnt;         // [K_max] active points connected in either graph
+    int32_t *ebnd;         // [K_max] bit 0: boundary point of the now graph, bit 1: of the past
     CompBuf past[2];       // shared by the slots
     SeqState *st;          // shared by the slots
 };
@@ -131,6 +135,7 @@ struct Batch {
     int tiles, bands;      // totals over the entries
     int tpe, bpe;          // tiles / bands of every entry when all are alike, else 0
     int kmax, nty;         // largest K_max and band count (launch shapes)
+    int classify;          // some entry classifies events
     int idx[DV_MAX_ENTRIES];        // table row of each entry
     int tbase[DV_MAX_ENTRIES + 1];  // first flat tile of each entry
     int bbase[DV_MAX_ENTRIES + 1];  // first flat band (32 rows) of each entry
@@ -162,7 +167,7 @@ __device__ __forceinline__ int past_slot(const Bufs *D, const Batch &G, int i) {
 // Stage ids, in launch order (names in dv_api.hip).
 enum {
     ST_TILE_CCL, ST_MERGE, ST_RESOLVE, ST_RELABEL, ST_FINALIZE, ST_OWNER_EDGES, ST_ROWS,
-    ST_MATCH, ST_DIFF, ST_PLACE, ST_COUNT
+    ST_MATCH, ST_DIFF, ST_EVENTS, ST_PLACE, ST_COUNT
 };
 
 // Optional event bracketing of one stage (measurement only).

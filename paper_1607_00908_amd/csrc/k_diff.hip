@@ -17,6 +17,8 @@
 //             T(p) is arising; each is reported once, from the row of its
 //             smaller now label, and staged in increasing order of the other
 //             end.  The local trigger of p is set when the two rows differ.
+//   k_events  (event classification only) one wave per changed row: active
+//             neighbours in either graph, boundary points of either graph.
 //   k_place   one block per frame: scans the per-row counts and places the
 //             staged flips in canonical order (breaking first, then arising,
 //             each by (a, b)).  Kept past and now points correspond one to
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
         const int p = gmem(B.inv)[n];
         const int dR = __popcll(__ballot(m != DV_EMPTY));
         if (lane == 0) e2 += dR;
-        int cb = 0, ca = 0;
+        int cb = 0, ca = 0, actv = 0;
         if (pv && cn != 1) {
             if (lane == 0) ++exn;
         } else if (pv) {
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
             const bool ari = mv != DV_EMPTY && !min_;
             const unsigned long long dmask = __ballot(brk || ari);
             if (lane == 0) gmem(B.trigger)[p] = dmask ? 1 : 0;
+            actv = dmask ? 1 : 0;
             // each couple once, from the row of its smaller now label
             const bool bo = brk && tv > n, ao = ari && mv > n;
             cb = __popcll(__ballot(bo));
@@ -152,6 +155,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
         if (lane == 0) {
             gmem(B.nb)[n] = cb;
             gmem(B.na)[n] = ca;
+            if (B.classify) gmem(B.act)[n] = actv;
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -172,6 +176,90 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
         if (a) atomicAdd(&fs->E2_acc, a);
         if (b) atomicAdd(&fs->excl_acc, b);
     }
+}
+
+// Event classification (Sec. 3.2.4), one wave per active now label n (an end
+// of a flip): the active points connected to n in either graph, and whether
+// n is a boundary point of the now graph and of the translated past graph
+// (one of its couples has ends sharing fewer than two neighbours).  Both
+// graphs keep only points with exactly one preimage, as in k_diff.  The
+// wave's two rows sit in LDS for the membership tests of its lanes.
+__global__ __launch_bounds__(256) void k_events(const Bufs *__restrict__ Dt, Batch G) {
+    __shared__ int rowR[4][64], rowT[4][64];
+    const int i = blockIdx.z;
+    const Bufs &B = Dt[G.idx[i]];
+    const FrameState *fs = B.fs;
+    if (!B.classify || fs->err) return;
+    const PastOf PO = past_of(Dt, G, i);
+    if (!PO.valid) return;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int KN = fs->K_now, D = B.maxdeg;
+    const CompBuf P = PO.C, N = B.cur;
+    const auto cnt = gmem(B.cnt), phi = gmem(B.phi), inv = gmem(B.inv), act = gmem(B.act);
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
+        if (!act[n]) continue;
+        const int m = lane < D ? gmem(N.adj)[(size_t)n * D + lane] : DV_EMPTY;
+        const int mv = (m != DV_EMPTY && cnt[m] == 1) ? m : DV_EMPTY;
+        const int p = inv[n];
+        const int q = lane < D ? gmem(P.adj)[(size_t)p * D + lane] : DV_EMPTY;
+        int tv = DV_EMPTY;
+        if (q != DV_EMPTY) {
+            const int nn = phi[q];
+            if (nn >= 0 && cnt[nn] == 1) tv = nn;
+        }
+        rowR[wid][lane] = mv;
+        rowT[wid][lane] = tv;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        bool tin = false;
+        for (int k = 0; k < D; ++k) tin |= (tv != DV_EMPTY && rowR[wid][k] == tv);
+        const bool aR = mv != DV_EMPTY && act[mv];
+        const bool aT = tv != DV_EMPTY && !tin && act[tv];
+        const int count = __popcll(__ballot(aR)) + __popcll(__ballot(aT));
+        // a couple (n, x) is a boundary couple when n and x share fewer than
+        // two neighbours; x's row is read from memory, n's from LDS
+        bool bN = false, bP = false;
+        if (mv != DV_EMPTY) {
+            int c = 0;
+            for (int k = 0; k < D && c < 2; ++k) {
+                const int x = gmem(N.adj)[(size_t)mv * D + k];
+                if (x == DV_EMPTY) break;
+                if (cnt[x] != 1) continue;
+                for (int j = 0; j < D; ++j)
+                    if (rowR[wid][j] == x) { ++c; break; }
+            }
+            bN = c < 2;
+        }
+        if (tv != DV_EMPTY) {
+            const int pt = inv[tv];
+            int c = 0;
+            for (int k = 0; k < D && c < 2; ++k) {
+                const int q2 = gmem(P.adj)[(size_t)pt * D + k];
+                if (q2 == DV_EMPTY) break;
+                const int x = phi[q2];
+                if (x < 0 || cnt[x] != 1) continue;
+                for (int j = 0; j < D; ++j)
+                    if (rowT[wid][j] == x) { ++c; break; }
+            }
+            bP = c < 2;
+        }
+        const bool anyN = __ballot(bN) != 0ull, anyP = __ballot(bP) != 0ull;
+        if (lane == 0) {
+            gmem(B.ecnt)[n] = count;
+            gmem(B.ebnd)[n] = (anyN ? 1 : 0) | (anyP ? 2 : 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// flags of a placed flip record (a, b, pa, pb, kind, flags)
+__device__ __forceinline__ int event_flags(const Bufs &B, int a, int b, int kind) {
+    const auto ecnt = gmem(B.ecnt), ebnd = gmem(B.ebnd);
+    int f = (ecnt[a] >= 3 && ecnt[b] >= 3) ? 1 : 0;
+    const int bit = kind < 0 ? 2 : 1;
+    if ((ebnd[a] & bit) && (ebnd[b] & bit)) f |= 2;
+    return f;
 }
 
 __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
@@ -209,6 +297,10 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
             for (int j = 0; j < 6 * cb; ++j) fb[j] = stg[j];
             int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
             for (int j = 0; j < 6 * ca; ++j) fa[j] = stg[6 * D + j];
+            if (B.classify) {
+                for (int j = 0; j < cb; ++j) fb[6 * j + 5] = event_flags(B, fb[6 * j], fb[6 * j + 1], -1);
+                for (int j = 0; j < ca; ++j) fa[6 * j + 5] = event_flags(B, fa[6 * j], fa[6 * j + 1], 1);
+            }
         }
         if (t == 0) {
             const int KP = PO.valid ? PO.K : 0;
@@ -328,6 +420,11 @@ void launch_compare(const Batch &G, hipStream_t s, Prof &P) {
     P.begin(ST_DIFF, s);
     hipLaunchKernelGGL(k_diff, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);
     P.end(ST_DIFF, s);
+    if (G.classify) {
+        P.begin(ST_EVENTS, s);
+        hipLaunchKernelGGL(k_events, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);
+        P.end(ST_EVENTS, s);
+    }
     P.begin(ST_PLACE, s);
     hipLaunchKernelGGL(k_place, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_PLACE, s);

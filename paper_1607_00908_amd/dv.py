@@ -21,6 +21,8 @@ NO_LABEL = -1
 PHASE_ABOVE = 0
 PHASE_BELOW = 1
 KEEP_MAPS = 1
+CLASSIFY = 2
+FLIP_BULK, FLIP_BOUNDARY = 1, 2
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = range(7)
 
@@ -34,7 +36,7 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
 DEFAULT_BATCH = 16   # what max_batch = 0 selects
 
 STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "rows",
-          "match", "diff", "place")
+          "match", "diff", "events", "place")
 
 
 class DVConfig(ctypes.Structure):
@@ -147,17 +149,20 @@ class Detector:
     a host synchronisation) for the caller's current stream, and the frame's
     kernels start after it, so a field produced there is complete when they
     read it.  ``max_batch``: frames queued and sent to the device together
-    (0: the library's default).
+    (0: the library's default).  ``classify``: fill the flips' event flags
+    (FLIP_BULK, FLIP_BOUNDARY).
     """
 
     def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
-                 device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0):
+                 device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0,
+                 classify: bool = False):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
         cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
                        int(connectivity), int(max_components), int(max_degree), int(device),
-                       KEEP_MAPS if keep_maps else 0, int(max_batch))
+                       (KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0),
+                       int(max_batch))
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))

@@ -66,13 +66,14 @@ def check_frame(det, now, ref, lx, ly, maps=True):
         assert len(phi) == 0
 
 
-def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag=""):
+def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag="",
+                 classify=False):
     ly, lx = fields[0].shape
     if kmax is None:
         kmax = lx * ly
     det = dv.Detector(lx, ly, thr, phase, conn, max_components=kmax, max_degree=max_degree,
-                      keep_maps=maps)
-    seq = oracle.Sequence(thr, phase, conn, NTHREADS)
+                      keep_maps=maps, classify=classify)
+    seq = oracle.Sequence(thr, phase, conn, NTHREADS, classify_events=classify)
     for i, f in enumerate(fields):
         say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase}")
         det.push(torch.from_numpy(np.ascontiguousarray(f)).to("cuda"))
@@ -351,6 +352,52 @@ def test_group_member_rejection_is_isolated():
     grp.close()
     for d in dets:
         d.close()
+
+
+def test_event_flags_t1_fixture():
+    import json
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "t1_fixture.json")))
+    names = ["A", "B", "C", "D"]
+    fields = []
+    for fr in ("0", "1"):
+        pts = [d["quartet"][fr][n] for n in names] + d["background"]
+        fields.append(synth.disk_field(d["lx"], d["ly"], np.array(pts, float),
+                                       np.full(len(pts), float(d["radius"]))))
+    run_sequence(fields, 0.5, tag="t1-events", classify=True)
+    det = dv.Detector(d["lx"], d["ly"], 0.5, max_components=128, classify=True)
+    for f in fields:
+        det.push(torch.from_numpy(f).cuda())
+    fl = det.flips()
+    assert fl[:, 5].tolist() == [dv.FLIP_BULK, dv.FLIP_BULK]
+    det.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_event_flags_moving_disks(seed):
+    rng = np.random.default_rng(4000 + seed)
+    lx, ly = int(rng.integers(60, 220)), int(rng.integers(60, 220))
+    sim = synth.DiskSim(lx, ly, int(rng.integers(8, 60)), 3.0, 6.0, 0.9, 4e-3, seed=5000 + seed)
+    run_sequence(list(sim.frames(6)), 0.5, tag=f"events{seed}", classify=True)
+
+
+def test_event_flags_random_field_with_exclusions():
+    sim = synth.GRFSim(256, 256, 4.0, 0.9, seed=41)
+    run_sequence(list(sim.frames(5)), 1.0, kmax=4096, tag="events-grf", classify=True)
+
+
+def test_event_flags_disks1024_batched():
+    sim, spec = synth.workload("disks1024")
+    frames = list(sim.frames(9))
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    det = dv.Detector(1024, 1024, spec["threshold"], spec["phase"], 8, max_components=4096,
+                      classify=True)
+    for k in range(len(frames)):
+        det.push(dev[k])
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS, classify_events=True)
+    seq.push(frames[-2])
+    now, ref = seq.push(frames[-1])
+    check_frame(det, now, ref, 1024, 1024)
+    det.close()
 
 
 def test_degree_overflow_is_reported():
