@@ -332,15 +332,20 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     // minimum image of some window point (relative offset within [-M/2, M/2]).
     // The offset rx lies in (-MX, MX) and the window is at most one lattice
     // wide, so only the images k = -1 .. 2 can qualify.
-    auto add_images = [&](int lab, int2 q) {
-        const int rx = q.x - OX, ry = q.y - OY;
-        unsigned mxk = 0, myk = 0;
+    auto image_masks = [&](int rx, int ry, unsigned &mxk, unsigned &myk) {
+        mxk = 0;
+        myk = 0;
 #pragma unroll
         for (int k = -1; k <= 2; ++k) {
             const int vx = rx + k * MX, vy = ry + k * MY;
             if (vx >= wxlo - MX / 2 && vx <= wxhi + MX / 2) mxk |= 1u << (k + 1);
             if (vy >= wylo - MY / 2 && vy <= wyhi + MY / 2) myk |= 1u << (k + 1);
         }
+    };
+    auto add_images = [&](int lab, int2 q) {
+        const int rx = q.x - OX, ry = q.y - OY;
+        unsigned mxk, myk;
+        image_masks(rx, ry, mxk, myk);
         for (unsigned a = mxk; a; a &= a - 1) {
             const int cx = rx + (__ffs(a) - 2) * MX;
             for (unsigned b = myk; b; b &= b - 1) {
@@ -367,23 +372,50 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
         {   // one thread per cell of the square walks the cell's centres
             const int n0x = sx0.hi0 - sx0.lo0 + 1, ncx = n0x + (sx0.n == 2 ? sx0.hi1 - sx0.lo1 + 1 : 0);
             const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
-            if (t < ncx * ncy) {
-                const int ix = t % ncx, iy = t / ncx;
-                const int cellx = ix < n0x ? sx0.lo0 + ix : sx0.lo1 + (ix - n0x);
-                const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
-                const auto cs = gmem(B.cell_start);
-                const int e0 = cs[celly * B.ntx + cellx], e1 = cs[celly * B.ntx + cellx + 1];
-                for (int e = e0; e < e1; ++e) {
-                    const int2 q = ld_int2(B.cell_q, e);
-                    const int lab = gmem(B.cell_items)[e];
-                    const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
-                    atomicMin(&S.best, (unsigned long long)d);
-                    const int slot = atomicAdd(&S.ntmp, 1);
-                    if (slot < TMP_CAP) {
-                        S.tmp[slot] = lab;
-                        S.tmpq[slot] = q;
-                        S.tmpd[slot] = d;
+            // (at most 7 x 7 cells: wave 0 holds them all; list slots come
+            // from ballots and the bound from one wave minimum, no atomics)
+            if (t < 64) {
+                int e = 0, e1 = 0;
+                if (t < ncx * ncy) {
+                    const int ix = t % ncx, iy = t / ncx;
+                    const int cellx = ix < n0x ? sx0.lo0 + ix : sx0.lo1 + (ix - n0x);
+                    const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
+                    const auto cs = gmem(B.cell_start);
+                    e = cs[celly * B.ntx + cellx];
+                    e1 = cs[celly * B.ntx + cellx + 1];
+                }
+                unsigned long long dmin = ~0ull;
+                int base = 0;
+                while (__ballot(e < e1)) {
+                    const bool has = e < e1;
+                    int2 q = make_int2(0, 0);
+                    int lab = 0;
+                    long long d = 0;
+                    if (has) {
+                        q = ld_int2(B.cell_q, e);
+                        lab = gmem(B.cell_items)[e];
+                        d = d2q(tcx, tcy, q.x, q.y, MX, MY);
+                        dmin = min(dmin, (unsigned long long)d);
                     }
+                    const unsigned long long bm = __ballot(has);
+                    if (has) {
+                        const int slot = base + __popcll(bm & ((1ull << t) - 1ull));
+                        if (slot < TMP_CAP) {
+                            S.tmp[slot] = lab;
+                            S.tmpq[slot] = q;
+                            S.tmpd[slot] = d;
+                        }
+                    }
+                    base += __popcll(bm);
+                    ++e;
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long other = __shfl_xor(dmin, o, 64);
+                    dmin = other < dmin ? other : dmin;
+                }
+                if (t == 0) {
+                    S.best = dmin;
+                    S.ntmp = base;
                 }
             }
             __syncthreads();
@@ -397,8 +429,42 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
             if (rho <= cov_x && rho <= cov_y) {
                 const double rq2 = (256.0 * rho) * (256.0 * rho);
                 const int n = S.ntmp;
-                for (int j = t; j < n; j += DV_BLOCK)
-                    if ((double)S.tmpd[j] <= rq2) add_images(S.tmp[j], S.tmpq[j]);
+                // one atomic per wave for the list slots of its images
+                const int lane = t & 63;
+                for (int j0 = 0; j0 < n; j0 += DV_BLOCK) {
+                    const int j = j0 + t;
+                    unsigned mxk = 0, myk = 0;
+                    int rx = 0, ry = 0, lab = 0;
+                    if (j < n && (double)S.tmpd[j] <= rq2) {
+                        const int2 q = S.tmpq[j];
+                        rx = q.x - OX;
+                        ry = q.y - OY;
+                        lab = S.tmp[j];
+                        image_masks(rx, ry, mxk, myk);
+                    }
+                    const int c = __popc(mxk) * __popc(myk);
+                    int x = c;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int y = __shfl_up(x, o, 64);
+                        if (lane >= o) x += y;
+                    }
+                    const int wtot = __shfl(x, 63, 64);
+                    int wbase = 0;
+                    if (lane == 0 && wtot) wbase = atomicAdd(&S.ncand, wtot);
+                    wbase = __shfl(wbase, 0, 64);
+                    int slot = wbase + x - c;
+                    for (unsigned a = mxk; a; a &= a - 1) {
+                        const int cx = rx + (__ffs(a) - 2) * MX;
+                        for (unsigned b = myk; b; b &= b - 1) {
+                            if (slot < DV_CAND_CAP) {
+                                S.cx[slot] = cx;
+                                S.cy[slot] = ry + (__ffs(b) - 2) * MY;
+                                S.lab[slot] = lab;
+                            }
+                            ++slot;
+                        }
+                    }
+                }
                 __syncthreads();
                 done = S.ncand <= DV_CAND_CAP;
                 __syncthreads();
