@@ -11,6 +11,10 @@ chain the steps in the paper's order:
 * ``Sequence``           -- keeps the past frame and applies Sec. 3.2.3-3.2.4
 * ``classify``           -- event flags of the flips (Sec. 3.2.4, optional)
 
+Geometry: every function takes ``open_x`` / ``open_y`` (that axis has walls
+instead of wrapping; default periodic) and, where sites are coloured or
+labelled, ``obstacles`` (one byte per site, nonzero = obstacle; Sec. 3.2.1).
+
 Each function's docstring names the section it follows; the readings of the
 paper that the oracle fixes are stated in ``oracle.cpp``.
 """
@@ -33,6 +37,7 @@ _lib = None
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f32p = ctypes.POINTER(ctypes.c_float)
 _f64p = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(verbose: bool = False) -> str:
@@ -53,21 +58,21 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     i32, f32, i64 = ctypes.c_int32, ctypes.c_float, ctypes.c_int64
     lib.or_label.restype = i32
-    lib.or_label.argtypes = [_f32p, i32, i32, f32, i32, i32, _i32p]
+    lib.or_label.argtypes = [_f32p, i32, i32, f32, i32, i32, _u8p, i32, _i32p]
     lib.or_centroids.restype = None
-    lib.or_centroids.argtypes = [_i32p, i32, i32, i32, i32, _i32p, _i32p, _i32p, _i32p,
+    lib.or_centroids.argtypes = [_i32p, i32, i32, i32, i32, i32, _i32p, _i32p, _i32p, _i32p,
                                  _f64p, _f64p, _i32p]
     lib.or_owner.restype = None
-    lib.or_owner.argtypes = [i32, i32, i32, _i32p, _i32p, _i32p, i32]
+    lib.or_owner.argtypes = [i32, i32, i32, _u8p, i32, _i32p, _i32p, _i32p, i32]
     lib.or_colour_at.restype = i32
-    lib.or_colour_at.argtypes = [i64, i64, i32, i32, i32, _i32p, _i32p]
+    lib.or_colour_at.argtypes = [i64, i64, i32, i32, i32, i32, _i32p, _i32p]
     lib.or_edges.restype = i32
-    lib.or_edges.argtypes = [i32, i32, i32, _i32p, _i32p, _i32p, _i32p, i32]
+    lib.or_edges.argtypes = [i32, i32, i32, i32, _i32p, _i32p, _i32p, _i32p, i32]
     lib.or_edges_window.restype = i32
-    lib.or_edges_window.argtypes = [i32, i32, i32, _i32p, _i32p, i32, i32, i32, i32,
+    lib.or_edges_window.argtypes = [i32, i32, i32, _u8p, i32, _i32p, _i32p, i32, i32, i32, i32,
                                     _i32p, i32, i32]
     lib.or_match.restype = None
-    lib.or_match.argtypes = [i32, i32, i32, _i32p, _i32p, i32, _i32p, _i32p, _i32p, _i32p]
+    lib.or_match.argtypes = [i32, i32, i32, i32, _i32p, _i32p, i32, _i32p, _i32p, _i32p, _i32p]
     lib.or_diff.restype = i32
     lib.or_diff.argtypes = [i32, i32, _i32p, _i32p, i32, i32, _i32p, _i32p, _i32p, i32,
                             _i32p, _i32p]
@@ -83,18 +88,35 @@ def _c32(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+def _open(open_x: bool, open_y: bool) -> int:
+    return (1 if open_x else 0) | (2 if open_y else 0)
+
+
+def _obst(obstacles, lx: int, ly: int):
+    """(array kept alive, pointer) of the obstacle mask, or (None, None)."""
+    if obstacles is None:
+        return None, None
+    m = np.ascontiguousarray(np.asarray(obstacles) != 0, dtype=np.uint8)
+    if m.shape != (ly, lx):
+        raise ValueError(f"obstacle mask of shape {m.shape}, lattice is {(ly, lx)}")
+    return m, _p(m, _u8p)
+
+
 # --------------------------------------------------------------------- Sec. 3.1
-def label(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8):
+def label(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8,
+          obstacles=None, open_x: bool = False, open_y: bool = False):
     """Threshold + cluster labelling (Sec. 3.1).  Returns (labels int32 [ly,lx], K)."""
     f = np.ascontiguousarray(field, dtype=np.float32)
     ly, lx = f.shape
+    keep, om = _obst(obstacles, lx, ly)
     lab = np.empty((ly, lx), dtype=np.int32)
     K = _load().or_label(_p(f, _f32p), lx, ly, float(threshold), int(phase), int(conn),
-                         _p(lab, _i32p))
+                         om, _open(open_x, open_y), _p(lab, _i32p))
     return lab, int(K)
 
 
-def centroids(labels: np.ndarray, K: int, conn: int = 8) -> dict:
+def centroids(labels: np.ndarray, K: int, conn: int = 8, open_x: bool = False,
+              open_y: bool = False) -> dict:
     """Sizes and centres of mass (Sec. 3.1), exact Q.8 and float64."""
     lab = _c32(labels)
     ly, lx = lab.shape
@@ -102,7 +124,7 @@ def centroids(labels: np.ndarray, K: int, conn: int = 8) -> dict:
     out["fx"] = np.zeros(K, dtype=np.float64)
     out["fy"] = np.zeros(K, dtype=np.float64)
     if K:
-        _load().or_centroids(_p(lab, _i32p), lx, ly, int(conn), int(K),
+        _load().or_centroids(_p(lab, _i32p), lx, ly, int(conn), _open(open_x, open_y), int(K),
                              _p(out["n"], _i32p), _p(out["root"], _i32p),
                              _p(out["qx"], _i32p), _p(out["qy"], _i32p),
                              _p(out["fx"], _f64p), _p(out["fy"], _f64p),
@@ -111,60 +133,68 @@ def centroids(labels: np.ndarray, K: int, conn: int = 8) -> dict:
 
 
 # ------------------------------------------------------------------- Sec. 3.2.1
-def owner(lx: int, ly: int, qx, qy, nthreads: int = 0) -> np.ndarray:
-    """Digital Voronoi colouring by brute force over all centres (Sec. 3.2.1)."""
+def owner(lx: int, ly: int, qx, qy, nthreads: int = 0, obstacles=None, open_x: bool = False,
+          open_y: bool = False) -> np.ndarray:
+    """Digital Voronoi colouring by brute force over all centres (Sec. 3.2.1);
+    obstacle sites get MAXLINK."""
     qx, qy = _c32(qx), _c32(qy)
+    keep, om = _obst(obstacles, lx, ly)
     out = np.empty((ly, lx), dtype=np.int32)
-    _load().or_owner(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), _p(out, _i32p),
-                     int(nthreads))
+    _load().or_owner(lx, ly, _open(open_x, open_y), om, len(qx), _p(qx, _i32p), _p(qy, _i32p),
+                     _p(out, _i32p), int(nthreads))
     return out
 
 
-def colour_at(X: int, Y: int, lx: int, ly: int, qx, qy) -> int:
+def colour_at(X: int, Y: int, lx: int, ly: int, qx, qy, open_x: bool = False,
+              open_y: bool = False) -> int:
     """Colour of one Q.8 point (Sec. 3.2.1 rule at an arbitrary point)."""
     qx, qy = _c32(qx), _c32(qy)
-    return int(_load().or_colour_at(int(X), int(Y), lx, ly, len(qx), _p(qx, _i32p),
-                                    _p(qy, _i32p)))
+    return int(_load().or_colour_at(int(X), int(Y), lx, ly, _open(open_x, open_y), len(qx),
+                                    _p(qx, _i32p), _p(qy, _i32p)))
 
 
 # ------------------------------------------------------------------- Sec. 3.2.2
-def edges(lx: int, ly: int, qx, qy, owner_map: np.ndarray) -> np.ndarray:
-    """Delaunay couples from Voronoi-vertex sites (Sec. 3.2.2); int32 [E,2], sorted."""
+def edges(lx: int, ly: int, qx, qy, owner_map: np.ndarray, open_x: bool = False,
+          open_y: bool = False) -> np.ndarray:
+    """Delaunay couples from Voronoi-vertex sites (Sec. 3.2.2); int32 [E,2], sorted.
+    Obstacles enter through the owner map (MAXLINK sites)."""
     qx, qy = _c32(qx), _c32(qy)
     om = _c32(owner_map)
     lib = _load()
     cap = 1 << 12
     while True:
         ab = np.empty((cap, 2), dtype=np.int32)
-        E = lib.or_edges(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), _p(om, _i32p),
-                         _p(ab, _i32p), cap)
+        E = lib.or_edges(lx, ly, _open(open_x, open_y), len(qx), _p(qx, _i32p), _p(qy, _i32p),
+                         _p(om, _i32p), _p(ab, _i32p), cap)
         if E <= cap:
             return ab[:E].copy()
         cap = E
 
 
 def edges_window(lx: int, ly: int, qx, qy, x0: int, y0: int, w: int, h: int,
-                 nthreads: int = 0) -> np.ndarray:
+                 nthreads: int = 0, obstacles=None, open_x: bool = False,
+                 open_y: bool = False) -> np.ndarray:
     """Couples emitted by the sites of one window, colours by brute force."""
     qx, qy = _c32(qx), _c32(qy)
+    keep, om = _obst(obstacles, lx, ly)
     lib = _load()
     cap = 1 << 12
     while True:
         ab = np.empty((cap, 2), dtype=np.int32)
-        E = lib.or_edges_window(lx, ly, len(qx), _p(qx, _i32p), _p(qy, _i32p), x0, y0, w, h,
-                                _p(ab, _i32p), cap, int(nthreads))
+        E = lib.or_edges_window(lx, ly, _open(open_x, open_y), om, len(qx), _p(qx, _i32p),
+                                _p(qy, _i32p), x0, y0, w, h, _p(ab, _i32p), cap, int(nthreads))
         if E <= cap:
             return ab[:E].copy()
         cap = E
 
 
 # ------------------------------------------------------------------- Sec. 3.2.3
-def match(lx: int, ly: int, pqx, pqy, nqx, nqy):
+def match(lx: int, ly: int, pqx, pqy, nqx, nqy, open_x: bool = False, open_y: bool = False):
     """Kinematic isomorphism Phi_{P->N} and preimage counts (Sec. 3.2.3)."""
     pqx, pqy, nqx, nqy = _c32(pqx), _c32(pqy), _c32(nqx), _c32(nqy)
     phi = np.empty(len(pqx), dtype=np.int32)
     cnt = np.empty(len(nqx), dtype=np.int32)
-    _load().or_match(lx, ly, len(pqx), _p(pqx, _i32p), _p(pqy, _i32p), len(nqx),
+    _load().or_match(lx, ly, _open(open_x, open_y), len(pqx), _p(pqx, _i32p), _p(pqy, _i32p), len(nqx),
                      _p(nqx, _i32p), _p(nqy, _i32p), _p(phi, _i32p), _p(cnt, _i32p))
     return phi, cnt
 
@@ -253,17 +283,21 @@ class FrameResult:
     comps: dict
     owner: np.ndarray
     edges: np.ndarray
+    open_x: bool = False
+    open_y: bool = False
 
 
 def frame(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8,
-          nthreads: int = 0) -> FrameResult:
+          nthreads: int = 0, obstacles=None, open_x: bool = False,
+          open_y: bool = False) -> FrameResult:
     """Sec. 3.1 then Sec. 3.2.1-3.2.2 on one field."""
-    lab, K = label(field, threshold, phase, conn)
-    comps = centroids(lab, K, conn)
+    g = dict(open_x=open_x, open_y=open_y)
+    lab, K = label(field, threshold, phase, conn, obstacles, **g)
+    comps = centroids(lab, K, conn, **g)
     ly, lx = lab.shape
-    om = owner(lx, ly, comps["qx"], comps["qy"], nthreads)
-    ab = edges(lx, ly, comps["qx"], comps["qy"], om)
-    return FrameResult(lab, K, comps, om, ab)
+    om = owner(lx, ly, comps["qx"], comps["qy"], nthreads, obstacles, **g)
+    ab = edges(lx, ly, comps["qx"], comps["qy"], om, **g)
+    return FrameResult(lab, K, comps, om, ab, bool(open_x), bool(open_y))
 
 
 @dataclass
@@ -281,13 +315,16 @@ class Sequence:
     """Frame-to-frame driver: the past triangulation is kept between calls."""
 
     def __init__(self, threshold: float, phase: int = 0, conn: int = 8, nthreads: int = 0,
-                 classify_events: bool = False):
+                 classify_events: bool = False, obstacles=None, open_x: bool = False,
+                 open_y: bool = False):
         self.threshold, self.phase, self.conn, self.nthreads = threshold, phase, conn, nthreads
         self.classify_events = classify_events
+        self.obstacles, self.open_x, self.open_y = obstacles, open_x, open_y
         self.past: FrameResult | None = None
 
     def push(self, field: np.ndarray):
-        now = frame(field, self.threshold, self.phase, self.conn, self.nthreads)
+        now = frame(field, self.threshold, self.phase, self.conn, self.nthreads,
+                    self.obstacles, self.open_x, self.open_y)
         res = compare(self.past, now, self.classify_events)
         self.past = now
         return now, res
@@ -301,7 +338,7 @@ def compare(past: FrameResult | None, now: FrameResult, classify_events: bool = 
         return DiffResult(np.zeros((0, 6), np.int32), z, np.zeros(now.K, np.int32), z, 0, 0, 0)
     ly, lx = now.labels.shape
     phi, cnt = match(lx, ly, past.comps["qx"], past.comps["qy"], now.comps["qx"],
-                     now.comps["qy"])
+                     now.comps["qy"], now.open_x, now.open_y)
     fl, lt, (exP, exN, g) = diff(past.K, past.edges, phi, now.K, now.edges, cnt)
     if classify_events and len(fl):
         fl = fl.copy()

@@ -15,6 +15,16 @@
 //   Sec. 3.2.4  breaking / arising couples
 // Readings where the paper is silent or ambiguous are stated at each step.
 //
+// Geometry (Sec. 3.2.1 obstacles, Sec. 3.2.2 frame on the domain boundary):
+// every axis is periodic unless its bit is set in `open` (bit 0 = x, bit 1 =
+// y).  On an open axis there is no wrap: components do not connect across
+// the domain edge, offsets and distances are plain differences, and frame
+// points beyond the edge read as MAXLINK (the frame keeps only neighbours
+// inside the domain; a dropped point makes no gap).  `obst` (nullable, one
+// byte per site, row-major) marks obstacle sites: they belong to no component
+// and their colour is MAXLINK.  Inner-frame points are coloured by the
+// nearest-centre rule alone (the obstacle field lives on the sites).
+//
 // Single-threaded except the per-site nearest-centre loops, which may use
 // OpenMP over sites (each site is computed independently by the same loop).
 
@@ -85,26 +95,41 @@ const int NB4[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
 
 // Sec. 3.2.1: colour = label of the nearest centre by squared Euclidean
 // distance.  Reading: exact integer distance between Q.8 points with the
-// periodic minimum image; ties go to the lowest label; no centre -> MAXLINK.
-// The query point is first brought into [0, 256 L); then every difference to
-// a centre lies in (-256 L, 256 L) and one conditional shift gives the same
-// minimum image as wrap_signed.
+// periodic minimum image on periodic axes and the plain difference on open
+// ones; ties go to the lowest label; no centre -> MAXLINK.  On a periodic
+// axis the query point is first brought into [0, 256 L); then every
+// difference to a centre lies in (-256 L, 256 L) and one conditional shift
+// gives the same minimum image as wrap_signed.
 int32_t nearest_centre(int64_t X, int64_t Y, int K, const int32_t* qx, const int32_t* qy,
-                       int lx, int ly) {
+                       int lx, int ly, int open) {
     const int64_t MX = 256LL * lx, MY = 256LL * ly, hx = MX / 2, hy = MY / 2;
-    X = pos_mod(X, MX);
-    Y = pos_mod(Y, MY);
+    const bool ox = open & 1, oy = open & 2;
+    if (!ox) X = pos_mod(X, MX);
+    if (!oy) Y = pos_mod(Y, MY);
     int32_t best = MAXLINK;
     int64_t bd = INT64_MAX;
     for (int i = 0; i < K; ++i) {
         int64_t dx = X - qx[i], dy = Y - qy[i];
-        if (dx >= MX - hx) dx -= MX; else if (dx < -hx) dx += MX;
-        if (dy >= MY - hy) dy -= MY; else if (dy < -hy) dy += MY;
+        if (!ox) { if (dx >= MX - hx) dx -= MX; else if (dx < -hx) dx += MX; }
+        if (!oy) { if (dy >= MY - hy) dy -= MY; else if (dy < -hy) dy += MY; }
         const int64_t d = dx * dx + dy * dy;
         if (d < bd) { bd = d; best = i; }
     }
     return best;
 }
+
+// Site (x, y) moved by (dx, dy): false when it leaves the domain across an
+// open axis; otherwise (xx, yy) is the site, wrapped on periodic axes.
+bool step(int64_t x, int64_t y, int dx, int dy, int lx, int ly, int open, int64_t& xx, int64_t& yy) {
+    xx = x + dx;
+    yy = y + dy;
+    if (open & 1) { if (xx < 0 || xx >= lx) return false; } else xx = pos_mod(xx, lx);
+    if (open & 2) { if (yy < 0 || yy >= ly) return false; } else yy = pos_mod(yy, ly);
+    return true;
+}
+
+// Offset between two coordinates of one axis: minimum image when periodic.
+int64_t axis_off(int64_t v, int64_t L, bool is_open) { return is_open ? v : wrap_signed(v, L); }
 
 // Frame of site k (Sec. 3.2.2).  The naming figure is missing; reading from
 // the mnemonics: s = "site", p/m = plus/minus along x/y.  Cyclic order:
@@ -154,17 +179,19 @@ void site_rules(int32_t ck, const int32_t f[8], Mid mid, std::set<std::pair<int3
 extern "C" {
 
 // ---------------------------------------------------------------------------
-// Sec. 3.1 -- cluster labelling.  Connected sets of inside sites on the torus.
+// Sec. 3.1 -- cluster labelling.  Connected sets of inside sites (periodic
+// axes wrap, open axes do not; obstacle sites are never inside).
 // Reading: labels 0..K-1 are given in increasing order of each component's
 // smallest linear index y*lx + x; outside sites get -1.  Sequential
 // union-find over the sites in raster order.
 // Returns K.
 // ---------------------------------------------------------------------------
 int32_t or_label(const float* field, int32_t lx, int32_t ly, float thr, int32_t phase,
-                 int32_t conn, int32_t* labels) {
+                 int32_t conn, const uint8_t* obst, int32_t open, int32_t* labels) {
     const int64_t N = (int64_t)lx * ly;
     std::vector<uint8_t> in(N);
-    for (int64_t s = 0; s < N; ++s) in[s] = inside(field[s], thr, phase) ? 1 : 0;
+    for (int64_t s = 0; s < N; ++s)
+        in[s] = (inside(field[s], thr, phase) && !(obst && obst[s])) ? 1 : 0;
     UF uf((size_t)N);
     const int (*nb)[2] = conn == 4 ? NB4 : NB8;
     const int nn = conn == 4 ? 4 : 8;
@@ -173,7 +200,8 @@ int32_t or_label(const float* field, int32_t lx, int32_t ly, float thr, int32_t 
             const int64_t s = (int64_t)y * lx + x;
             if (!in[s]) continue;
             for (int k = 0; k < nn; ++k) {
-                const int64_t xx = pos_mod(x + nb[k][0], lx), yy = pos_mod(y + nb[k][1], ly);
+                int64_t xx, yy;
+                if (!step(x, y, nb[k][0], nb[k][1], lx, ly, open, xx, yy)) continue;
                 const int64_t t = yy * lx + xx;
                 if (in[t]) uf.unite((int32_t)s, (int32_t)t);
             }
@@ -194,16 +222,18 @@ int32_t or_label(const float* field, int32_t lx, int32_t ly, float thr, int32_t 
 // of the bubble and divide by its size" (unweighted; the density-weighted
 // definition of Sec. 2 is not what the procedure computes).
 // Reading for the torus: offsets are taken relative to the component's
-// smallest-index site r with the signed minimum image, so
+// smallest-index site r with the signed minimum image (plain differences on
+// an open axis, where the mod below changes nothing), so
 //   S = sum_s wrap(s - r),  centre = r + S/n  (mod L).
 // Q.8 (units of 1/256 site) = 256 r + round_half_up(256 S / n), i.e.
 //   256 r + floor((512 S + n) / (2 n))  mod 256 L,   exact integers.
 // The float64 centre is r + (double)S/(double)n, wrapped once into [0, L).
 // A component is "ambiguous" when two adjacent member sites get unwrapped
-// coordinates more than one site apart (it crosses its own antipodal line).
+// coordinates more than one site apart (it crosses its own antipodal line);
+// only a periodic axis can do that.
 // Outputs (length K): n, root (linear index), qx, qy, fx, fy, amb (0/1).
 // ---------------------------------------------------------------------------
-void or_centroids(const int32_t* labels, int32_t lx, int32_t ly, int32_t conn, int32_t K,
+void or_centroids(const int32_t* labels, int32_t lx, int32_t ly, int32_t conn, int32_t open, int32_t K,
                   int32_t* n_out, int32_t* root_out, int32_t* qx, int32_t* qy,
                   double* fx, double* fy, int32_t* amb) {
     const int64_t N = (int64_t)lx * ly;
@@ -220,14 +250,16 @@ void or_centroids(const int32_t* labels, int32_t lx, int32_t ly, int32_t conn, i
             const int32_t l = labels[(int64_t)y * lx + x];
             if (l < 0) continue;
             const int64_t rx = rootv[l] % lx, ry = rootv[l] / lx;
-            const int64_t ux = rx + wrap_signed(x - rx, lx), uy = ry + wrap_signed(y - ry, ly);
+            const bool ox = open & 1, oy = open & 2;
+            const int64_t ux = rx + axis_off(x - rx, lx, ox), uy = ry + axis_off(y - ry, ly, oy);
             n[l] += 1;
             sx[l] += ux - rx;
             sy[l] += uy - ry;
             for (int k = 0; k < nn; ++k) {
-                const int64_t xx = pos_mod(x + nb[k][0], lx), yy = pos_mod(y + nb[k][1], ly);
+                int64_t xx, yy;
+                if (!step(x, y, nb[k][0], nb[k][1], lx, ly, open, xx, yy)) continue;
                 if (labels[yy * lx + xx] != l) continue;
-                const int64_t vx = rx + wrap_signed(xx - rx, lx), vy = ry + wrap_signed(yy - ry, ly);
+                const int64_t vx = rx + axis_off(xx - rx, lx, ox), vy = ry + axis_off(yy - ry, ly, oy);
                 if (vx - ux > 1 || ux - vx > 1 || vy - uy > 1 || uy - vy > 1) a[l] = 1;
             }
         }
@@ -249,44 +281,51 @@ void or_centroids(const int32_t* labels, int32_t lx, int32_t ly, int32_t conn, i
 
 // ---------------------------------------------------------------------------
 // Sec. 3.2.1 -- digital Voronoi colouring: one evaluation per site over all
-// centres.  owner[y*lx + x] = nearest_centre(256x, 256y).
+// centres.  owner[y*lx + x] = nearest_centre(256x, 256y), MAXLINK on obstacles.
 // ---------------------------------------------------------------------------
-void or_owner(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, const int32_t* qy,
-              int32_t* owner, int32_t nthreads) {
+void or_owner(int32_t lx, int32_t ly, int32_t open, const uint8_t* obst, int32_t K,
+              const int32_t* qx, const int32_t* qy, int32_t* owner, int32_t nthreads) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
 #endif
     for (int32_t y = 0; y < ly; ++y)
         for (int32_t x = 0; x < lx; ++x)
-            owner[(int64_t)y * lx + x] = nearest_centre(256LL * x, 256LL * y, K, qx, qy, lx, ly);
+            owner[(int64_t)y * lx + x] = (obst && obst[(int64_t)y * lx + x])
+                                             ? MAXLINK
+                                             : nearest_centre(256LL * x, 256LL * y, K, qx, qy, lx, ly, open);
     (void)nthreads;
 }
 
 // Colour of an arbitrary Q.8 point (used by tests for single sites / midpoints).
-int32_t or_colour_at(int64_t X, int64_t Y, int32_t lx, int32_t ly, int32_t K,
+int32_t or_colour_at(int64_t X, int64_t Y, int32_t lx, int32_t ly, int32_t open, int32_t K,
                      const int32_t* qx, const int32_t* qy) {
-    return nearest_centre(X, Y, K, qx, qy, lx, ly);
+    return nearest_centre(X, Y, K, qx, qy, lx, ly, open);
 }
 
 // ---------------------------------------------------------------------------
 // Sec. 3.2.2 -- Delaunay couples from Voronoi-vertex sites, on a full colour
 // map.  Inner-frame colours are evaluated on demand with the same nearest-
-// centre rule.  The compressed adjacency (sort + unique of the rows) is the
+// centre rule; frame points beyond an open edge read as MAXLINK.  The
+// compressed adjacency (sort + unique of the rows) is the
 // ordered set of undirected couples (a < b).  Writes up to cap couples as
 // (a, b) pairs into ab and returns the total count E.
 // ---------------------------------------------------------------------------
-int32_t or_edges(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, const int32_t* qy,
-                 const int32_t* owner, int32_t* ab, int32_t cap) {
+int32_t or_edges(int32_t lx, int32_t ly, int32_t open, int32_t K, const int32_t* qx,
+                 const int32_t* qy, const int32_t* owner, int32_t* ab, int32_t cap) {
     std::set<std::pair<int32_t, int32_t>> E;
     for (int32_t y = 0; y < ly; ++y)
         for (int32_t x = 0; x < lx; ++x) {
             int32_t f[8];
-            for (int i = 0; i < 8; ++i)
-                f[i] = owner[pos_mod(y + FRAME[i][1], ly) * lx + pos_mod(x + FRAME[i][0], lx)];
+            for (int i = 0; i < 8; ++i) {
+                int64_t xx, yy;
+                f[i] = step(x, y, FRAME[i][0], FRAME[i][1], lx, ly, open, xx, yy) ? owner[yy * lx + xx]
+                                                                                   : MAXLINK;
+            }
             const int32_t ck = owner[(int64_t)y * lx + x];
             auto mid = [&](int r) {
-                return nearest_centre(256LL * x + INNER[r][0], 256LL * y + INNER[r][1], K, qx, qy, lx, ly);
+                return nearest_centre(256LL * x + INNER[r][0], 256LL * y + INNER[r][1], K, qx, qy, lx, ly,
+                                      open);
             };
             site_rules(ck, f, mid, E);
         }
@@ -299,11 +338,12 @@ int32_t or_edges(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, const int
 }
 
 // Same rules restricted to the sites of the window [x0, x0+w) x [y0, y0+h)
-// (periodic), colouring the window and its one-site ring by brute force.
+// (inside the domain), colouring the window and its one-site ring by brute
+// force (ring sites beyond an open edge and obstacle sites are MAXLINK).
 // Used to check large lattices one region at a time.
-int32_t or_edges_window(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, const int32_t* qy,
-                        int32_t x0, int32_t y0, int32_t w, int32_t h, int32_t* ab, int32_t cap,
-                        int32_t nthreads) {
+int32_t or_edges_window(int32_t lx, int32_t ly, int32_t open, const uint8_t* obst, int32_t K,
+                        const int32_t* qx, const int32_t* qy, int32_t x0, int32_t y0, int32_t w,
+                        int32_t h, int32_t* ab, int32_t cap, int32_t nthreads) {
     const int32_t W = w + 2, H = h + 2;
     std::vector<int32_t> c((size_t)W * H);
 #ifdef _OPENMP
@@ -312,8 +352,11 @@ int32_t or_edges_window(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, co
 #endif
     for (int32_t j = 0; j < H; ++j)
         for (int32_t i = 0; i < W; ++i) {
-            const int64_t x = pos_mod(x0 - 1 + i, lx), y = pos_mod(y0 - 1 + j, ly);
-            c[(size_t)j * W + i] = nearest_centre(256 * x, 256 * y, K, qx, qy, lx, ly);
+            int64_t x, y;
+            int32_t col = MAXLINK;
+            if (step(x0, y0, i - 1, j - 1, lx, ly, open, x, y) && !(obst && obst[y * lx + x]))
+                col = nearest_centre(256 * x, 256 * y, K, qx, qy, lx, ly, open);
+            c[(size_t)j * W + i] = col;
         }
     (void)nthreads;
     std::set<std::pair<int32_t, int32_t>> E;
@@ -324,7 +367,7 @@ int32_t or_edges_window(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, co
             const int32_t ck = c[(size_t)j * W + i];
             const int64_t x = pos_mod(x0 - 1 + i, lx), y = pos_mod(y0 - 1 + j, ly);
             auto mid = [&](int r) {
-                return nearest_centre(256 * x + INNER[r][0], 256 * y + INNER[r][1], K, qx, qy, lx, ly);
+                return nearest_centre(256 * x + INNER[r][0], 256 * y + INNER[r][1], K, qx, qy, lx, ly, open);
             };
             site_rules(ck, f, mid, E);
         }
@@ -339,16 +382,16 @@ int32_t or_edges_window(int32_t lx, int32_t ly, int32_t K, const int32_t* qx, co
 // ---------------------------------------------------------------------------
 // Sec. 3.2.3 -- kinematic isomorphism: each past centre is matched to the
 // nearest now centre ("comparing the two sets of centers of mass").
-// Reading: exact Q.8 periodic squared distance, ties to the lowest now label,
-// no distance cut-off.  cnt[n] = number of past labels mapped to n.
-// With KN == 0 every phi is -1.
+// Reading: exact Q.8 squared distance (minimum image on periodic axes), ties
+// to the lowest now label, no distance cut-off.  cnt[n] = number of past
+// labels mapped to n.  With KN == 0 every phi is -1.
 // ---------------------------------------------------------------------------
-void or_match(int32_t lx, int32_t ly, int32_t KP, const int32_t* pqx, const int32_t* pqy,
+void or_match(int32_t lx, int32_t ly, int32_t open, int32_t KP, const int32_t* pqx, const int32_t* pqy,
               int32_t KN, const int32_t* nqx, const int32_t* nqy, int32_t* phi, int32_t* cnt) {
     for (int32_t n = 0; n < KN; ++n) cnt[n] = 0;
     for (int32_t p = 0; p < KP; ++p) {
         if (KN == 0) { phi[p] = -1; continue; }
-        const int32_t m = nearest_centre(pqx[p], pqy[p], KN, nqx, nqy, lx, ly);
+        const int32_t m = nearest_centre(pqx[p], pqy[p], KN, nqx, nqy, lx, ly, open);
         phi[p] = m;
         cnt[m] += 1;
     }

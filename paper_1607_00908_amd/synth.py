@@ -16,6 +16,11 @@ Generators
 * ``GRFSim``    -- periodic Gaussian random field (white noise smoothed by a
   Gaussian kernel via FFT, standardised), evolved as AR(1).  Thresholding it
   gives irregular "bubbles" like the random-field sample of Sec. 1.
+* ``ChannelSim`` -- disks in a channel with walls across x and rectangular
+  posts on the left wall, drifting along y with a parabolic (Poiseuille-like)
+  profile plus jitter, kept clear of each other, the walls and the posts.
+  Stand-in for the pressure-driven emulsion in a channel with posts of Sec. 4;
+  ``obstacles()`` gives the posts as a binary site field.
 * ``tiny_random_field`` -- uniform noise for fuzzing small lattices.
 
 All arithmetic is float64; fields are cast to float32 exactly once.
@@ -30,6 +35,7 @@ import numpy as np
 __all__ = [
     "DiskSim",
     "GRFSim",
+    "ChannelSim",
     "tiny_random_field",
     "disk_field",
     "workload",
@@ -180,6 +186,130 @@ class DiskSim:
             yield self.field()
 
 
+@dataclass
+class ChannelSim:
+    """Disks in a channel: walls at x = -1/2 and x = lx - 1/2 (no wrap in x),
+    periodic in y, posts of post_w x post_h sites on the left wall every
+    post_period sites along y.  Each frame moves disk i by
+    vmax * 4 u (1 - u) along y (u = x / lx, the parabolic profile of a
+    pressure-driven channel flow) plus Gaussian jitter, then relaxes overlaps
+    with each other, the walls and the posts (gap sites kept free)."""
+
+    lx: int
+    ly: int
+    n_disks: int
+    r_min: float
+    r_max: float
+    post_w: int
+    post_h: int
+    post_period: int
+    vmax: float
+    sigma: float
+    seed: int
+    gap: float = 2.0
+    width: float = 2.0
+    relax_iters: int = 300
+    centers: np.ndarray = dc_field(init=False, repr=False)
+    radii: np.ndarray = dc_field(init=False, repr=False)
+    rng: np.random.Generator = dc_field(init=False, repr=False)
+
+    def __post_init__(self):
+        self.rng = np.random.default_rng(self.seed)
+        self.radii = self.rng.uniform(self.r_min, self.r_max, self.n_disks)
+        self.centers = np.stack([
+            self.rng.uniform(self.post_w, self.lx, self.n_disks),
+            self.rng.uniform(0, self.ly, self.n_disks)], axis=1)
+        self._relax()
+
+    def obstacles(self) -> np.ndarray:
+        """bool [ly, lx]: True on post sites."""
+        m = np.zeros((self.ly, self.lx), dtype=bool)
+        rows = (np.arange(self.ly) % self.post_period) < self.post_h
+        m[rows, :self.post_w] = True
+        return m
+
+    def _post_push(self, c: np.ndarray, r: np.ndarray) -> np.ndarray:
+        """Displacement that takes each disk gap/2 + r clear of the nearest
+        post rectangle [-inf, post_w - 1/2] x [y0 - 1/2, y0 + post_h - 1/2]."""
+        y0 = np.floor(c[:, 1] / self.post_period) * self.post_period
+        mv = np.zeros_like(c)
+        for off in (-self.post_period, 0.0, self.post_period):
+            lo = y0 + off - 0.5
+            hi = lo + self.post_h
+            nx = np.minimum(c[:, 0], self.post_w - 0.5)
+            ny = np.clip(c[:, 1], lo, hi)
+            dx, dy = c[:, 0] - nx, c[:, 1] - ny
+            d = np.sqrt(dx * dx + dy * dy)
+            need = r + self.gap
+            m = d < need
+            inside = d < 1e-9
+            ux = np.where(inside, 1.0, dx / np.where(inside, 1.0, d))
+            uy = np.where(inside, 0.0, dy / np.where(inside, 1.0, d))
+            amt = np.where(m, need - d + 1e-3, 0.0)
+            mv[:, 0] += amt * ux
+            mv[:, 1] += amt * uy
+        return mv
+
+    def _relax(self):
+        """Jacobi relaxation of disk pairs, walls and posts."""
+        from scipy.spatial import cKDTree
+        c = self.centers
+        r = self.radii
+        reach = 2.0 * float(np.max(r)) + self.gap if len(r) else 0.0
+        # x lies in [0, lx): a period of 2 lx in the tree never joins the walls
+        box = np.array([2.0 * self.lx, self.ly], dtype=np.float64)
+        lo_x = r + 0.5 * self.gap
+        hi_x = self.lx - 1.0 - r - 0.5 * self.gap
+        for _ in range(self.relax_iters):
+            c[:, 0] = np.clip(c[:, 0], lo_x, hi_x)
+            c[:, 1] %= self.ly
+            mv = self._post_push(c, r)
+            tree = cKDTree(c, boxsize=box)
+            pairs = tree.query_pairs(reach, output_type="ndarray")
+            if pairs.size:
+                i, j = pairs[:, 0], pairs[:, 1]
+                dx = c[i, 0] - c[j, 0]
+                dy = _wrap_delta(c[i, 1] - c[j, 1], self.ly)
+                d = np.sqrt(dx * dx + dy * dy)
+                over = r[i] + r[j] + self.gap - d
+                m = over > 0
+                i, j, dx, dy, d, over = i[m], j[m], dx[m], dy[m], d[m], over[m]
+                push = 0.5 * (over + 1e-3)
+                dsafe = np.where(d > 1e-9, d, 1.0)
+                ux = np.where(d > 1e-9, dx / dsafe, 1.0)
+                uy = np.where(d > 1e-9, dy / dsafe, 0.0)
+                np.add.at(mv[:, 0], i, push * ux)
+                np.add.at(mv[:, 1], i, push * uy)
+                np.add.at(mv[:, 0], j, -push * ux)
+                np.add.at(mv[:, 1], j, -push * uy)
+            if not np.any(mv):
+                break
+            c += mv
+        c[:, 0] = np.clip(c[:, 0], lo_x, hi_x)
+        c[:, 1] %= self.ly
+        self.centers = c
+
+    def field(self) -> np.ndarray:
+        f = disk_field(self.lx, self.ly, self.centers, self.radii, self.width)
+        f[self.obstacles()] = 0.0
+        return f
+
+    def step(self):
+        c = self.centers
+        u = c[:, 0] / self.lx
+        c[:, 1] += self.vmax * 4.0 * u * (1.0 - u)
+        c += self.rng.normal(0.0, self.sigma, c.shape)
+        self.centers = c
+        self._relax()
+
+    def frames(self, n: int):
+        """Yield n float32 fields; frame 0 is the initial placement."""
+        for t in range(n):
+            if t:
+                self.step()
+            yield self.field()
+
+
 def _smooth_noise(rng: np.random.Generator, lx: int, ly: int, sigma: float,
                   workers: int) -> np.ndarray:
     import scipy.fft as sfft
@@ -244,6 +374,12 @@ WORKLOADS = {
     # thresholded at +1 std
     "grf4096": dict(kind="grf", lx=4096, ly=4096, sigma=6.0, rho=0.98, seed=3,
                     frames=50, threshold=1.0, phase=0),
+    # 2048 (wall to wall, x) x 1024 (periodic, y) channel, posts 48 x 64 every
+    # 128 on the left wall, 2000 disks r~U(12.5,15), parabolic drift 1.0 at the
+    # centre line, jitter 0.2, 20 frames
+    "channel2048": dict(kind="channel", lx=2048, ly=1024, n_disks=2000, r_min=12.5,
+                        r_max=15.0, post_w=48, post_h=64, post_period=128, vmax=1.0,
+                        sigma=0.2, seed=5, frames=20, threshold=0.5, phase=0, open_x=True),
 }
 
 
@@ -256,6 +392,10 @@ def workload(name: str, **override):
                       spec["sigma"], spec["shear"], spec["seed"])
     elif spec["kind"] == "grf":
         sim = GRFSim(spec["lx"], spec["ly"], spec["sigma"], spec["rho"], spec["seed"])
+    elif spec["kind"] == "channel":
+        sim = ChannelSim(spec["lx"], spec["ly"], spec["n_disks"], spec["r_min"], spec["r_max"],
+                         spec["post_w"], spec["post_h"], spec["post_period"], spec["vmax"],
+                         spec["sigma"], spec["seed"])
     else:
         raise ValueError(spec["kind"])
     return sim, spec
