@@ -1,6 +1,6 @@
 """Benchmark of the per-frame detection path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload disks1024]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload disks1024|grf4096|channel2048]
 python bench.py --workload mixed64 [--fields 64] [--frames 5] [--steps 20]
 python bench.py --workload serve32 [--fields 32] [--gap-ms 2] [--steps 10000]
 
@@ -46,6 +46,8 @@ STAGE_BYTES = {
     "relabel": (4, 0),         # label map write
     "owner_edges": (4, 0),     # owner map write
 }
+# with an obstacle mask, both of these also read its byte per site
+OBSTACLE_BYTES = {"tile_ccl": 1, "owner_edges": 1}
 STAGE_SOURCES = {
     "tile_ccl": "k_label.hip", "relabel": "k_label.hip", "owner_edges": "k_voronoi.hip",
 }
@@ -149,10 +151,10 @@ def counters_from(fetch_csv: str, write_csv: str, stage: str, workload: str, map
     print(json.dumps({"stage": stage, "bytes_per_dispatch": round(bytes_per), **res}))
 
 
-def unbatched_rate(dv, args, spec, lx, ly, kmax, maps, stream, ptrs, F, N):
+def unbatched_rate(dv, args, spec, lx, ly, kmax, maps, stream, ptrs, F, N, geom):
     """The same pushes with one frame per launch of each stage."""
     det1 = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
-                       keep_maps=maps, max_batch=1, stream=stream)
+                       keep_maps=maps, max_batch=1, stream=stream, **geom)
     for i in range(args.warmup):
         det1.push(ptrs[i % F])
     det1.sync()
@@ -338,18 +340,21 @@ def bench_serve(args):
 
 
 def make_frames(workload: str, frames: int | None):
+    """(frames, spec, geometry keywords: walls and the obstacle mask)."""
     from paper_1607_00908_amd import synth
     sim, spec = synth.workload(workload)
     n = spec["frames"] if frames is None else frames
     out = list(sim.frames(n))
-    return out, spec
+    geom = {"open_x": bool(spec.get("open_x", False)), "open_y": bool(spec.get("open_y", False)),
+            "obstacles": sim.obstacles() if hasattr(sim, "obstacles") else None}
+    return out, spec, geom
 
 
-def cpu_baseline(frames, spec, seconds: float):
+def cpu_baseline(frames, spec, seconds: float, geom):
     """Run the oracle on the first frames until about `seconds` of CPU work."""
     import oracle
     ly, lx = frames[0].shape
-    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, nthreads=1)
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, nthreads=1, **geom)
     t0 = time.perf_counter()
     n = 0
     for f in frames:
@@ -418,7 +423,7 @@ def main():
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
     t0 = time.perf_counter()
-    frames, spec = make_frames(args.workload, args.frames)
+    frames, spec, geom = make_frames(args.workload, args.frames)
     spec["name"] = args.workload
     ly, lx = frames[0].shape
     N = lx * ly
@@ -430,7 +435,7 @@ def main():
     maps = not args.flips_only
     kmax = 32768 if N > (1 << 22) else 4096
     det = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
-                      keep_maps=maps, max_batch=args.max_batch)
+                      keep_maps=maps, max_batch=args.max_batch, **geom)
     F = ring.shape[0]
 
     # the ring is complete on the device (synchronised above): frames are
@@ -462,7 +467,7 @@ def main():
     # the same frames with one frame per launch (no batching), for comparison
     unbatched = None
     if not args.no_unbatched:
-        unbatched = unbatched_rate(dv, args, spec, lx, ly, kmax, maps, det.stream, ptrs, F, N)
+        unbatched = unbatched_rate(dv, args, spec, lx, ly, kmax, maps, det.stream, ptrs, F, N, geom)
 
     # latency: push -> flips returned, host-synchronous
     lat = []
@@ -477,7 +482,9 @@ def main():
     # one launch of a stage covers every frame of a batch
     stage_avg_ms = stage_ms / max(launches, 1)
     frames_per_launch = args.steps / max(launches, 1)
+    has_obst = geom["obstacles"] is not None
     per_site = STAGE_BYTES.get(args.stage, (0, 0))[0 if maps else 1]
+    per_site += OBSTACLE_BYTES.get(args.stage, 0) if has_obst else 0
     alg_bytes = per_site * N * frames_per_launch
     achieved = alg_bytes / (stage_avg_ms * 1e-3) / 1e9 if stage_avg_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -504,9 +511,12 @@ def main():
         "config": {"workload": args.workload, "lx": lx, "ly": ly, "frames_in_ring": F,
                    "components": info.n_components, "edges": info.n_edges,
                    "mode": "maps+flips" if maps else "flips-only",
+                   "walls": "".join(a for a in ("x", "y") if geom[f"open_{a}"]) or "none",
+                   "obstacle_sites": int(geom["obstacles"].sum()) if has_obst else 0,
                    "max_batch": args.max_batch or dv.DEFAULT_BATCH, "parallelism": "single-gpu"},
         "frames_per_s": round(args.steps / elapsed, 1),
-        "hbm_frac_pipeline": round(msites * 1e6 * (12 if maps else 4) / (HBM_PEAK_GBS * 1e9), 5),
+        "hbm_frac_pipeline": round(msites * 1e6 * ((12 if maps else 4) + (2 if has_obst else 0))
+                                   / (HBM_PEAK_GBS * 1e9), 5),
         "latency_ms": ({"p50": round(float(np.percentile(lat, 50)), 4),
                         "p99": round(float(np.percentile(lat, 99)), 4),
                         "samples": len(lat)} if len(lat) else None),
@@ -515,7 +525,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(frames, spec, args.cpu_seconds, geom)
     det.close()
     print(json.dumps(out))
 

@@ -17,7 +17,16 @@
  *
  * Conventions fixed by this library where the paper leaves them open:
  *   - lattice: lx * ly sites, site (x, y) at linear index y*lx + x, periodic
- *     in both axes; connectivity 8 (the D2Q9 directions) or 4;
+ *     in both axes unless DV_OPEN_X / DV_OPEN_Y put walls across an axis;
+ *     connectivity 8 (the D2Q9 directions) or 4;
+ *   - walls (Sec. 3.2.2, frame on the domain boundary): on a walled axis
+ *     components do not connect across the edge, offsets and distances are
+ *     plain differences, and frame points beyond the edge count as MAXLINK
+ *     (no gap, never a neighbour);
+ *   - obstacles (Sec. 3.2.1, supplementary binary field; DV_OBSTACLES): an
+ *     obstacle site is never inside a component and its colour is MAXLINK;
+ *     the other sites are coloured by straight-line distance as before, and
+ *     cells that meet only across an obstacle are not neighbours;
  *   - inside: rho > threshold (phase DV_PHASE_ABOVE, droplets) or
  *     rho < threshold (DV_PHASE_BELOW, bubbles); equality and NaN are outside;
  *   - labels 0..K-1 in increasing order of each component's smallest linear
@@ -56,6 +65,9 @@ extern "C" {
 /* flags */
 #define DV_KEEP_MAPS 1u  /* label / owner maps stay readable after each push */
 #define DV_CLASSIFY 2u   /* fill dv_flip.flags with the event classification */
+#define DV_OBSTACLES 4u  /* the context holds an obstacle mask (dv_set_obstacles) */
+#define DV_OPEN_X 8u     /* walls across x instead of the periodic wrap          */
+#define DV_OPEN_Y 16u    /* walls across y instead of the periodic wrap          */
 
 /* dv_flip.flags bits (with DV_CLASSIFY; Sec. 3.2.4, extraction of events).
  * Active points are the ends of the flips.  BULK: both ends are connected to
@@ -91,7 +103,8 @@ typedef struct {
     int32_t max_degree;      /* row capacity of the adjacency (Delaunay degree),
                                 4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
-    uint32_t flags;          /* DV_KEEP_MAPS | DV_CLASSIFY                         */
+    uint32_t flags;          /* DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES |
+                                DV_OPEN_X | DV_OPEN_Y                              */
     int32_t max_batch;       /* frames sent to the device together, 1 .. 16; 0
                                 selects 16.  Each holds its own per-site buffers. */
 } dv_config;
@@ -144,6 +157,14 @@ dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
  * capacity, is rejected: the next synchronising call reports
  * DV_ERR_CAPACITY and the past state stays that of the last accepted frame. */
 dv_status dv_push_frame(dv_ctx *ctx, const float *field_device);
+
+/* Set the obstacle mask (Sec. 3.2.1): lx*ly bytes, row-major, nonzero = obstacle;
+ * in device memory when mask_on_device is nonzero, else host memory; NULL
+ * clears every obstacle.  The context keeps its own copy: frames pushed
+ * before the call keep the previous mask, later ones use this one.  Queued
+ * frames are sent first and the call returns when the copy is complete.
+ * Needs DV_OBSTACLES at creation (else DV_ERR_STATE); the mask starts empty. */
+dv_status dv_set_obstacles(dv_ctx *ctx, const uint8_t *mask, int32_t mask_on_device);
 
 /* Wait for the device and copy the flips of the most recent push.  When
  * capacity is smaller than the count, *n_out receives the count, nothing is

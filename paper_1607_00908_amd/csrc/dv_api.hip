@@ -38,6 +38,7 @@ struct dv_ctx {
     int32_t *d_edge_scratch; // [2 * K_max] for the couple-list getter
     int32_t *d_edge_ab;      // [K_max * max_degree] pairs
     int32_t *d_edge_total;
+    uint8_t *d_obst;         // obstacle mask (DV_OBSTACLES), else null
     bool pushed;
     Prof prof;
     std::string err;
@@ -92,6 +93,7 @@ dv_status flush(dv_ctx *c) {
     G.kmax = H.kmax;
     G.nty = H.nty;
     G.classify = H.classify;
+    G.geom = (H.open_x | H.open_y | (H.obst != nullptr)) ? 1 : 0;
     launch_label(G, c->pending, c->stream, c->prof);
     launch_voronoi(G, c->stream, c->prof);
     launch_compare(G, c->stream, c->prof);
@@ -140,7 +142,8 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->max_degree != 0 && (cfg->max_degree < 4 || cfg->max_degree > 64))
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
-    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY)) return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
+    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y))
+        return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
         return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 16]");
     return DV_OK;
@@ -197,6 +200,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     c->h_state = nullptr;
     c->h_frame = nullptr;
     c->d_tab = nullptr;
+    c->d_obst = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -227,6 +231,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     B.ncells = B.ntx * B.nty;
     B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
     B.classify = (c->cfg.flags & DV_CLASSIFY) ? 1 : 0;
+    B.open_x = (c->cfg.flags & DV_OPEN_X) ? 1 : 0;
+    B.open_y = (c->cfg.flags & DV_OPEN_Y) ? 1 : 0;
     const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
     const size_t segs = (size_t)B.ly * B.ntx;
     auto comp_alloc = [&](CompBuf &C) {
@@ -237,6 +243,12 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     bool ok = dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
               dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
               dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
+    uint8_t *obst = nullptr;   // one mask for every slot (no obstacle until set)
+    if (ok && (c->cfg.flags & DV_OBSTACLES)) {
+        ok = dalloc(c, &obst, N);
+        B.obst = obst;
+        c->d_obst = obst;
+    }
     // per-slot buffers
     for (int k = 0; ok && k < c->batch; ++k) {
         Bufs &b = c->h_tab[k];
@@ -270,7 +282,8 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     hipStream_t s0 = c->stream;
     bool z = hipMemcpyAsync(c->d_tab, c->h_tab, sizeof(Bufs) * c->batch, hipMemcpyHostToDevice, s0) ==
                  hipSuccess &&
-             hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess;
+             hipMemsetAsync(B.st, 0, sizeof(SeqState), s0) == hipSuccess &&
+             (!obst || hipMemsetAsync(obst, 0, N, s0) == hipSuccess);
     for (int b = 0; z && b < 2; ++b)
         z = hipMemsetD32Async((hipDeviceptr_t)B.past[b].adj, DV_EMPTY, K * B.maxdeg, s0) == hipSuccess;
     for (int k = 0; z && k < c->batch; ++k) {
@@ -306,6 +319,24 @@ dv_status dv_sync(dv_ctx *c) {
     if (!c) return DV_ERR_ARG;
     (void)hipSetDevice(c->device);
     return drain(c);
+}
+
+dv_status dv_set_obstacles(dv_ctx *c, const uint8_t *mask, int32_t mask_on_device) {
+    if (!c) return DV_ERR_ARG;
+    if (!c->d_obst) return fail(c, DV_ERR_STATE, "context made without DV_OBSTACLES");
+    (void)hipSetDevice(c->device);
+    // frames pushed before this call keep the mask they were pushed with
+    dv_status s = flush(c);
+    if (s != DV_OK) return s;
+    const size_t N = (size_t)c->cfg.lx * c->cfg.ly;
+    hipError_t e;
+    if (!mask) e = hipMemsetAsync(c->d_obst, 0, N, c->stream);
+    else
+        e = hipMemcpyAsync(c->d_obst, mask, N, mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream);
+    if (e != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, DV_ERR_DEVICE, std::string("mask copy failed: ") + hipGetErrorString(e));
+    return DV_OK;
 }
 
 dv_status dv_get_info(dv_ctx *c, dv_frame_info *info) {
@@ -563,6 +594,7 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
         G.kmax = std::max(G.kmax, b.kmax);
         G.nty = std::max(G.nty, b.nty);
         G.classify |= b.classify;
+        G.geom |= (b.open_x | b.open_y | (b.obst != nullptr)) ? 1 : 0;
         alike = alike && b.ncells == g->h_tab[members[0]].ncells && b.nty == g->h_tab[members[0]].nty;
     }
     G.tiles = G.tbase[n];

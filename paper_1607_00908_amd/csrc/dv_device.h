@@ -1,5 +1,6 @@
-// Device helpers shared by the HIP sources of libdv: exact periodic Q.8
-// distances and the bucket grid of centres (one cell per 32x32 tile).
+// Device helpers shared by the HIP sources of libdv: exact Q.8 distances
+// (minimum image on periodic axes, plain on walled ones) and the bucket grid
+// of centres (one cell per 32x32 tile).
 #pragma once
 
 #include "dv_internal.h"
@@ -33,7 +34,13 @@ __device__ __forceinline__ int wrap_q(int v, int M) {
     return v;
 }
 
-// squared periodic distance between Q.8 points; X, Y, cx, cy in [0, M)
+// Wrap period (Q.8) of an axis for distances: 256 L on a periodic axis.  On
+// a walled axis 512 L: no difference of two in-domain points (|v| < 256 L)
+// reaches half of it, so wrap_q leaves every difference as it is.
+__device__ __forceinline__ int qperiod(int L, int open) { return open ? 512 * L : 256 * L; }
+
+// squared distance between Q.8 points; X, Y, cx, cy in [0, 256 L); MX, MY
+// wrap periods (qperiod)
 __device__ __forceinline__ long long d2q(int X, int Y, int cx, int cy, int MX, int MY) {
     const int dx = wrap_q(X - cx, MX), dy = wrap_q(Y - cy, MY);
     return (long long)dx * dx + (long long)dy * dy;
@@ -53,10 +60,19 @@ struct Span {
     __device__ __forceinline__ int hi(int i) const { return i ? hi1 : hi0; }
 };
 
-// Cells whose sites meet the periodic site interval [a, b] (integers, a <= b).
-__device__ __forceinline__ Span span_sites(int a, int b, int L) {
+// Cells whose sites meet the site interval [a, b] (integers, a <= b): wrapped
+// on a periodic axis, cut at the walls on an open one.
+__device__ __forceinline__ Span span_sites(int a, int b, int L, int open) {
     Span s;
     const int ncell = (L + DV_TILE - 1) / DV_TILE;
+    if (open) {
+        a = max(a, 0);
+        b = min(b, L - 1);
+        s.lo1 = 0; s.hi1 = -1;
+        if (a > b) { s.n = 0; s.lo0 = 0; s.hi0 = -1; }
+        else { s.n = 1; s.lo0 = a / DV_TILE; s.hi0 = b / DV_TILE; }
+        return s;
+    }
     if (b - a >= L - 1) {
         s.n = 1; s.lo0 = 0; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = -1;
         return s;
@@ -71,9 +87,14 @@ __device__ __forceinline__ Span span_sites(int a, int b, int L) {
     return s;
 }
 
-// Cells within Chebyshev cell distance R of cell c (periodic, no repeats).
-__device__ __forceinline__ Span span_cells(int c, int R, int ncell) {
+// Cells within Chebyshev cell distance R of cell c (no repeats; wrapped on a
+// periodic axis, cut at the walls on an open one).
+__device__ __forceinline__ Span span_cells(int c, int R, int ncell, int open) {
     Span s;
+    if (open) {
+        s.n = 1; s.lo0 = max(c - R, 0); s.hi0 = min(c + R, ncell - 1); s.lo1 = 0; s.hi1 = -1;
+        return s;
+    }
     if (2 * R + 1 >= ncell) {
         s.n = 1; s.lo0 = 0; s.hi0 = ncell - 1; s.lo1 = 0; s.hi1 = -1;
         return s;
@@ -93,18 +114,18 @@ __device__ __forceinline__ bool span_full(const Span &s, int ncell) {
     return s.n == 1 && s.lo0 == 0 && s.hi0 == ncell - 1;
 }
 
-// Nearest now centre of the Q.8 point (X, Y) in [0,MX) x [0,MY), exact, ties to
-// the lowest label, by the bucket grid.  K >= 1.  First a growing square of
+// Nearest now centre of the Q.8 point (X, Y) in [0, 256 lx) x [0, 256 ly),
+// exact, ties to the lowest label, by the bucket grid.  K >= 1.  First a growing square of
 // cells around the point's cell until a centre is seen; its distance bounds
 // the answer, so every cell meeting the disc of that radius (+1 site) around
 // the point is then scanned.
 __device__ int point_nearest(const Bufs &B, int X, int Y) {
-    const int MX = 256 * B.lx, MY = 256 * B.ly;
+    const int MX = qperiod(B.lx, B.open_x), MY = qperiod(B.ly, B.open_y);
     const int cx = X >> 13, cy = Y >> 13;
     const auto cs = gmem(B.cell_start);
     long long bd = LLONG_MAX;
     for (int R = 1;; R *= 2) {
-        const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
+        const Span sx = span_cells(cx, R, B.ntx, B.open_x), sy = span_cells(cy, R, B.nty, B.open_y);
         for (int ry = 0; ry < sy.n; ++ry)
             for (int row = sy.lo(ry); row <= sy.hi(ry); ++row)
                 for (int rx = 0; rx < sx.n; ++rx) {
@@ -120,8 +141,8 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
     // disc of radius sqrt(bd) + 1 site around the point
     const double rho = sqrt((double)bd) / 256.0 + 1.0;
     const double px = X / 256.0, py = Y / 256.0;
-    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx);
-    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly);
+    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx, B.open_x);
+    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly, B.open_y);
     long long best = LLONG_MAX;
     int bl = DV_EMPTY;
     for (int ry = 0; ry < sy.n; ++ry)
@@ -151,14 +172,14 @@ __device__ __forceinline__ void wave_min_dl(long long &d, int &lab) {
 // lane j takes the (row, column range) pairs j, j + 64, ...  Every lane of the
 // wave must call it with the same point; every lane gets the answer.
 __device__ int wave_nearest(const Bufs &B, int X, int Y) {
-    const int MX = 256 * B.lx, MY = 256 * B.ly;
+    const int MX = qperiod(B.lx, B.open_x), MY = qperiod(B.ly, B.open_y);
     const int cx = X >> 13, cy = Y >> 13;
     const int lane = threadIdx.x & 63;
     const auto cs = gmem(B.cell_start);
     long long bd = LLONG_MAX;
     int dummy = 0;
     for (int R = 1;; R *= 2) {
-        const Span sx = span_cells(cx, R, B.ntx), sy = span_cells(cy, R, B.nty);
+        const Span sx = span_cells(cx, R, B.ntx, B.open_x), sy = span_cells(cy, R, B.nty, B.open_y);
         const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
         for (int j = lane; j < nrows * sx.n; j += 64) {
             const int ri = j / sx.n, c = j % sx.n;
@@ -175,8 +196,8 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
     }
     const double rho = sqrt((double)bd) / 256.0 + 1.0;
     const double px = X / 256.0, py = Y / 256.0;
-    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx);
-    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly);
+    const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), B.lx, B.open_x);
+    const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), B.ly, B.open_y);
     const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
     long long best = LLONG_MAX;
     int bl = DV_EMPTY;

@@ -77,6 +77,8 @@ struct Bufs {
     int32_t ncells;        // bucket grid = tile grid
     int32_t keep_maps;     // write the label / owner maps
     int32_t classify;      // fill the flips' event flags
+    int32_t open_x, open_y;  // 1: walls across that axis instead of wrapping
+    const uint8_t *obst;   // [N] obstacle sites (nonzero), or null: none
     int32_t *parent;       // [N] union-find over tile-border sites and piece roots
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
@@ -136,6 +138,7 @@ struct Batch {
     int tpe, bpe;          // tiles / bands of every entry when all are alike, else 0
     int kmax, nty;         // largest K_max and band count (launch shapes)
     int classify;          // some entry classifies events
+    int geom;              // some entry has walls or obstacles (general kernels)
     int idx[DV_MAX_ENTRIES];        // table row of each entry
     int tbase[DV_MAX_ENTRIES + 1];  // first flat tile of each entry
     int bbase[DV_MAX_ENTRIES + 1];  // first flat band (32 rows) of each entry

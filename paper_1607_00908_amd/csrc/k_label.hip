@@ -4,7 +4,8 @@
 //   k_tile_ccl   threshold + union-find of each tile in LDS; every tile-border
 //                site and every tile-local root ("piece") gets an entry in the
 //                global parent array (global linear site indices);
-//   k_merge      unions across tile borders and the periodic seams;
+//   k_merge      unions across tile borders and the periodic seams (none
+//                across a wall);
 //   k_resolve    per band of 32 rows: each piece finds its global root;
 //                component roots (the smallest linear index of each component)
 //                are marked in a bitmap of (row, tile column) segments, which
@@ -131,22 +132,26 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 // responsibility column -- column x + 1 for every site, and additionally
 // columns a - 1 and a for the first site a of a run (8-connectivity), or
 // column x for every site (4-connectivity).
+template <bool GEOM>
 __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int tw, int th, int *L,
                          uint32_t *rowm) {
     const int t = threadIdx.x, cx = t & 31, ry = t >> 5, lane = t & 63;
     // the four loads are issued together (an out-of-tile lane reads the tile
     // origin and ignores it)
     float v[4];
+    uint8_t ob[4] = {0, 0, 0, 0};   // obstacle sites are never inside
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
         const bool ok = cx < tw && y < th;
-        v[i] = field[ok ? (size_t)(y0 + y) * B.lx + x0 + cx : (size_t)y0 * B.lx + x0];
+        const size_t g = ok ? (size_t)(y0 + y) * B.lx + x0 + cx : (size_t)y0 * B.lx + x0;
+        v[i] = field[g];
+        if (GEOM && B.obst) ob[i] = gmem(B.obst)[g];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
-        const bool in = cx < tw && y < th && is_in(v[i], B.thr, B.phase);
+        const bool in = cx < tw && y < th && !ob[i] && is_in(v[i], B.thr, B.phase);
         const unsigned long long bal = __ballot(in);
         const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (cx == 0) rowm[y] = m;
@@ -208,6 +213,9 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
     __syncthreads();
 }
 
+// GEOM: some entry of the launch has walls or obstacles; the periodic,
+// unobstructed instance carries none of their tests.
+template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
     }
 
-    tile_ccl(B, F.p[e], x0, y0, tw, th, L, rowm);
+    tile_ccl<GEOM>(B, F.p[e], x0, y0, tw, th, L, rowm);
 
     const int cx = t & 31, ry = t >> 5;
 #pragma unroll
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
 // column against the next column (periodic); lane 32 + j takes column j of
 // the last row against the next row.  Together they cover every adjacent
 // pair that crosses a tile border, including the diagonal pairs at tile
-// corners and the periodic seams.  Uniting two sites is uniting the values they hold, so the pairs of
+// corners and the periodic seams; a pair across a wall is not formed.  Uniting two sites is uniting the values they hold, so the pairs of
 // held values are united, and a pair equal to one the previous thread of the
 // same line unites is skipped (two pieces usually touch along many sites).
 __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], bool conn8, bool active,
@@ -309,6 +317,7 @@ __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], boo
     }
 }
 
+template <bool GEOM>
 __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch G) {
     // one wave per tile, four tiles per block
     const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -326,30 +335,32 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
     bool active;
     if (lane < 32) {
         // row j of the last column against the next column
-        active = j < th;
+        const int x = x0 + tw - 1, y = y0 + j;
+        active = j < th && !(GEOM && B.open_x && x + 1 == lx);
         if (active) {
-            const int x = x0 + tw - 1, y = y0 + j;
             const int xn = (x + 1 == lx) ? 0 : x + 1;
             ps = gmem(B.parent)[y * lx + x];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int yn = y + k - 1;
+                const bool cut = GEOM && B.open_y && (yn < 0 || yn >= ly);
                 yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
-                pu[k] = gmem(B.parent)[yn * lx + xn];
+                pu[k] = cut ? -1 : gmem(B.parent)[yn * lx + xn];
             }
         }
     } else {
         // column j of the last row against the next row
-        active = j < tw;
+        const int x = x0 + j, y = y0 + th - 1;
+        active = j < tw && !(GEOM && B.open_y && y + 1 == ly);
         if (active) {
-            const int x = x0 + j, y = y0 + th - 1;
             const int yn = (y + 1 == ly) ? 0 : y + 1;
             ps = gmem(B.parent)[y * lx + x];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int xn = x + k - 1;
+                const bool cut = GEOM && B.open_x && (xn < 0 || xn >= lx);
                 xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
-                pu[k] = gmem(B.parent)[yn * lx + xn];
+                pu[k] = cut ? -1 : gmem(B.parent)[yn * lx + xn];
             }
         }
     }
@@ -426,6 +437,7 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
     return v;
 }
 
+template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
@@ -490,7 +502,13 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     }
     __syncthreads();
 
-    const int hix = lx - 1 - (lx >> 1), hiy = ly - 1 - (ly >> 1);
+    // offsets from the root: minimum image on a periodic axis; on a walled axis
+    // plain differences (wrap_off over twice the length changes nothing), and
+    // no antipodal line to cross
+    const bool ox = GEOM && B.open_x, oy = GEOM && B.open_y;
+    const int wlx = ox ? 2 * lx : lx, wly = oy ? 2 * ly : ly;
+    const int hix = ox ? INT_MAX : lx - 1 - (lx >> 1);
+    const int hiy = oy ? INT_MAX : ly - 1 - (ly >> 1);
     const int lane = t & 63;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -504,8 +522,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         if (B.keep_maps) gmem(B.labels)[g] = inside ? prank[r] : -1;
         if (!inside) continue;
         const int prx = (int)(pxy[r] & 0xffffu), pry = (int)(pxy[r] >> 16);
-        const int dx = wrap_off(x0 + cx - prx, lx);
-        const int dy = wrap_off(y0 + y - pry, ly);
+        const int dx = wrap_off(x0 + cx - prx, wlx);
+        const int dy = wrap_off(y0 + y - pry, wly);
         // an adjacent inside site is a member; crossing the antipodal line of
         // the root makes the unwrapped coordinates jump by L - 1.  Sites on
         // that line are rare: their neighbours are read from the global map.
@@ -531,13 +549,13 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         // the first site of each horizontal run adds the whole run (one piece)
         if (cx > 0 && ((m >> (cx - 1)) & 1u)) continue;
         const int len = __builtin_ctzll(~(unsigned long long)(m >> cx));   // a full row is 32
-        const int dx_end = wrap_off(x0 + cx + len - 1 - prx, lx);
+        const int dx_end = wrap_off(x0 + cx + len - 1 - prx, wlx);
         int sxr;
         if (dx_end - dx == len - 1) {
             sxr = (dx + dx_end) * len / 2;     // no wrap inside the run
         } else {
             sxr = 0;
-            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx, lx);
+            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx, wlx);
         }
         atomicAdd(&psx[r], sxr);
         atomicAdd(&psy[r], dy * len);
@@ -560,15 +578,18 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
 
 void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     P.begin(ST_TILE_CCL, s);
-    hipLaunchKernelGGL(k_tile_ccl, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+    if (G.geom) hipLaunchKernelGGL(k_tile_ccl<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+    else hipLaunchKernelGGL(k_tile_ccl<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
-    hipLaunchKernelGGL(k_merge, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
+    if (G.geom) hipLaunchKernelGGL(k_merge<true>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
+    else hipLaunchKernelGGL(k_merge<false>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, dim3(G.bands), dim3(1024), 0, s, G.D, G);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    hipLaunchKernelGGL(k_relabel, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
+    if (G.geom) hipLaunchKernelGGL(k_relabel<true>, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
+    else hipLaunchKernelGGL(k_relabel<false>, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
     P.end(ST_RELABEL, s);
 }

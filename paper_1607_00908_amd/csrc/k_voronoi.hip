@@ -239,6 +239,9 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
 
 // Six resident blocks per CU (register budget 85): the block's gather and
 // barrier-bounded phases are latency chains that other resident blocks fill.
+// GEOM: some entry of the launch has walls or obstacles; the periodic,
+// unobstructed instance carries none of their tests.
+template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
@@ -253,7 +256,10 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int W = tw + 2, H = th + 2;
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
-    const int MX = 256 * lx, MY = 256 * ly;
+    // wrap periods (Q.8): the lattice period of a periodic axis; on a walled
+    // axis a period that no distance reaches (images are not used there)
+    const bool ox = GEOM && B.open_x, oy = GEOM && B.open_y;
+    const int MX = qperiod(lx, ox), MY = qperiod(ly, oy);
     const int OX = 256 * x0, OY = 256 * y0;   // tile origin (Q.8); coordinates below are relative
 
     // window sites of this thread: exact tile-relative Q.8 coordinates
@@ -331,7 +337,11 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     // candidate list entry for centre e: every image of the centre that is the
     // minimum image of some window point (relative offset within [-M/2, M/2]).
     // The offset rx lies in (-MX, MX) and the window is at most one lattice
-    // wide, so only the images k = -1 .. 2 can qualify.
+    // wide, so only the images k = -1 .. 2 can qualify.  On a walled axis
+    // (M = 512 L) the centre itself always qualifies and a shifted copy only
+    // for a centre on the first or last site line, seen from the tile at the
+    // other wall: that copy is farther than the centre from every point inside
+    // the domain (the only points whose colour is used), so it owns none.
     auto image_masks = [&](int rx, int ry, unsigned &mxk, unsigned &myk) {
         mxk = 0;
         myk = 0;
@@ -368,7 +378,7 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
         // (nearest centre seen) and, when they cover the radius it implies,
         // every candidate as well
         const int R0 = 3;
-        const Span sx0 = span_cells(tx, R0, B.ntx), sy0 = span_cells(ty, R0, B.nty);
+        const Span sx0 = span_cells(tx, R0, B.ntx, ox), sy0 = span_cells(ty, R0, B.nty, oy);
         {   // one thread per cell of the square walks the cell's centres
             const int n0x = sx0.hi0 - sx0.lo0 + 1, ncx = n0x + (sx0.n == 2 ? sx0.hi1 - sx0.lo1 + 1 : 0);
             const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
@@ -477,7 +487,7 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
             // every cell meeting the disc, evaluated in LDS-sized chunks
             for (int R = R0;; R *= 2) {
                 if (S.best != ~0ull) break;
-                const Span sx = span_cells(tx, 2 * R, B.ntx), sy = span_cells(ty, 2 * R, B.nty);
+                const Span sx = span_cells(tx, 2 * R, B.ntx, ox), sy = span_cells(ty, 2 * R, B.nty, oy);
                 visit_items(B, S, sx, sy, 1 << 30,
                             [&](int e) {
                                 const int2 q = ld_int2(B.cell_q, e);
@@ -489,8 +499,8 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
             const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
             const double rq2 = (256.0 * rho) * (256.0 * rho);
             const double px = tcx / 256.0, py = tcy / 256.0;
-            const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx);
-            const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), ly);
+            const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx, ox);
+            const Span sy = span_sites((int)floor(py - rho), (int)floor(py + rho), ly, oy);
             visit_items(
                 B, S, sx, sy, CAND_BATCH,
                 [&](int e) {
@@ -509,11 +519,20 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
         }
         eval_owners();
     }
+    // window sites with no colour: beyond a wall, and obstacles
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
         const int w = t + i * DV_BLOCK;
         const int wy = (w * wmagic) >> 16, wx = w - wy * W;
-        if (w < W * H) S.own[wy * 34 + wx] = bl[i];
+        if (w >= W * H) continue;
+        int ax = x0 + wx - 1, ay = y0 + wy - 1;
+        bool none = (ox && (ax < 0 || ax >= lx)) || (oy && (ay < 0 || ay >= ly));
+        if (GEOM && B.obst && !none) {
+            ax = ax < 0 ? ax + lx : (ax >= lx ? ax - lx : ax);
+            ay = ay < 0 ? ay + ly : (ay >= ly ? ay - ly : ay);
+            none = gmem(B.obst)[(size_t)ay * lx + ax] != 0;
+        }
+        S.own[wy * 34 + wx] = none ? DV_EMPTY : bl[i];
     }
     __syncthreads();
 
@@ -614,6 +633,8 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
                         m = lt ? S.sl[k] : m;
                     }
                 } else {
+                    // (on a walled axis the point is inside: its diagonal
+                    // partner has a colour)
                     int X = OX + 256 * qsx + inx(r), Y = OY + 256 * qsy + iny(r);
                     if (X < 0) X += MX;
                     if (Y < 0) Y += MY;
@@ -677,7 +698,8 @@ void launch_voronoi(const Batch &G, hipStream_t s, Prof &P) {
     hipLaunchKernelGGL(k_finalize, dim3(fgrid, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_FINALIZE, s);
     P.begin(ST_OWNER_EDGES, s);
-    hipLaunchKernelGGL(k_owner_edges, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
+    if (G.geom) hipLaunchKernelGGL(k_owner_edges<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
+    else hipLaunchKernelGGL(k_owner_edges<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
     P.end(ST_OWNER_EDGES, s);
     P.begin(ST_ROWS, s);
     hipLaunchKernelGGL(k_rows, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);

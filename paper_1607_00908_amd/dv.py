@@ -22,6 +22,9 @@ PHASE_ABOVE = 0
 PHASE_BELOW = 1
 KEEP_MAPS = 1
 CLASSIFY = 2
+OBSTACLES = 4
+OPEN_X = 8
+OPEN_Y = 16
 FLIP_BULK, FLIP_BOUNDARY = 1, 2
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = range(7)
@@ -29,7 +32,7 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 # every entry point declared in include/dv.h
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
-           "dv_get_matching", "dv_group_create", "dv_group_push", "dv_group_push_some",
+           "dv_get_matching", "dv_set_obstacles", "dv_group_create", "dv_group_push", "dv_group_push_some",
            "dv_group_destroy",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
@@ -101,6 +104,8 @@ def load(path: str = LIB_PATH):
     lib.dv_get_edges.argtypes = [vp, vp, i32, i32p]
     lib.dv_get_matching.restype = i32
     lib.dv_get_matching.argtypes = [vp, vp, i32, i32p]
+    lib.dv_set_obstacles.restype = i32
+    lib.dv_set_obstacles.argtypes = [vp, vp, i32]
     lib.dv_group_create.restype = i32
     lib.dv_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     lib.dv_group_push.restype = i32
@@ -150,19 +155,26 @@ class Detector:
     kernels start after it, so a field produced there is complete when they
     read it.  ``max_batch``: frames queued and sent to the device together
     (0: the library's default).  ``classify``: fill the flips' event flags
-    (FLIP_BULK, FLIP_BOUNDARY).
+    (FLIP_BULK, FLIP_BOUNDARY).  ``open_x`` / ``open_y``: walls across that
+    axis instead of the periodic wrap.  ``obstacles``: a [ly, lx] mask
+    (nonzero = obstacle; numpy array or device tensor) set at creation; it can
+    be replaced later with ``set_obstacles`` (the context then holds a mask
+    even when this is None, with ``with_obstacles=True``).
     """
 
     def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
                  device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0,
-                 classify: bool = False):
+                 classify: bool = False, open_x: bool = False, open_y: bool = False,
+                 obstacles=None, with_obstacles: bool = False):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
+        flags = ((KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0)
+                 | (OPEN_X if open_x else 0) | (OPEN_Y if open_y else 0)
+                 | (OBSTACLES if (with_obstacles or obstacles is not None) else 0))
         cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
                        int(connectivity), int(max_components), int(max_degree), int(device),
-                       (KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0),
-                       int(max_batch))
+                       flags, int(max_batch))
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))
@@ -177,6 +189,8 @@ class Detector:
         self.h = h
         self.cfg = cfg
         self._field_refs = []
+        if obstacles is not None:
+            self.set_obstacles(obstacles)
 
     # -- lifecycle -----------------------------------------------------------
     def close(self):
@@ -227,6 +241,27 @@ class Detector:
     def sync(self):
         self._check(self.lib.dv_sync(self.h))
         self._field_refs.clear()
+
+    def set_obstacles(self, mask) -> None:
+        """Replace the obstacle mask ([ly, lx], nonzero = obstacle; numpy array,
+        device tensor, or None to clear).  Frames pushed before keep the old one."""
+        if mask is None:
+            self._check(self.lib.dv_set_obstacles(self.h, None, 0))
+            return
+        if hasattr(mask, "is_cuda") and mask.is_cuda:
+            if tuple(mask.shape) != (self.ly, self.lx):
+                raise ValueError(f"mask must have shape ({self.ly}, {self.lx})")
+            m = (mask != 0).to(self._torch.uint8).contiguous()
+            if m.device != self.device:
+                raise ValueError(f"mask is on {m.device}, the context on {self.device}")
+            # the copy runs on the context's stream after the caller's work
+            self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
+            self._check(self.lib.dv_set_obstacles(self.h, ctypes.c_void_p(m.data_ptr()), 1))
+            return
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        if m.shape != (self.ly, self.lx):
+            raise ValueError(f"mask must have shape ({self.ly}, {self.lx})")
+        self._check(self.lib.dv_set_obstacles(self.h, _ptr(m), 0))
 
     def flips(self) -> np.ndarray:
         """Flips of the most recent frame: int32 [F, 6] = (a, b, pa, pb, kind, flags)."""

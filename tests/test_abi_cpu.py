@@ -47,7 +47,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
     dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
-    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=4),
+    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=32), dict(flags=0x80000000),
     dict(max_batch=-1), dict(max_batch=17)])
 def test_invalid_config_is_rejected_on_the_host(bad):
     lib = dv.load()
@@ -70,6 +70,7 @@ def test_null_arguments():
     lib = dv.load()
     assert lib.dv_create(None, None, None) == dv.ERR_ARG
     assert lib.dv_push_frame(None, None) == dv.ERR_ARG
+    assert lib.dv_set_obstacles(None, None, 0) == dv.ERR_ARG
     n = ctypes.c_int32(0)
     assert lib.dv_get_flips(None, None, 0, ctypes.byref(n)) == dv.ERR_ARG
     lib.dv_destroy(None)   # NULL-safe

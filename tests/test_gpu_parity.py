@@ -67,15 +67,18 @@ def check_frame(det, now, ref, lx, ly, maps=True):
 
 
 def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag="",
-                 classify=False):
+                 classify=False, open_x=False, open_y=False, obstacles=None):
     ly, lx = fields[0].shape
     if kmax is None:
         kmax = lx * ly
     det = dv.Detector(lx, ly, thr, phase, conn, max_components=kmax, max_degree=max_degree,
-                      keep_maps=maps, classify=classify)
-    seq = oracle.Sequence(thr, phase, conn, NTHREADS, classify_events=classify)
+                      keep_maps=maps, classify=classify, open_x=open_x, open_y=open_y,
+                      obstacles=obstacles)
+    seq = oracle.Sequence(thr, phase, conn, NTHREADS, classify_events=classify,
+                          obstacles=obstacles, open_x=open_x, open_y=open_y)
     for i, f in enumerate(fields):
-        say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase}")
+        say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase} open={int(open_x)}{int(open_y)}"
+            f" obstacles={obstacles is not None}")
         det.push(torch.from_numpy(np.ascontiguousarray(f)).to("cuda"))
         now, ref = seq.push(f)
         check_frame(det, now, ref, lx, ly, maps)
@@ -516,3 +519,157 @@ def test_serving_results_equal_alone_and_in_the_mix():
             assert (K, E, F) == (info.n_components, info.n_edges, info.n_flips), (i, k)
             assert np.array_equal(got, fl), (i, k)
         det.close()
+
+
+# ------------------------------------------------------------ walls and obstacles
+@pytest.mark.parametrize("seed", range(24))
+def test_walls_and_obstacles_fuzz_small_lattices(seed):
+    rng = np.random.default_rng(7000 + seed)
+    lx, ly = int(rng.integers(3, 90)), int(rng.integers(3, 90))
+    conn = int(rng.choice([4, 8]))
+    phase = int(rng.integers(0, 2))
+    ox, oy = [(True, False), (False, True), (True, True), (False, False)][seed % 4]
+    obst = rng.random((ly, lx)) < rng.uniform(0.0, 0.2) if seed % 3 else None
+    p = float(rng.uniform(0.15, 0.6))
+    thr = p if phase == 1 else 1.0 - p
+    fields = [synth.tiny_random_field(lx, ly, 8000 + 7 * seed + k) for k in range(3)]
+    run_sequence(fields, thr, phase, conn, tag=f"walls{seed}", open_x=ox, open_y=oy,
+                 obstacles=obst)
+
+
+@pytest.mark.parametrize("lx,ly", [(3, 3), (3, 17), (64, 3), (32, 32), (33, 31), (65, 97), (31, 200)])
+def test_walled_shapes_and_ragged_tiles(lx, ly):
+    fields = [synth.tiny_random_field(lx, ly, 31 * lx + ly + k) for k in range(3)]
+    for ox, oy in ((True, False), (False, True), (True, True)):
+        run_sequence(fields, 0.4, 1, 8, tag=f"wshape{lx}x{ly}", open_x=ox, open_y=oy)
+
+
+def test_walls_empty_full_and_edge_components():
+    """Components touching the walls, one covering everything, none; the same
+    fields on the torus join across the seams instead."""
+    lx, ly = 70, 45
+    edge = np.zeros((ly, lx), np.float32)
+    edge[10:20, 0:4] = 1.0
+    edge[12:18, lx - 3:lx] = 1.0
+    edge[0:3, 30:40] = 1.0
+    edge[ly - 2:ly, 33:37] = 1.0
+    full = np.ones((ly, lx), np.float32)
+    empty = np.zeros((ly, lx), np.float32)
+    for ox, oy in ((True, False), (False, True), (True, True)):
+        run_sequence([edge, full, empty, edge], 0.5, tag="walls-edge", open_x=ox, open_y=oy)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_channel_with_posts_small(seed):
+    """The paper's channel in small: walls across x, posts on the left wall,
+    drifting droplets; event flags on."""
+    sim = synth.ChannelSim(192, 256, 60, 7.0, 9.0, 24, 32, 64, 1.5, 0.4, seed=60 + seed)
+    run_sequence(list(sim.frames(5)), 0.5, kmax=256, tag=f"channel{seed}", classify=True,
+                 open_x=True, obstacles=sim.obstacles())
+
+
+def test_channel2048_batched_burst():
+    """Full-size channel frames (2048 x 1024, 2000 droplets, posts) pushed back
+    to back in batches of 16; the first two and the last comparisons against
+    the oracle."""
+    sim, spec = synth.workload("channel2048")
+    obst = sim.obstacles()
+    frames = list(sim.frames(18))
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    det = dv.Detector(2048, 1024, spec["threshold"], spec["phase"], 8, max_components=8192,
+                      open_x=True, obstacles=obst, classify=True)
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS, classify_events=True,
+                          obstacles=obst, open_x=True)
+    for k in range(2):
+        say(f"  [channel2048] frame {k}")
+        det.push(dev[k])
+        now, ref = seq.push(frames[k])
+        check_frame(det, now, ref, 2048, 1024)
+    for k in range(2, len(frames)):
+        det.push(dev[k])
+    say("  [channel2048] burst done")
+    seq.push(frames[-2])
+    now, ref = seq.push(frames[-1])
+    check_frame(det, now, ref, 2048, 1024)
+    assert det.info().frame == len(frames)
+    det.close()
+
+
+def test_obstacle_mask_replaced_between_pushes():
+    """Frames queued before set_obstacles keep the old mask, later ones the
+    new one (also when the mask comes from device memory)."""
+    lx, ly = 96, 80
+    sim = synth.DiskSim(lx, ly, 20, 4.0, 7.0, 0.6, 2e-3, seed=91)
+    fr = list(sim.frames(6))
+    rng = np.random.default_rng(3)
+    m1 = rng.random((ly, lx)) < 0.05
+    m2 = np.zeros((ly, lx), bool)
+    m2[30:50, 10:70] = True
+    masks = [m1, m1, m2, m2, None, None]
+    det = dv.Detector(lx, ly, 0.5, max_components=512, with_obstacles=True, max_batch=4)
+    det.set_obstacles(m1)
+    det.push(torch.from_numpy(fr[0]).cuda())
+    det.push(torch.from_numpy(fr[1]).cuda())
+    det.set_obstacles(torch.from_numpy(m2.astype(np.uint8)).cuda())
+    det.push(torch.from_numpy(fr[2]).cuda())
+    det.push(torch.from_numpy(fr[3]).cuda())
+    det.set_obstacles(None)
+    det.push(torch.from_numpy(fr[4]).cuda())
+    det.push(torch.from_numpy(fr[5]).cuda())
+    past = oracle.frame(fr[4], 0.5, obstacles=masks[4])
+    now = oracle.frame(fr[5], 0.5, obstacles=masks[5])
+    check_frame(det, now, oracle.compare(past, now), lx, ly)
+    assert det.info().frame == 6
+    # the same frames with a mask per frame, compared one at a time
+    det2 = dv.Detector(lx, ly, 0.5, max_components=512, with_obstacles=True, max_batch=1)
+    past = None
+    for k in range(6):
+        det2.set_obstacles(masks[k])
+        det2.push(torch.from_numpy(fr[k]).cuda())
+        now = oracle.frame(fr[k], 0.5, obstacles=masks[k])
+        check_frame(det2, now, oracle.compare(past, now), lx, ly)
+        past = now
+    det.close()
+    det2.close()
+
+
+def test_group_of_mixed_geometries():
+    """Periodic, walled and obstructed members in one launch per stage."""
+    stream = torch.cuda.Stream()
+    specs = [(96, 64, False, False, False), (80, 120, True, False, True),
+             (128, 96, False, True, False), (70, 70, True, True, True)]
+    sims, dets, seqs = [], [], []
+    for i, (lx, ly, ox, oy, ob) in enumerate(specs):
+        sim = synth.DiskSim(lx, ly, max(4, lx * ly // 400), 3.0, 6.0, 0.6, 3e-3, seed=820 + i)
+        mask = (np.random.default_rng(i).random((ly, lx)) < 0.04) if ob else None
+        sims.append(list(sim.frames(4)))
+        dets.append(dv.Detector(lx, ly, 0.5, max_components=512, max_batch=2, stream=stream,
+                                open_x=ox, open_y=oy, obstacles=mask, classify=True))
+        seqs.append(oracle.Sequence(0.5, 0, 8, NTHREADS, classify_events=True, obstacles=mask,
+                                    open_x=ox, open_y=oy))
+    grp = dv.Group(dets)
+    for k in range(4):
+        say(f"  [group-geometry] frame {k}")
+        grp.push([torch.from_numpy(sims[i][k]).cuda() for i in range(len(specs))])
+        for i, (lx, ly, _, _, _) in enumerate(specs):
+            now, ref = seqs[i].push(sims[i][k])
+            check_frame(dets[i], now, ref, lx, ly)
+    grp.close()
+    for d in dets:
+        d.close()
+
+
+def test_walled_sparse_cluster_exercises_candidate_overflow():
+    """The grid search behind a candidate-list overflow, with walls and an
+    obstacle band between the cluster and the far tiles."""
+    L = 384
+    f = np.zeros((L, L), np.float32)
+    f[10:90:2, 20:100:2] = 1.0
+    g = f.copy()
+    g[10:90:2, 20:100:2] = 0.0
+    g[11:91:2, 21:101:2] = 1.0
+    obst = np.zeros((L, L), bool)
+    obst[150:160, :300] = True
+    for ox, oy in ((True, True), (True, False)):
+        run_sequence([f, g], 0.5, kmax=2048, tag="wcluster", open_x=ox, open_y=oy,
+                     obstacles=obst)
