@@ -153,6 +153,8 @@ struct OwnerLds {
     // the same, ordered by label for evaluation: x, y, |c|^2 as doubles
     double sx[DV_CAND_CAP], sy[DV_CAND_CAP], sk[DV_CAND_CAP];
     int sl[DV_CAND_CAP];
+    uint8_t keep[DV_CAND_CAP];   // the candidate is not beaten everywhere in the window
+    int nkeep;                   // candidates kept (the ordered list's length)
     int ncand;
     int nchunks;   // times the list was evaluated and emptied before the end
     // item ranges of the cell rectangle being visited
@@ -274,33 +276,68 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
         be[i] = 1.0e300;
         bl[i] = DV_EMPTY;
     }
-    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; }
+    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; S.nkeep = 0; }
     __syncthreads();
 
     // tile centre (absolute Q.8) and the window's relative x / y extent
     const int tcx = OX + 128 * (tw - 1), tcy = OY + 128 * (th - 1);
     const int wxlo = -256, wxhi = 256 * tw, wylo = -256, wyhi = 256 * th;
 
-    // Nearest candidate of every window site.  The chunk is first ordered by
-    // label, so that within it a strict comparison already sends ties to the
-    // lowest label; a later chunk (after an overflow) also compares labels.
+    // Nearest candidate of every window site.  Candidates that another
+    // candidate beats everywhere in the window are dropped first: the
+    // difference of the squared distances to two centres is affine in the
+    // point, so when its minimum over the window rectangle (at the corner its
+    // gradient picks) is positive, the other centre is strictly nearer at
+    // every window site and inner-frame point, and the dropped one owns none
+    // of them.  Some candidate always stays (strict domination has a minimal
+    // element), and so does the owner of every point.  The test is exact in
+    // float64: coordinates stay below 2^26 in magnitude (Q.8, images
+    // included), so every square and sum is an integer below 2^53, and where
+    // rounding could occur the value is far from zero.  The kept candidates
+    // are ordered by label, so that a strict comparison already sends ties to
+    // the lowest label; a later chunk (after an overflow) also compares
+    // labels.
     auto eval_owners = [&]() {
-        double m2x[WSITES], m2y[WSITES];
-#pragma unroll
-        for (int i = 0; i < WSITES; ++i) {
-            const int w = t + i * DV_BLOCK;
-            const int wy = (w * wmagic) >> 16, wx = w - wy * W;
-            m2x[i] = -512.0 * (wx - 1);
-            m2y[i] = -512.0 * (wy - 1);
-        }
+        if (t == 0) S.nkeep = 0;
         __syncthreads();
         const int nc = min(S.ncand, DV_CAND_CAP);
+        {   // 16 lanes per candidate i, lane j of the group takes the rivals j, j + 16, ...
+            const int gi = t >> 4, gj = t & 15;
+#pragma unroll 1
+            for (int i0 = 0; i0 < nc; i0 += DV_BLOCK / 16) {
+                const int i = i0 + gi;
+                bool beaten = false;
+                if (i < nc) {
+                    const double cx = (double)S.cx[i], cy = (double)S.cy[i];
+                    const double cc = fma(cx, cx, cy * cy);
+#pragma unroll 1
+                    for (int j = gj; j < nc && !beaten; j += 16) {
+                        if (j == i) continue;
+                        const double jx = (double)S.cx[j], jy = (double)S.cy[j];
+                        // |w - c|^2 - |w - j|^2 = 2 w.(j - c) + |c|^2 - |j|^2
+                        const double ax = 2.0 * (jx - cx), ay = 2.0 * (jy - cy);
+                        const double f = fma(ax, ax >= 0.0 ? (double)wxlo : (double)wxhi,
+                                             fma(ay, ay >= 0.0 ? (double)wylo : (double)wyhi,
+                                                 cc - fma(jx, jx, jy * jy)));
+                        beaten = f > 0.0;
+                    }
+                }
+                const unsigned long long b = __ballot(beaten);
+                const unsigned grp = (unsigned)(b >> (t & 48)) & 0xffffu;
+                if (gj == 0 && i < nc) {
+                    S.keep[i] = grp ? 0 : 1;
+                    if (!grp) atomicAdd(&S.nkeep, 1);
+                }
+            }
+        }
+        __syncthreads();
         for (int c = t; c < nc; c += DV_BLOCK) {
+            if (!S.keep[c]) continue;
             const int lab = S.lab[c];
             int r = 0;
             for (int j = 0; j < nc; ++j) {
                 const int l2 = S.lab[j];
-                r += (l2 < lab || (l2 == lab && j < c)) ? 1 : 0;
+                r += (S.keep[j] && (l2 < lab || (l2 == lab && j < c))) ? 1 : 0;
             }
             const double x = (double)S.cx[c], y = (double)S.cy[c];
             S.sx[r] = x;
@@ -309,8 +346,17 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
             S.sl[r] = lab;
         }
         __syncthreads();
+        const int nk = S.nkeep;
+        double m2x[WSITES], m2y[WSITES];
+#pragma unroll
+        for (int i = 0; i < WSITES; ++i) {
+            const int w = t + i * DV_BLOCK;
+            const int wy = (w * wmagic) >> 16, wx = w - wy * W;
+            m2x[i] = -512.0 * (wx - 1);
+            m2y[i] = -512.0 * (wy - 1);
+        }
         if (S.nchunks == 0) {
-            for (int c = 0; c < nc; ++c) {
+            for (int c = 0; c < nk; ++c) {
                 const double cx = S.sx[c], cy = S.sy[c], kk = S.sk[c];
                 const int lab = S.sl[c];
 #pragma unroll
@@ -322,7 +368,7 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
                 }
             }
         } else {
-            for (int c = 0; c < nc; ++c) {
+            for (int c = 0; c < nk; ++c) {
                 const double cx = S.sx[c], cy = S.sy[c], kk = S.sk[c];
                 const int lab = S.sl[c];
 #pragma unroll
@@ -541,7 +587,7 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     // against the candidate list (or, after a candidate-list overflow, by the
     // exact grid search).
     const bool in_lds = S.nchunks == 0;
-    const int ncl = S.ncand;
+    const int ncl = S.nkeep;   // the ordered list of the single chunk
     auto emit = [&](int a, int b) {
         const int slot = atomicAdd(&S.npair, 1);
         if (slot < PAIR_CAP) {
@@ -651,13 +697,24 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     __syncthreads();
     // --- distinct couples of the tile go to its list (k_rows fills the rows);
     // beyond the list's capacity they go into the rows directly
+    // (a group of GL lanes per couple looks for an earlier copy; one wave holds
+    // whole groups, and a ballot ORs the group's answers)
     const int np = min(S.npair, PAIR_CAP);
-    for (int i = t; i < np; i += DV_BLOCK) {
-        const unsigned long long key = S.pair[i];
-        bool first = true;
-        for (int j = 0; j < i; ++j)
-            if (S.pair[j] == key) { first = false; break; }
-        if (!first) continue;
+    int GL = 64;
+    while (GL > 1 && np * GL > DV_BLOCK) GL >>= 1;
+    const int sub = t & (GL - 1);
+    const unsigned long long gmask = (GL == 64 ? ~0ull : ((1ull << GL) - 1ull)) << ((t & 63) & ~(GL - 1));
+    for (int i0 = 0; i0 < np; i0 += DV_BLOCK / GL) {
+        const int i = i0 + t / GL;
+        unsigned long long key = 0;
+        bool dup = false;
+        if (i < np) {
+            key = S.pair[i];
+            for (int j = sub; j < i; j += GL)
+                if (S.pair[j] == key) { dup = true; break; }
+        }
+        const bool first = i < np && !(__ballot(dup) & gmask);
+        if (!first || sub != 0) continue;
         const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
         const int slot = atomicAdd(&S.nout, 1);
         if (slot < DV_TILE_PAIRS) {
