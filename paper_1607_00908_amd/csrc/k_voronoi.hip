@@ -617,20 +617,22 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
         int f[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) f[k] = g[i + 1 + fry(k)][1 + frx(k)];
+        // (without walls and obstacles no frame point is MAXLINK once the site
+        // has a colour: there is a centre, so every point has one)
         int gaps = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int a = f[k], b = f[(k + 1) & 7];
-            gaps += (a != b && a != DV_EMPTY && b != DV_EMPTY) ? 1 : 0;
+            gaps += (a != b && (!GEOM || (a != DV_EMPTY && b != DV_EMPTY))) ? 1 : 0;
         }
         if (gaps < 3) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int tg = f[2 * r];
             const int pa = f[(2 * r + 2) & 7], pb = f[(2 * r + 7) & 7];
-            if (tg != DV_EMPTY && pa != pb && tg != ckk) emit(min(ckk, tg), max(ckk, tg));
+            if ((!GEOM || tg != DV_EMPTY) && pa != pb && tg != ckk) emit(min(ckk, tg), max(ckk, tg));
             const int dg = f[2 * r + 1];
-            if (dg != DV_EMPTY && dg != ckk && pa != pb && pa != tg) pend |= 1u << (4 * i + r);
+            if ((!GEOM || dg != DV_EMPTY) && dg != ckk && pa != pb && pa != tg) pend |= 1u << (4 * i + r);
         }
     }
     // inner-frame queries: numbered by a block scan of the per-thread counts,
