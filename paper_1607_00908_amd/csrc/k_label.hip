@@ -127,11 +127,8 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 // or -1 when s is outside or beyond the lattice.  rowm: LDS [32] row masks.
 //
 // Runs of a row are connected by construction (each site points to its run's
-// first site).  Runs of consecutive rows are united once per touching pair:
-// a site unites its run with the run above that starts to be adjacent at its
-// responsibility column -- column x + 1 for every site, and additionally
-// columns a - 1 and a for the first site a of a run (8-connectivity), or
-// column x for every site (4-connectivity).
+// first site).  Runs of consecutive rows are united once per touching pair,
+// by one lane per row.
 template <bool GEOM>
 __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int tw, int th, int *L,
                          uint32_t *rowm) {
@@ -158,30 +155,36 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
         L[y * 32 + cx] = in ? y * 32 + run_start(m, cx) : -1;
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
-        if (y == 0 || L[s] < 0) continue;
+    // Unions of each run [a, b] with the runs of the row above that touch
+    // it: columns a - 1 .. b + 1 (8-connectivity) or a .. b (4): the run
+    // holding the lowest touching site of the row above, and every other
+    // run of that row starting inside the span.  Lane y of the first wave
+    // takes row y.
+    if (t < 32 && t >= 1 && t < th) {
+        const int y = t;
         const uint32_t m = rowm[y], up = rowm[y - 1];
-        if (up == 0u) continue;
-        const int a = run_start(m, cx);
-        const int me = y * 32 + a;
-        if (B.conn == 8) {
-            const int lo = a > 0 ? a - 1 : 0;
-            // candidate columns above: x + 1, plus a - 1 and a at the run start
-            int cand[3] = {cx + 1, -1, -1};
-            if (cx == a) { cand[1] = a - 1; cand[2] = a; }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int u = cand[k];
-                if (u < lo || u > 31 || !((up >> u) & 1u)) continue;
-                if (u > lo && ((up >> (u - 1)) & 1u)) continue;   // not the first of its run
-                lunite(L, me, (y - 1) * 32 + run_start(up, u));
-            }
-        } else {
-            const int u = cx;
-            if ((up >> u) & 1u) {
-                if (u == a || !((up >> (u - 1)) & 1u)) lunite(L, me, (y - 1) * 32 + run_start(up, u));
+        if (m && up) {
+            const uint32_t st_up = up & ~(up << 1);
+            uint32_t starts = m & ~(m << 1);
+            while (starts) {
+                const int a = __ffs(starts) - 1;
+                starts &= starts - 1;
+                const uint32_t rest = ~(m >> a);            // bit k clear: a + k inside
+                const int b = rest ? a + __ffs(rest) - 2 : 31;
+                const int lo = (B.conn == 8 && a > 0) ? a - 1 : a;
+                const int hi = (B.conn == 8 && b < 31) ? b + 1 : b;
+                const uint32_t span = (hi == 31 ? 0xffffffffu : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
+                const uint32_t hit = up & span;
+                if (!hit) continue;
+                const int me = y * 32 + a;
+                const int p0 = __ffs(hit) - 1;
+                lunite(L, me, (y - 1) * 32 + run_start(up, p0));
+                uint32_t more = st_up & hit & ~(1u << p0);
+                while (more) {
+                    const int q = __ffs(more) - 1;
+                    more &= more - 1;
+                    lunite(L, me, (y - 1) * 32 + q);
+                }
             }
         }
     }
