@@ -451,6 +451,9 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     __shared__ uint32_t pxy[DV_TILE_SITES];
     __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
     __shared__ int wsum[16];
+    __shared__ uint32_t rowm[DV_TILE];
+    __shared__ uint16_t runs[DV_TILE_SITES / 2];   // (row << 5) | first column of each run
+    __shared__ int nruns;
     extern __shared__ int boff[];   // [nty] roots in the bands before each band
     FrameState *fs = B.fs;
     const int tile = blockIdx.x - G.tbase[e];
@@ -513,56 +516,85 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     const int hix = ox ? INT_MAX : lx - 1 - (lx >> 1);
     const int hiy = oy ? INT_MAX : ly - 1 - (ly >> 1);
     const int lane = t & 63;
+    // label map and row masks
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
         const int r = L[s];
         const bool inside = r >= 0;
         const unsigned long long bal = __ballot(inside);
-        const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
-        if (cx >= tw || y >= th) continue;
-        const size_t g = (size_t)(y0 + y) * lx + x0 + cx;
-        if (B.keep_maps) gmem(B.labels)[g] = inside ? prank[r] : -1;
-        if (!inside) continue;
+        if (cx == 0) rowm[y] = (uint32_t)(lane < 32 ? bal : (bal >> 32));
+        if (B.keep_maps && cx < tw && y < th)
+            gmem(B.labels)[(size_t)(y0 + y) * lx + x0 + cx] = inside ? prank[r] : -1;
+    }
+    __syncthreads();
+    // list of the horizontal runs: lane y of the first wave writes those of row y
+    if (t < 64) {
+        const uint32_t m = t < 32 ? rowm[t] : 0u;
+        uint32_t st = m & ~(m << 1);
+        const int c = __popc(st);
+        int x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(x, o, 64);
+            if (lane >= o) x += v;
+        }
+        for (int k = x - c; st; ++k) {
+            runs[k] = (uint16_t)((t << 5) | (__ffs(st) - 1));
+            st &= st - 1;
+        }
+        if (t == 63) nruns = x;
+    }
+    __syncthreads();
+    // one thread per run: its closed-form sums go to its piece; a run that
+    // meets the root's antipodal line checks its sites (an adjacent inside
+    // site is a member; crossing the line makes the unwrapped coordinates
+    // jump by L - 1; such sites are rare, their neighbours are read from the
+    // global map)
+    const int nr = nruns;
+    for (int k = t; k < nr; k += DV_BLOCK) {
+        const int y = runs[k] >> 5, a = runs[k] & 31;
+        const int r = L[y * 32 + a];
+        const uint32_t m = rowm[y];
+        const int len = __builtin_ctzll(~(unsigned long long)(m >> a));   // a full row is 32
         const int prx = (int)(pxy[r] & 0xffffu), pry = (int)(pxy[r] >> 16);
-        const int dx = wrap_off(x0 + cx - prx, wlx);
+        const int dx = wrap_off(x0 + a - prx, wlx);
         const int dy = wrap_off(y0 + y - pry, wly);
-        // an adjacent inside site is a member; crossing the antipodal line of
-        // the root makes the unwrapped coordinates jump by L - 1.  Sites on
-        // that line are rare: their neighbours are read from the global map.
-        bool amb = false;
-        if (dx == hix || dy == hiy) {
-            const int gx = x0 + cx, gy = y0 + y;
-            const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
+        const int dx_end = wrap_off(x0 + a + len - 1 - prx, wlx);
+        const bool straight = dx_end - dx == len - 1;
+        int sxr;
+        if (straight) {
+            sxr = (dx + dx_end) * len / 2;
+        } else {
+            sxr = 0;
+            for (int j = 0; j < len; ++j) sxr += wrap_off(x0 + a + j - prx, wlx);
+        }
+        atomicAdd(&psx[r], sxr);
+        atomicAdd(&psy[r], dy * len);
+        atomicAdd(&pn[r], len);
+        if (dy == hiy || !straight || (dx <= hix && hix <= dx_end)) {
+            bool amb = false;
+            const int gy = y0 + y;
             const int yp = gy + 1 == ly ? 0 : gy + 1, ym = gy == 0 ? ly - 1 : gy - 1;
             auto inside_at = [&](int xx, int yy) {
                 const size_t tl = (size_t)(yy >> 5) * B.ntx + (xx >> 5);
                 return gmem(B.lab16)[tl * DV_TILE_SITES + (yy & 31) * 32 + (xx & 31)] != 0xffff;
             };
-            if (dx == hix) {
-                amb = inside_at(xp, gy);
-                if (B.conn == 8) amb = amb || inside_at(xp, ym) || inside_at(xp, yp);
+            for (int j = 0; j < len; ++j) {
+                const int gx = x0 + a + j;
+                const int dxj = wrap_off(gx - prx, wlx);
+                if (dxj != hix && dy != hiy) continue;
+                const int xp = gx + 1 == lx ? 0 : gx + 1, xm = gx == 0 ? lx - 1 : gx - 1;
+                if (dxj == hix) {
+                    amb = amb || inside_at(xp, gy);
+                    if (B.conn == 8) amb = amb || inside_at(xp, ym) || inside_at(xp, yp);
+                }
+                if (dy == hiy) {
+                    amb = amb || inside_at(gx, yp);
+                    if (B.conn == 8) amb = amb || inside_at(xm, yp) || inside_at(xp, yp);
+                }
             }
-            if (dy == hiy) {
-                amb = amb || inside_at(gx, yp);
-                if (B.conn == 8) amb = amb || inside_at(xm, yp) || inside_at(xp, yp);
-            }
+            if (amb && prank[r] < B.kmax) atomicOr(&B.acc_amb[prank[r]], 1);
         }
-        if (amb && prank[r] < B.kmax) atomicOr(&B.acc_amb[prank[r]], 1);
-        // the first site of each horizontal run adds the whole run (one piece)
-        if (cx > 0 && ((m >> (cx - 1)) & 1u)) continue;
-        const int len = __builtin_ctzll(~(unsigned long long)(m >> cx));   // a full row is 32
-        const int dx_end = wrap_off(x0 + cx + len - 1 - prx, wlx);
-        int sxr;
-        if (dx_end - dx == len - 1) {
-            sxr = (dx + dx_end) * len / 2;     // no wrap inside the run
-        } else {
-            sxr = 0;
-            for (int k = 0; k < len; ++k) sxr += wrap_off(x0 + cx + k - prx, wlx);
-        }
-        atomicAdd(&psx[r], sxr);
-        atomicAdd(&psy[r], dy * len);
-        atomicAdd(&pn[r], len);
     }
     __syncthreads();
 #pragma unroll
