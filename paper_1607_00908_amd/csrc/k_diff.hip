@@ -262,6 +262,21 @@ __device__ __forceinline__ int event_flags(const Bufs &B, int a, int b, int kind
     return f;
 }
 
+// n 8-byte words from src to dst (distinct buffers), four loads in flight
+__device__ __forceinline__ void copy_words(const int2 *__restrict__ src, int2 *__restrict__ dst, int n) {
+    const auto s = gmem(reinterpret_cast<const unsigned long long *>(src));
+    const auto d = gmem(reinterpret_cast<unsigned long long *>(dst));
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        const unsigned long long a0 = s[j], a1 = s[j + 1], a2 = s[j + 2], a3 = s[j + 3];
+        d[j] = a0;
+        d[j + 1] = a1;
+        d[j + 2] = a2;
+        d[j + 3] = a3;
+    }
+    for (; j < n; ++j) d[j] = s[j];
+}
+
 __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int wsum[16];
     __shared__ int s_last;
@@ -294,9 +309,10 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
             if (cb == 0 && ca == 0) continue;
             const int *stg = B.stage + (size_t)n * (2 * D) * 6;
             int *fb = B.flips + (size_t)6 * B.ob[n];
-            for (int j = 0; j < 6 * cb; ++j) fb[j] = stg[j];
             int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
-            for (int j = 0; j < 6 * ca; ++j) fa[j] = stg[6 * D + j];
+            // records are 24 bytes: copied as 8-byte words, loads issued together
+            copy_words(reinterpret_cast<const int2 *>(stg), reinterpret_cast<int2 *>(fb), 3 * cb);
+            copy_words(reinterpret_cast<const int2 *>(stg + 6 * D), reinterpret_cast<int2 *>(fa), 3 * ca);
             if (B.classify) {
                 for (int j = 0; j < cb; ++j) fb[6 * j + 5] = event_flags(B, fb[6 * j], fb[6 * j + 1], -1);
                 for (int j = 0; j < ca; ++j) fa[6 * j + 5] = event_flags(B, fa[6 * j], fa[6 * j + 1], 1);
