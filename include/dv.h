@@ -105,8 +105,8 @@ typedef struct {
     int32_t device;          /* HIP device ordinal                                 */
     uint32_t flags;          /* DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES |
                                 DV_OPEN_X | DV_OPEN_Y                              */
-    int32_t max_batch;       /* frames sent to the device together, 1 .. 16; 0
-                                selects 16.  Each holds its own per-site buffers. */
+    int32_t max_batch;       /* frames sent to the device together, 1 .. 64; 0
+                                selects 32.  Each holds its own per-site buffers. */
 } dv_config;
 
 /* One edge flip (Sec. 3.2.4).  a < b are now labels; pa, pb the past labels

@@ -145,7 +145,7 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y))
         return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
-        return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 16]");
+        return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 64]");
     return DV_OK;
 }
 

@@ -159,29 +159,33 @@ __device__ int point_nearest(const Bufs &B, int X, int Y) {
     return bl;
 }
 
-// Lexicographic (distance, label) minimum across the 64 lanes of a wave.
-__device__ __forceinline__ void wave_min_dl(long long &d, int &lab) {
-    for (int o = 32; o > 0; o >>= 1) {
+// Lexicographic (distance, label) minimum across a group of GL lanes (an
+// aligned part of a wave).
+template <int GL>
+__device__ __forceinline__ void group_min_dl(long long &d, int &lab) {
+    for (int o = GL / 2; o > 0; o >>= 1) {
         const long long d2 = __shfl_xor(d, o, 64);
         const int l2 = __shfl_xor(lab, o, 64);
         if (d2 < d || (d2 == d && l2 < lab)) { d = d2; lab = l2; }
     }
 }
 
-// Same search as point_nearest with the 64 lanes of a wave sharing the cells:
-// lane j takes the (row, column range) pairs j, j + 64, ...  Every lane of the
-// wave must call it with the same point; every lane gets the answer.
-__device__ int wave_nearest(const Bufs &B, int X, int Y) {
+// Same search as point_nearest with a group of GL lanes (an aligned part of
+// a wave) sharing the cells: lane j of the group takes the (row, column
+// range) pairs j, j + GL, ...  Every lane of the group must call it with the
+// same point; every lane of the group gets the answer.
+template <int GL>
+__device__ int group_nearest(const Bufs &B, int X, int Y) {
     const int MX = qperiod(B.lx, B.open_x), MY = qperiod(B.ly, B.open_y);
     const int cx = X >> 13, cy = Y >> 13;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & (GL - 1);
     const auto cs = gmem(B.cell_start);
     long long bd = LLONG_MAX;
     int dummy = 0;
     for (int R = 1;; R *= 2) {
         const Span sx = span_cells(cx, R, B.ntx, B.open_x), sy = span_cells(cy, R, B.nty, B.open_y);
         const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
-        for (int j = lane; j < nrows * sx.n; j += 64) {
+        for (int j = lane; j < nrows * sx.n; j += GL) {
             const int ri = j / sx.n, c = j % sx.n;
             const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
             const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
@@ -191,7 +195,7 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
                 if (d < bd) bd = d;
             }
         }
-        wave_min_dl(bd, dummy);
+        group_min_dl<GL>(bd, dummy);
         if (bd != LLONG_MAX || (span_full(sx, B.ntx) && span_full(sy, B.nty))) break;
     }
     const double rho = sqrt((double)bd) / 256.0 + 1.0;
@@ -201,7 +205,7 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
     const int n0 = sy.hi0 - sy.lo0 + 1, nrows = n0 + (sy.n == 2 ? sy.hi1 - sy.lo1 + 1 : 0);
     long long best = LLONG_MAX;
     int bl = DV_EMPTY;
-    for (int j = lane; j < nrows * sx.n; j += 64) {
+    for (int j = lane; j < nrows * sx.n; j += GL) {
         const int ri = j / sx.n, c = j % sx.n;
         const int row = ri < n0 ? sy.lo0 + ri : sy.lo1 + (ri - n0);
         const int e0 = cs[row * B.ntx + sx.lo(c)], e1 = cs[row * B.ntx + sx.hi(c) + 1];
@@ -212,7 +216,7 @@ __device__ int wave_nearest(const Bufs &B, int X, int Y) {
             if (d < best || (d == best && lab < bl)) { best = d; bl = lab; }
         }
     }
-    wave_min_dl(best, bl);
+    group_min_dl<GL>(best, bl);
     return bl;
 }
 

@@ -16,9 +16,9 @@
 #define DV_E_KMAX 1u               // more components than K_max
 #define DV_E_DEGREE 2u             // a Delaunay row overflowed max_degree
 
-#define DV_MAX_BATCH 16            // frames of one sequence processed by one launch
+#define DV_MAX_BATCH 64            // frames of one sequence processed by one launch
 #define DV_MAX_ENTRIES 64          // frames (of one or several sequences) in one launch
-#define DV_DEFAULT_BATCH 16        // what max_batch = 0 selects
+#define DV_DEFAULT_BATCH 32        // what max_batch = 0 selects
 
 // Per-frame header, one per batch slot (device memory).
 struct FrameState {

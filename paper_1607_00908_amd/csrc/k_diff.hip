@@ -4,9 +4,9 @@
 // (known on the device from the frame headers), else the shared past buffer,
 // so the comparisons of a batch are independent of each other.
 //
-//   k_match   Phi(p) = nearest now centre of every past centre p, one wave
-//             per point through the frame's bucket grid, exact, ties to the
-//             lowest label; preimage counts of the now points.
+//   k_match   Phi(p) = nearest now centre of every past centre p, a group
+//             of 16 lanes per point through the frame's bucket grid, exact,
+//             ties to the lowest label; preimage counts of the now points.
 //   k_diff    one wave per now label n.  The batch's last accepted frame
 //             copies its components and rows into the spare past buffer (the
 //             past of the next batch).  When n has exactly one preimage p,
@@ -53,17 +53,20 @@ __device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) 
     return r;
 }
 
+#define MATCH_LANES 16
 __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch G) {
     const Bufs &B = D[G.idx[blockIdx.z]];
     if (B.fs->err) return;
     const PastOf P = past_of(D, G, blockIdx.z);
     if (!P.valid) return;
     const int KP = P.K, KN = B.fs->K_now;
-    const int lane = threadIdx.x & 63;
-    const int nw = blockDim.x >> 6;
-    for (int p = blockIdx.x * nw + (threadIdx.x >> 6); p < KP; p += gridDim.x * nw) {
+    // a group of MATCH_LANES lanes per past centre (the search of one point
+    // rarely visits more cells than that)
+    const int lane = threadIdx.x & (MATCH_LANES - 1);
+    const int ng = blockDim.x / MATCH_LANES;
+    for (int p = blockIdx.x * ng + (threadIdx.x / MATCH_LANES); p < KP; p += gridDim.x * ng) {
         int n = -1;
-        if (KN > 0) n = wave_nearest(B, gmem(P.C.qx)[p], gmem(P.C.qy)[p]);
+        if (KN > 0) n = group_nearest<MATCH_LANES>(B, gmem(P.C.qx)[p], gmem(P.C.qy)[p]);
         if (lane == 0) {
             gmem(B.phi)[p] = n;
             if (n >= 0) {
@@ -431,7 +434,9 @@ void launch_compare(const Batch &G, hipStream_t s, Prof &P) {
     // (K is usually well below K_max)
     const int grid = (int)std::max<long long>(1, std::min<long long>((G.kmax + 15) / 16, 512));
     P.begin(ST_MATCH, s);
-    hipLaunchKernelGGL(k_match, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);
+    // (k_match: MATCH_LANES lanes per point, so a quarter of the blocks)
+    const int mgrid = (int)std::max<long long>(1, std::min<long long>((G.kmax + 63) / 64, 512));
+    hipLaunchKernelGGL(k_match, dim3(mgrid, 1, G.n), dim3(256), 0, s, G.D, G);
     P.end(ST_MATCH, s);
     P.begin(ST_DIFF, s);
     hipLaunchKernelGGL(k_diff, dim3(grid, 1, G.n), dim3(256), 0, s, G.D, G);

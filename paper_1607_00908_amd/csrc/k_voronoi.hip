@@ -730,10 +730,13 @@ __global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restr
     if (t == 0) gmem(B.tpair_n)[tile] = min(S.nout, DV_TILE_PAIRS);
 }
 
-// Rows from the tiles' couple lists: one wave per tile, one lane per couple
-// end.  Rows are sets: a couple found by several tiles is stored once.
+// Rows from the tiles' couple lists: 16 lanes per tile (a tile lists a few
+// couples), one lane per couple end.  Rows are sets: a couple found by
+// several tiles is stored once.
+#define ROW_LANES 16
 __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D, Batch G) {
-    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int gt = blockIdx.x * (256 / ROW_LANES) + (threadIdx.x / ROW_LANES);
+    const int lane = threadIdx.x % ROW_LANES;
     if (gt >= G.tiles) return;
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
     const Bufs &B = D[G.idx[e]];
@@ -742,7 +745,7 @@ __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D, Batch 
     if (fs->err) return;
     const int n = gmem(B.tpair_n)[tile];
     gint *adj = gmem(B.cur.adj);
-    for (int j = lane; j < 2 * n; j += 64) {
+    for (int j = lane; j < 2 * n; j += ROW_LANES) {
         const int2 p = ld_int2(B.tpairs, (size_t)tile * DV_TILE_PAIRS + (j >> 1));
         if (j & 1) row_insert(adj + (size_t)p.y * B.maxdeg, B.maxdeg, p.x, fs);
         else row_insert(adj + (size_t)p.x * B.maxdeg, B.maxdeg, p.y, fs);
@@ -761,6 +764,6 @@ void launch_voronoi(const Batch &G, hipStream_t s, Prof &P) {
     else hipLaunchKernelGGL(k_owner_edges<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
     P.end(ST_OWNER_EDGES, s);
     P.begin(ST_ROWS, s);
-    hipLaunchKernelGGL(k_rows, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
+    hipLaunchKernelGGL(k_rows, dim3((G.tiles + 256 / ROW_LANES - 1) / (256 / ROW_LANES)), dim3(256), 0, s, G.D, G);
     P.end(ST_ROWS, s);
 }

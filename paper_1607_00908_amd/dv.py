@@ -36,7 +36,7 @@ EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync
            "dv_group_destroy",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
-DEFAULT_BATCH = 16   # what max_batch = 0 selects
+DEFAULT_BATCH = 32   # what max_batch = 0 selects
 
 STAGES = ("tile_ccl", "merge", "resolve", "relabel", "finalize", "owner_edges", "rows",
           "match", "diff", "events", "place")

@@ -187,7 +187,7 @@ def test_capacity_rejection_keeps_the_past():
     det.close()
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3, 4, 8, 16])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 8, 16, 32, 64])
 def test_batched_bursts_match_the_oracle(depth):
     """Frames pushed back to back with no synchronisation in between go to the
     device in batches (each stage one launch over the batch, the comparisons
@@ -195,14 +195,16 @@ def test_batched_bursts_match_the_oracle(depth):
     previous frame, labels, couples, matching) must equal the oracle's."""
     lx, ly = 200, 160
     sim = synth.DiskSim(lx, ly, 30, 4.0, 7.0, 0.6, 3e-3, seed=91 + depth)
-    frames = list(sim.frames(11))
+    # bursts: a full batch (frames 1 .. depth), then a full and a partial one
+    n = max(11, 2 * depth + 3)
+    frames = list(sim.frames(n))
     dev = [torch.from_numpy(f).cuda() for f in frames]
     det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=depth)
     seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
     for k, f in enumerate(frames):
         now, ref = seq.push(f)
         det.push(dev[k])
-        if k in (0, 4, 10):
+        if k in (0, depth, n - 1):
             say(f"  [batch{depth}] burst ends at frame {k}")
             check_frame(det, now, ref, lx, ly)
     assert det.info().frame == len(frames)
