@@ -224,6 +224,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
     const Bufs &B = D[G.idx[e]];
     __shared__ int L[DV_TILE_SITES];
     __shared__ uint32_t rowm[DV_TILE];
+    __shared__ uint16_t slot_of[DV_TILE_SITES];   // piece slot of each piece root
     __shared__ int npc;
     const int tile = blockIdx.x - G.tbase[e];
     const int tx = tile % B.ntx, ty = tile / B.ntx;
@@ -255,28 +256,30 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
     tile_ccl<GEOM>(B, F.p[e], x0, y0, tw, th, L, rowm);
 
     const int cx = t & 31, ry = t >> 5;
+    // piece roots take their slots in the tile's piece list
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = ry + 8 * i, s = y * 32 + cx;
+        if (L[s] != s) continue;
+        const int slot = atomicAdd(&npc, 1);
+        slot_of[s] = (uint16_t)slot;
+        gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
+        const int g = (y0 + y) * B.lx + x0 + cx;
+        gmem(B.parent)[g] = g;
+    }
+    __syncthreads();
+    // the 16-bit map holds each inside site's piece slot
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
         const int r = L[s];
+        if (cx >= tw || y >= th) continue;
         const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
-        if (cx < tw && y < th)
-            gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
-        if (r < 0) {
-            // an outside border site is marked so that merging needs no field
-            if (border && cx < tw && y < th) gmem(B.parent)[(y0 + y) * B.lx + x0 + cx] = -1;
-            continue;
-        }
-        const int g = (y0 + y) * B.lx + x0 + cx;
-        if (r == s) {
-            const int slot = atomicAdd(&npc, 1);
-            gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
-            gmem(B.parent)[g] = g;
-        } else if (border) {
-            gmem(B.parent)[g] = (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
-        }
+        gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : slot_of[r];
+        if (!border || r == s) continue;
+        // an outside border site is marked so that merging needs no field
+        gmem(B.parent)[(y0 + y) * B.lx + x0 + cx] = r < 0 ? -1 : (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
     }
-    __syncthreads();
     if (t == 0) B.npieces[tile] = npc;
 }
 
@@ -444,12 +447,13 @@ template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
-    __shared__ int L[DV_TILE_SITES];
-    // per piece root (indexed by its tile-local site): rank, component root
-    // (x | y << 16), integer sums
-    __shared__ int prank[DV_TILE_SITES];
-    __shared__ uint32_t pxy[DV_TILE_SITES];
-    __shared__ int psx[DV_TILE_SITES], psy[DV_TILE_SITES], pn[DV_TILE_SITES];
+    // piece slot of every site (0xffff outside), as written by k_tile_ccl
+    __shared__ uint16_t L[DV_TILE_SITES];
+    // per piece (indexed by its slot; a tile has at most 512 pieces): rank,
+    // component root (x | y << 16), integer sums
+    __shared__ int prank[DV_TILE_SITES / 2];
+    __shared__ uint32_t pxy[DV_TILE_SITES / 2];
+    __shared__ int psx[DV_TILE_SITES / 2], psy[DV_TILE_SITES / 2], pn[DV_TILE_SITES / 2];
     __shared__ int wsum[16];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ uint16_t runs[DV_TILE_SITES / 2];   // (row << 5) | first column of each run
@@ -462,7 +466,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
 
-    // tile-local roots of the tile, as written by k_tile_ccl
+    // piece slots of the tile's sites and its piece count, as written by k_tile_ccl
     const int cx = t & 31, ry = t >> 5;
     uint16_t u[4];
 #pragma unroll
@@ -471,10 +475,12 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const bool ok = cx < tw && y < th;
         u[i] = gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + (ok ? y * 32 + cx : 0)];
     }
+    const int np = gmem(B.npieces)[tile];
+    const int proot = t < np ? gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + t] : 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
-        L[y * 32 + cx] = (cx < tw && y < th && u[i] != 0xffff) ? (int)u[i] : -1;
+        L[y * 32 + cx] = (cx < tw && y < th) ? u[i] : (uint16_t)0xffff;
     }
     // roots in the bands before each band (exclusive prefix of band totals);
     // the first block publishes K and the capacity check
@@ -486,24 +492,22 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     }
     __syncthreads();
 
-    // each piece root (a site that is its own tile-local root) looks up the
-    // component root and its canonical rank
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, r = y * 32 + cx;
-        if (L[r] != r) continue;
-        const int g = (y0 + y) * lx + x0 + cx;
+    // each piece (thread t takes slot t; at most 512) looks up the component
+    // root and its canonical rank
+    for (int k = t; k < np; k += DV_BLOCK) {
+        const int r = k == t ? proot : gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + k];
+        const int g = (y0 + (r >> 5)) * lx + x0 + (r & 31);
         const int G = gmem(B.parent)[g];    // component root (compressed)
         const int gx = G % lx, gy = G / lx;
         const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
         const uint32_t below = (1u << (gx & 31)) - 1u;
         const int rank = boff[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
                          __popc(gmem(B.seg_mask)[seg] & below);
-        prank[r] = rank;
-        pxy[r] = (uint32_t)gx | ((uint32_t)gy << 16);
-        psx[r] = 0;
-        psy[r] = 0;
-        pn[r] = 0;
+        prank[k] = rank;
+        pxy[k] = (uint32_t)gx | ((uint32_t)gy << 16);
+        psx[k] = 0;
+        psy[k] = 0;
+        pn[k] = 0;
         if (G == g && rank < B.kmax) gmem(B.acc_root)[rank] = G;
     }
     __syncthreads();
@@ -521,7 +525,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
         const int r = L[s];
-        const bool inside = r >= 0;
+        const bool inside = r != 0xffff;
         const unsigned long long bal = __ballot(inside);
         if (cx == 0) rowm[y] = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (B.keep_maps && cx < tw && y < th)
@@ -597,15 +601,12 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, r = y * 32 + cx;
-        if (L[r] != r) continue;
-        const int rank = prank[r];
+    for (int k = t; k < np; k += DV_BLOCK) {
+        const int rank = prank[k];
         if (rank >= B.kmax) continue;
-        atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)(long long)psx[r]);
-        atomicAdd((unsigned long long *)&B.acc_y[rank], (unsigned long long)(long long)psy[r]);
-        atomicAdd(&B.acc_n[rank], pn[r]);
+        atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)(long long)psx[k]);
+        atomicAdd((unsigned long long *)&B.acc_y[rank], (unsigned long long)(long long)psy[k]);
+        atomicAdd(&B.acc_n[rank], pn[k]);
     }
 }
 
