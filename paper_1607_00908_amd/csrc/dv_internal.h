@@ -9,7 +9,7 @@
 #define DV_TILE_SITES (DV_TILE * DV_TILE)
 #define DV_BLOCK 256               // threads per tile workgroup
 #define DV_EMPTY 0x77777777        // MAXLINK: empty row slot / no colour
-#define DV_CAND_CAP 256            // candidate centre images held in LDS per chunk
+#define DV_CAND_CAP 128            // candidate centre images held in LDS per chunk
 #define DV_TILE_PAIRS 128          // couples a colouring tile lists for the row build
 
 // error bits raised on the device during a frame

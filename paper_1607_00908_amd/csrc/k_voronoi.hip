@@ -142,7 +142,7 @@ __device__ __forceinline__ void row_insert(gint *row, int maxdeg, int v, FrameSt
 #define WSITES 5      // ceil(34*34 / 256) window sites per thread
 #define RCAP 256      // item ranges held in LDS per batch
 #define IMG_MAX 9     // periodic images one centre can contribute (tiny lattices)
-#define CAND_BATCH 16 // centres appended per batch (room for IMG_MAX images each)
+#define CAND_BATCH 8  // centres appended per batch (room for IMG_MAX images each)
 
 // Shared state of one colouring tile.
 struct OwnerLds {
@@ -239,12 +239,13 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
     }
 }
 
-// Six resident blocks per CU (register budget 85): the block's gather and
-// barrier-bounded phases are latency chains that other resident blocks fill.
+// Seven resident blocks per CU (register budget 73, 21 KB of LDS): the
+// block's gather and barrier-bounded phases are latency chains that other
+// resident blocks fill, which pays for the few values that spill.
 // GEOM: some entry of the launch has walls or obstacles; the periodic,
 // unobstructed instance carries none of their tests.
 template <bool GEOM>
-__global__ __launch_bounds__(DV_BLOCK, 6) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
+__global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
     const int tile = blockIdx.x - G.tbase[e];
