@@ -150,11 +150,17 @@ struct OwnerLds {
     // candidate centres as appended: tile-relative Q.8 image positions, label
     int cx[DV_CAND_CAP], cy[DV_CAND_CAP];
     int lab[DV_CAND_CAP];
-    // the same, ordered by label for evaluation: x, y, |c|^2 as doubles
-    double sx[DV_CAND_CAP], sy[DV_CAND_CAP], sk[DV_CAND_CAP];
+    // the kept ones, ordered by label for evaluation: x, y, |c|^2 as doubles,
+    // or as 32-bit integers when every kept one is near the tile (imode)
+    union {
+        struct { double sx[DV_CAND_CAP], sy[DV_CAND_CAP], sk[DV_CAND_CAP]; };
+        struct { int ix[DV_CAND_CAP], iy[DV_CAND_CAP], ik[DV_CAND_CAP]; };
+    };
     int sl[DV_CAND_CAP];
     uint8_t keep[DV_CAND_CAP];   // the candidate is not beaten everywhere in the window
     int nkeep;                   // candidates kept (the ordered list's length)
+    int far;                     // some kept candidate is beyond the 32-bit range
+    int imode;                   // the ordered list holds 32-bit integers
     int ncand;
     int nchunks;   // times the list was evaluated and emptied before the end
     // item ranges of the cell rectangle being visited
@@ -277,7 +283,7 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
         be[i] = 1.0e300;
         bl[i] = DV_EMPTY;
     }
-    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; S.nkeep = 0; }
+    if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; S.nkeep = 0; S.imode = 0; }
     __syncthreads();
 
     // tile centre (absolute Q.8) and the window's relative x / y extent
@@ -298,8 +304,15 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
     // are ordered by label, so that a strict comparison already sends ties to
     // the lowest label; a later chunk (after an overflow) also compares
     // labels.
-    auto eval_owners = [&]() {
-        if (t == 0) S.nkeep = 0;
+    // In the usual case every kept candidate lies within 23170 Q.8 units
+    // (about 90 sites) of the tile origin on both axes: then |c|^2 < 2^30,
+    // each product of a coordinate with a doubled point coordinate (at most
+    // 16384 in magnitude) fits 24-bit operands, and every value below stays
+    // inside 32-bit range, so the same exact comparison runs on integers.
+    // That applies to the only evaluation of a tile (no overflow chunks);
+    // otherwise the float64 form is used.
+    auto eval_owners = [&](bool last) {
+        if (t == 0) { S.nkeep = 0; S.far = 0; }
         __syncthreads();
         const int nc = min(S.ncand, DV_CAND_CAP);
         {   // 16 lanes per candidate i, lane j of the group takes the rivals j, j + 16, ...
@@ -327,11 +340,15 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
                 const unsigned grp = (unsigned)(b >> (t & 48)) & 0xffffu;
                 if (gj == 0 && i < nc) {
                     S.keep[i] = grp ? 0 : 1;
-                    if (!grp) atomicAdd(&S.nkeep, 1);
+                    if (!grp) {
+                        atomicAdd(&S.nkeep, 1);
+                        if (abs(S.cx[i]) > 23170 || abs(S.cy[i]) > 23170) S.far = 1;
+                    }
                 }
             }
         }
         __syncthreads();
+        const bool im = last && S.nchunks == 0 && !S.far;
         for (int c = t; c < nc; c += DV_BLOCK) {
             if (!S.keep[c]) continue;
             const int lab = S.lab[c];
@@ -340,14 +357,46 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
                 const int l2 = S.lab[j];
                 r += (S.keep[j] && (l2 < lab || (l2 == lab && j < c))) ? 1 : 0;
             }
-            const double x = (double)S.cx[c], y = (double)S.cy[c];
-            S.sx[r] = x;
-            S.sy[r] = y;
-            S.sk[r] = x * x + y * y;
+            const int ix = S.cx[c], iy = S.cy[c];
+            if (im) {
+                S.ix[r] = ix;
+                S.iy[r] = iy;
+                S.ik[r] = ix * ix + iy * iy;
+            } else {
+                const double x = (double)ix, y = (double)iy;
+                S.sx[r] = x;
+                S.sy[r] = y;
+                S.sk[r] = x * x + y * y;
+            }
             S.sl[r] = lab;
         }
+        if (t == 0) S.imode = im ? 1 : 0;
         __syncthreads();
         const int nk = S.nkeep;
+        if (im) {
+            // the only evaluation: strict comparison, ties to the first (lowest label)
+            int m2x[WSITES], m2y[WSITES], bi[WSITES];
+#pragma unroll
+            for (int i = 0; i < WSITES; ++i) {
+                const int w = t + i * DV_BLOCK;
+                const int wy = (w * wmagic) >> 16, wx = w - wy * W;
+                m2x[i] = -512 * (wx - 1);
+                m2y[i] = -512 * (wy - 1);
+                bi[i] = INT_MAX;
+            }
+            for (int c = 0; c < nk; ++c) {
+                const int cx = S.ix[c], cy = S.iy[c], kk = S.ik[c];
+                const int lab = S.sl[c];
+#pragma unroll
+                for (int i = 0; i < WSITES; ++i) {
+                    const int e = __mul24(m2x[i], cx) + __mul24(m2y[i], cy) + kk;
+                    const bool lt = e < bi[i];
+                    bi[i] = lt ? e : bi[i];
+                    bl[i] = lt ? lab : bl[i];
+                }
+            }
+            return;
+        }
         double m2x[WSITES], m2y[WSITES];
 #pragma unroll
         for (int i = 0; i < WSITES; ++i) {
@@ -557,14 +606,14 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
                 [&](int m) {
                     // evaluate and empty the list when this batch could overflow it
                     if (S.ncand + m * IMG_MAX > DV_CAND_CAP) {
-                        eval_owners();
+                        eval_owners(false);
                         __syncthreads();
                         if (t == 0) { S.ncand = 0; S.nchunks += 1; }
                         __syncthreads();
                     }
                 });
         }
-        eval_owners();
+        eval_owners(true);
     }
     // window sites with no colour: beyond a wall, and obstacles
 #pragma unroll
@@ -588,6 +637,7 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
     // against the candidate list (or, after a candidate-list overflow, by the
     // exact grid search).
     const bool in_lds = S.nchunks == 0;
+    const bool imode = S.imode;
     const int ncl = S.nkeep;   // the ordered list of the single chunk
     auto emit = [&](int a, int b) {
         const int slot = atomicAdd(&S.npair, 1);
@@ -670,7 +720,19 @@ __global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restr
                 const int code = S.q[j], r = code & 3, sxy = code >> 2;
                 const int qsx = sxy & 31, qsy = sxy >> 5;
                 int m;
-                if (in_lds) {
+                if (in_lds && imode) {
+                    // (the 32-bit form of the evaluation; |2 q| <= 16384 as for the sites)
+                    const int qx = -2 * (256 * qsx + inx(r)), qy = -2 * (256 * qsy + iny(r));
+                    int bee = INT_MAX;
+                    m = DV_EMPTY;
+                    // the single chunk is ordered by label: ties keep the first
+                    for (int k = 0; k < ncl; ++k) {
+                        const int e = __mul24(qx, S.ix[k]) + __mul24(qy, S.iy[k]) + S.ik[k];
+                        const bool lt = e < bee;
+                        bee = lt ? e : bee;
+                        m = lt ? S.sl[k] : m;
+                    }
+                } else if (in_lds) {
                     const double qx = -2.0 * (256.0 * qsx + inx(r)), qy = -2.0 * (256.0 * qsy + iny(r));
                     double bee = 1.0e300;
                     m = DV_EMPTY;
