@@ -137,7 +137,7 @@ __device__ __forceinline__ void row_insert(gint *row, int maxdeg, int v, FrameSt
 
 #define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
 #define QCAP 512        // inner-frame queries answered per chunk
-#define TMP_CAP 256     // centres kept from the first pass
+#define TMP_CAP 128     // centres kept from the first pass
 
 #define WSITES 5      // ceil(34*34 / 256) window sites per thread
 #define RCAP 256      // item ranges held in LDS per batch
@@ -245,13 +245,13 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
     }
 }
 
-// Seven resident blocks per CU (register budget 73, 21 KB of LDS): the
+// Eight resident blocks per CU (register budget 64, 18.8 KB of LDS): the
 // block's gather and barrier-bounded phases are latency chains that other
-// resident blocks fill, which pays for the few values that spill.
+// resident blocks fill, which pays for the values that spill.
 // GEOM: some entry of the launch has walls or obstacles; the periodic,
 // unobstructed instance carries none of their tests.
 template <bool GEOM>
-__global__ __launch_bounds__(DV_BLOCK, 7) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
+__global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs &B = D[G.idx[e]];
     const int tile = blockIdx.x - G.tbase[e];
