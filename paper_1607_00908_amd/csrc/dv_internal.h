@@ -82,9 +82,10 @@ struct Bufs {
     int32_t *parent;       // [N] union-find over tile-border sites and piece roots
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
-    uint16_t *lab16;       // [tiles][32][32] tile-local root of every site, 0xffff outside
+    uint16_t *lab16;       // [tiles][32][32] piece slot of every site (its index in the
+                           // tile's piece list), 0xffff outside
                            // (tile-major: a tile's 2 KB are contiguous)
-    uint16_t *pieces;      // [tiles][DV_TILE_SITES] local roots of each tile
+    uint16_t *pieces;      // [tiles][DV_TILE_SITES] tile-local root site of each piece slot
     int32_t *npieces;      // [tiles]
     uint32_t *seg_mask;    // [ly][ntx] component-root bits per (row, tile column)
     int32_t *seg_prefix;   // [ly][ntx] roots before each segment within its band

@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_edge_write(const Bufs *__restrict__ D, 
 }  // namespace
 
 void launch_compare(const Batch &G, hipStream_t s, Prof &P) {
-    // one wave per point / row, grid-stride: a quarter of K_max waves per frame
+    // one wave per row, grid-stride: a quarter of K_max waves per frame
     // (K is usually well below K_max)
     const int grid = (int)std::max<long long>(1, std::min<long long>((G.kmax + 15) / 16, 512));
     P.begin(ST_MATCH, s);

@@ -3,14 +3,16 @@
 // The lattice is cut into 32x32 tiles.  Per frame:
 //   k_tile_ccl   threshold + union-find of each tile in LDS; every tile-border
 //                site and every tile-local root ("piece") gets an entry in the
-//                global parent array (global linear site indices);
+//                global parent array (global linear site indices); pieces take
+//                slots in the tile's piece list, and every inside site's slot
+//                goes to a 16-bit map;
 //   k_merge      unions across tile borders and the periodic seams (none
 //                across a wall);
 //   k_resolve    per band of 32 rows: each piece finds its global root;
 //                component roots (the smallest linear index of each component)
 //                are marked in a bitmap of (row, tile column) segments, which
 //                is scanned in raster order within the band;
-//   k_relabel    reads the tile-local roots written by k_tile_ccl, writes
+//   k_relabel    reads the piece slots written by k_tile_ccl, writes
 //                canonical labels and accumulates exact integer offsets from
 //                each component's root (signed minimum image) per piece, then
 //                per component.

@@ -572,7 +572,7 @@ def test_channel_with_posts_small(seed):
 
 def test_channel2048_batched_burst():
     """Full-size channel frames (2048 x 1024, 2000 droplets, posts) pushed back
-    to back in batches of 16; the first two and the last comparisons against
+    to back in batches of 32 (the default); the first two and the last comparisons against
     the oracle."""
     sim, spec = synth.workload("channel2048")
     obst = sim.obstacles()
