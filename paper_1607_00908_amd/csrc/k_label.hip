@@ -125,8 +125,10 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 }
 
 // Labels the inside sites of one tile with tile-local union-find.  On return
-// (after a barrier) L[s] is the smallest tile-local index of the piece of s,
-// or -1 when s is outside or beyond the lattice.  rowm: LDS [32] row masks.
+// (after a barrier) L[L[s]] is the smallest tile-local index of the piece of
+// an inside site s (L[s] is that index for the first site of a run, else the
+// run's first site), and L[s] is -1 when s is outside or beyond the lattice.
+// rowm: LDS [32] row masks.
 //
 // Runs of a row are connected by construction (each site points to its run's
 // first site).  Runs of consecutive rows are united once per touching pair,
@@ -147,6 +149,7 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
         v[i] = field[g];
         if (GEOM && B.obst) ob[i] = gmem(B.obst)[g];
     }
+    int rs[4];   // first column of each site's run (-1 outside)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
@@ -154,7 +157,8 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
         const unsigned long long bal = __ballot(in);
         const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
         if (cx == 0) rowm[y] = m;
-        L[y * 32 + cx] = in ? y * 32 + run_start(m, cx) : -1;
+        rs[i] = in ? run_start(m, cx) : -1;
+        L[y * 32 + cx] = in ? y * 32 + rs[i] : -1;
     }
     __syncthreads();
     // Unions of each run [a, b] with the runs of the row above that touch
@@ -191,30 +195,20 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
         }
     }
     __syncthreads();
-    // roots of the run starts, then every site takes its run start's root.
-    // The roots are stored only after a barrier: a find that is still
-    // shortening its path could otherwise overwrite a stored root with an
-    // intermediate ancestor.
+    // roots of the run starts.  The roots are stored only after a barrier: a
+    // find that is still shortening its path could otherwise overwrite a
+    // stored root with an intermediate ancestor.  Other inside sites keep
+    // pointing at their run start.
     int root[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
-        const int v = L[s];
-        root[i] = (v >= 0 && v < s && run_start(rowm[y], cx) == cx) ? lfind(L, s) : -1;
+        root[i] = (rs[i] == cx && L[s] < s) ? lfind(L, s) : -1;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         if (root[i] >= 0) L[(ry + 8 * i) * 32 + cx] = root[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
-        if (L[s] >= 0) {
-            const int st = y * 32 + run_start(rowm[y], cx);
-            if (st != s) L[s] = L[st];
-        }
-    }
     __syncthreads();
 }
 
@@ -274,7 +268,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
-        const int r = L[s];
+        int r = L[s];
+        if (r >= 0) r = L[r];   // the run start's root
         if (cx >= tw || y >= th) continue;
         const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
         gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : slot_of[r];
