@@ -484,6 +484,25 @@ def test_sparse_cluster_exercises_candidate_overflow():
     run_sequence([f, g], 0.5, kmax=2048, tag="cluster")
 
 
+def test_few_far_centres_mix_integer_and_float_colouring():
+    """Five small droplets on a 768^2 lattice: tiles near a droplet have their
+    candidates within the 32-bit range, distant tiles do not and take the
+    float64 form; both must give the oracle's colours, couples and flips."""
+    L = 768
+    rng = np.random.default_rng(21)
+    frames = []
+    c = rng.uniform(0, L, (5, 2))
+    for k in range(3):
+        f = np.zeros((L, L), np.float32)
+        for x, y in c + k * np.array([1.3, -0.7]):
+            yy, xx = np.ogrid[0:L, 0:L]
+            dx = (xx - x + L / 2) % L - L / 2
+            dy = (yy - y + L / 2) % L - L / 2
+            f[(dx * dx + dy * dy) < 36.0] = 1.0
+        frames.append(f)
+    run_sequence(frames, 0.5, kmax=64, tag="far5")
+
+
 def test_serving_results_equal_alone_and_in_the_mix():
     """Frames of six streams arriving in a random order are served in mixed
     batches; every frame's flips and counts equal those of the same stream run
