@@ -68,22 +68,9 @@ __device__ void lunite(int *L, int a, int b) {
 }
 
 // ---- union-find in global memory over linear site indices -------------------
-// Same path shortening as lfind.  gfind_ro walks without writing: it is the
-// find of a pass that also stores final roots, which a concurrent shortening
-// store could otherwise replace with an intermediate ancestor.
-__device__ __forceinline__ int gfind(gint *P, int a) {
-    int p = P[a];
-    if (p == a) return a;
-    int prev = a;
-    for (;;) {
-        const int next = P[p];
-        if (next == p) return p;
-        P[prev] = next;
-        prev = p;
-        p = next;
-    }
-}
-
+// gfind2 shortens paths as lfind does.  gfind_ro walks without writing: it is
+// the find of a pass that also stores final roots, which a concurrent
+// shortening store could otherwise replace with an intermediate ancestor.
 __device__ __forceinline__ int gfind_ro(const gint *P, int a) {
     int p = P[a];
     while (p != a) {
@@ -93,11 +80,43 @@ __device__ __forceinline__ int gfind_ro(const gint *P, int a) {
     return a;
 }
 
+// Finds of two nodes at once: the walks advance together, so the loads of a
+// step are in flight together (a root's parent is itself, so both loads are
+// always valid); each walk shortens its path (a node gets its grandparent, as
+// in lfind), and each step moves to a smaller index, so both end.
+__device__ __forceinline__ void gfind2(gint *P, int &a, int &b) {
+    int pa = P[a], pb = P[b];
+    int preva = a, prevb = b;
+    bool da = pa == a, db = pb == b;
+    while (!(da && db)) {
+        const int na = P[pa], nb = P[pb];
+        if (!da) {
+            if (na == pa) {
+                da = true;
+            } else {
+                P[preva] = na;
+                preva = pa;
+                pa = na;
+            }
+        }
+        if (!db) {
+            if (nb == pb) {
+                db = true;
+            } else {
+                P[prevb] = nb;
+                prevb = pb;
+                pb = nb;
+            }
+        }
+    }
+    a = pa;
+    b = pb;
+}
+
 __device__ void gunite(gint *P, int a, int b) {
     bool done;
     do {
-        a = gfind(P, a);
-        b = gfind(P, b);
+        gfind2(P, a, b);
         if (a < b) {
             const int old = __hip_atomic_fetch_min(P + b, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             done = (old == b);
