@@ -68,6 +68,8 @@ extern "C" {
 #define DV_OBSTACLES 4u  /* the context holds an obstacle mask (dv_set_obstacles) */
 #define DV_OPEN_X 8u     /* walls across x instead of the periodic wrap          */
 #define DV_OPEN_Y 16u    /* walls across y instead of the periodic wrap          */
+#define DV_KEEP_RESULTS 32u /* keep every frame's record and flips until
+                                dv_get_results returns them (Sec. 3.2.4, Sec. 4) */
 
 /* dv_flip.flags bits (with DV_CLASSIFY; Sec. 3.2.4, extraction of events).
  * Active points are the ends of the flips.  BULK: both ends are connected to
@@ -104,7 +106,7 @@ typedef struct {
                                 4 .. 64; 0 selects 48                              */
     int32_t device;          /* HIP device ordinal                                 */
     uint32_t flags;          /* DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES |
-                                DV_OPEN_X | DV_OPEN_Y                              */
+                                DV_OPEN_X | DV_OPEN_Y | DV_KEEP_RESULTS            */
     int32_t max_batch;       /* frames sent to the device together, 1 .. 64; 0
                                 selects 32.  Each holds its own per-site buffers. */
 } dv_config;
@@ -121,10 +123,12 @@ typedef struct {
     uint32_t flags;
 } dv_flip;
 
-/* Summary of the most recent push. */
+/* Summary of one frame (Sec. 3.1 counts, Sec. 3.2.3 exclusions and trigger,
+ * Sec. 3.2.4 flips): of the most recent push (dv_get_info), or of every frame
+ * in push order (dv_get_results). */
 typedef struct {
-    int64_t frame;                  /* frames accepted so far                          */
-    int32_t status;                 /* dv_status of the most recent push               */
+    int64_t frame;                  /* frames accepted up to and including this one    */
+    int32_t status;                 /* DV_OK, or DV_ERR_CAPACITY when rejected          */
     int32_t n_components;           /* K of the most recent push (may exceed K_max
                                        when status is DV_ERR_CAPACITY)                  */
     int32_t n_edges;                /* E: undirected Delaunay couples                   */
@@ -136,7 +140,8 @@ typedef struct {
     uint32_t global_trigger;        /* 1 when any row changed (Sec. 3.2.3)             */
 } dv_frame_info;
 
-/* Create a context on cfg->device.  hip_stream is a hipStream_t on that
+/* Create a context on cfg->device (state of one sequence of configurations
+ * compared frame by frame, Sec. 3.2.3).  hip_stream is a hipStream_t on that
  * device, or NULL for a stream the context creates (and destroys).  All
  * device work of the context is ordered on that stream.  Pushed frames are
  * queued on the host and sent to the device together, max_batch at a time
@@ -145,7 +150,8 @@ typedef struct {
  * failure *out is NULL. */
 dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
 
-/* Enqueue one frame.  field_device: lx*ly float32 values in device memory,
+/* Enqueue one frame: the whole procedure of Sec. 3.1-3.2.4 runs on it.
+ * field_device: lx*ly float32 values in device memory,
  * row-major (x fastest), complete in the order of the context's stream at
  * the time of this call.  The field is read asynchronously on that stream,
  * at the latest when the next synchronising call (dv_get_flips, dv_get_info,
@@ -154,8 +160,10 @@ dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
  * every max_batch-th push enqueues the launches of the queued frames.
  * The first accepted frame has no past and yields no flips.  A frame whose
  * component count exceeds K_max, or whose Delaunay degree exceeds the row
- * capacity, is rejected: the next synchronising call reports
- * DV_ERR_CAPACITY and the past state stays that of the last accepted frame. */
+ * capacity, is rejected and the past state stays that of the last accepted
+ * frame.  The rejection is reported in that frame's record (dv_get_results)
+ * and, while it is the most recent push, by dv_get_info, dv_get_flips and the
+ * other getters (DV_ERR_CAPACITY). */
 dv_status dv_push_frame(dv_ctx *ctx, const float *field_device);
 
 /* Set the obstacle mask (Sec. 3.2.1): lx*ly bytes, row-major, nonzero = obstacle;
@@ -166,41 +174,82 @@ dv_status dv_push_frame(dv_ctx *ctx, const float *field_device);
  * Needs DV_OBSTACLES at creation (else DV_ERR_STATE); the mask starts empty. */
 dv_status dv_set_obstacles(dv_ctx *ctx, const uint8_t *mask, int32_t mask_on_device);
 
-/* Wait for the device and copy the flips of the most recent push.  When
- * capacity is smaller than the count, *n_out receives the count, nothing is
- * written and DV_ERR_CAPACITY is returned. */
+/* Breaking and arising couples of the most recent push (Sec. 3.2.4), in the
+ * order given at dv_flip.  Waits for the device.  When capacity is smaller
+ * than the count, *n_out receives the count, nothing is written and
+ * DV_ERR_CAPACITY is returned.  With batched pushes only the last frame of
+ * the batch is the most recent push: dv_get_results returns every frame's. */
 dv_status dv_get_flips(dv_ctx *ctx, dv_flip *host_out, int32_t capacity, int32_t *n_out);
 
-/* Wait for the device; fill *info for the most recent push.  Returns the
- * status of that push (DV_OK or DV_ERR_CAPACITY); *info is filled either way. */
+/* Wait for the device; fill *info for the most recent push (counts of
+ * Sec. 3.1-3.2.4).  Returns the status of that push (DV_OK or
+ * DV_ERR_CAPACITY); *info is filled either way. */
 dv_status dv_get_info(dv_ctx *ctx, dv_frame_info *info);
 
-/* Send any queued frames and wait until every pushed frame is processed. */
+/* ---- every frame's results (Sec. 3.2.4: the flips of each comparison; Sec.
+ * 4: detection at every interval of the run).  Needs DV_KEEP_RESULTS, else
+ * DV_ERR_STATE.  The library keeps, for every frame sent to the device, its
+ * dv_frame_info and its flips until dv_get_results has returned them: frames
+ * of a batch are never overwritten unread (when a results page has to be
+ * reused first, its unread frames are moved to host memory).
+ *
+ * wait != 0: queued frames are sent and every pushed frame is waited for.
+ * wait == 0: nothing is sent or waited for; only frames whose launch has
+ *            completed count (possibly none).
+ *
+ * dv_results_ready: *n_frames unread frames and *n_flips flips in them. */
+dv_status dv_results_ready(dv_ctx *ctx, int32_t wait, int32_t *n_frames, int32_t *n_flips);
+
+/* Return unread frames oldest first (push order, rejected frames included,
+ * with status DV_ERR_CAPACITY and no flips): infos[i] for the i-th, and their
+ * flips concatenated in the same order (infos[i].n_flips each, dv_flip order
+ * within a frame).  Whole frames are returned while both capacities allow;
+ * *n_frames and *n_flips receive what was written.  Returns DV_OK when every
+ * ready frame was returned, DV_ERR_CAPACITY when some remain unread (they are
+ * returned by the next call).  Host outputs; NULL is accepted for an output
+ * whose capacity is 0. */
+dv_status dv_get_results(dv_ctx *ctx, int32_t wait, dv_frame_info *infos, int32_t cap_frames,
+                         int32_t *n_frames, dv_flip *flips, int32_t cap_flips, int32_t *n_flips);
+
+/* Send any queued frames and wait until every pushed frame has gone through
+ * the procedure of Sec. 3.1-3.2.4. */
 dv_status dv_sync(dv_ctx *ctx);
 
-/* Release everything the context owns.  NULL is accepted. */
+/* Release everything the context owns (the sequence state of Sec. 3.2.3:
+ * past centres and rows).  NULL is accepted. */
 void dv_destroy(dv_ctx *ctx);
 
 /* ---- inspection (all synchronise; host outputs; state of the most recent
  * push, which must have been accepted, else its error is returned) ---- */
 
-/* Label map, lx*ly int32.  Needs DV_KEEP_MAPS (else DV_ERR_STATE). */
+/* Label map of the cluster labelling (Sec. 3.1), lx*ly int32 row-major,
+ * DV_NO_LABEL outside.  Needs DV_KEEP_MAPS (else DV_ERR_STATE). */
 dv_status dv_get_labels(dv_ctx *ctx, int32_t *host_out);
-/* Voronoi owner (colour) map, lx*ly int32.  Needs DV_KEEP_MAPS. */
+/* Colour map of the digital Voronoi tessellation (Sec. 3.2.1): nearest centre
+ * of every site, DV_MAXLINK on obstacles and when there is no centre; lx*ly
+ * int32 row-major.  Needs DV_KEEP_MAPS. */
 dv_status dv_get_owner(dv_ctx *ctx, int32_t *host_out);
-/* Components: q8_xy[2k], [2k+1] Q.8 centre; xy[2k], [2k+1] float64 centre;
- * size[k] member count; any output pointer may be NULL. */
+/* Centres of mass and sizes of the components (Sec. 3.1, last step; centroid
+ * equation of Sec. 2 with unit weights): q8_xy[2k], [2k+1] Q.8 centre;
+ * xy[2k], [2k+1] float64 centre; size[k] member count; any output pointer may
+ * be NULL.  capacity and *n_out count components (DV_ERR_CAPACITY with the
+ * count when too small). */
 dv_status dv_get_components(dv_ctx *ctx, int32_t *q8_xy, double *xy, int32_t *size,
                             int32_t capacity, int32_t *n_out);
-/* Undirected couples ab[2e] < ab[2e+1], sorted by (a, b). */
+/* Delaunay couples given by the neighbour rules (Sec. 3.2.2, compressed
+ * adjacency of Sec. 3.2.2-3.2.3): undirected, ab[2e] < ab[2e+1], sorted by
+ * (a, b); capacity and *n_out count couples. */
 dv_status dv_get_edges(dv_ctx *ctx, int32_t *ab, int32_t capacity, int32_t *n_out);
-/* Phi of the most recent comparison indexed by past label; -1 for dropped
- * past points; *n_out = K of the past frame (0 for the first frame). */
+/* Kinematic isomorphism Phi_{P->N} of the most recent comparison (Sec.
+ * 3.2.3) indexed by past label; -1 for past points dropped as appearing /
+ * vanishing bubbles; *n_out = K of the past frame (0 for the first frame). */
 dv_status dv_get_matching(dv_ctx *ctx, int32_t *phi, int32_t capacity, int32_t *n_out);
 
 /* ---- groups: many independent fields in one launch per stage ---- */
 
-/* A group sends one frame of each of its members to the device together:
+/* (The paper runs one sequence at a time, Sec. 4; a group runs the same
+ * per-frame procedure of Sec. 3.1-3.2.4 on the frames of several sequences.)
+ * A group sends one frame of each of its members to the device together:
  * every stage is one launch over all members' frames, whatever their lattice
  * sizes (a flat work list of tiles).  Members are contexts made by dv_create
  * with the same device and the same hip_stream; each keeps its own past,
@@ -223,12 +272,19 @@ dv_status dv_group_push(dv_group *g, const float *const *fields_device);
 dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *const *fields_device,
                              int32_t n);
 
-/* Release the group (not its members).  NULL is accepted. */
+/* Release the group (not its members, whose state of Sec. 3.2.3 stays).
+ * NULL is accepted. */
 void dv_group_destroy(dv_group *g);
 
 /* ---- measurement ---- */
 
-/* Stages of the per-frame procedure, in launch order. */
+/* Stages of the per-frame procedure, in launch order: threshold and cluster
+ * labelling (Sec. 3.1) in tile_ccl, merge, resolve, relabel; centres and the
+ * centre grid (Sec. 3.1) in finalize; colouring and neighbour rules (Sec.
+ * 3.2.1-3.2.2) in owner_edges; compressed rows (Sec. 3.2.2) in rows;
+ * isomorphism (Sec. 3.2.3) in match; row comparison and flips (Sec.
+ * 3.2.3-3.2.4) in diff and place; event classification (Sec. 3.2.4) in
+ * events. */
 #define DV_N_STAGES 11
 /* Bracket every launch of one stage with HIP events on the context's stream
  * (one launch covers every frame of a batch).
@@ -239,12 +295,14 @@ dv_status dv_set_profile(dv_ctx *ctx, int32_t stage, int32_t capacity);
 /* Wait for the device; *total_ms = summed event time of the recorded
  * launches, *launches = their number; clears the record. */
 dv_status dv_get_profile(dv_ctx *ctx, double *total_ms, int32_t *launches);
-/* Name of a stage ("tile_ccl", "owner_edges", ...); NULL when out of range. */
+/* Name of a stage of the list above ("tile_ccl", "owner_edges", ...); NULL
+ * when out of range. */
 const char *dv_stage_name(int32_t stage);
 
+/* Text of a status code (errors of the calls above). */
 const char *dv_status_str(dv_status s);
 /* Text of the last error on this context ("" when none).  NULL ctx: text of
- * the last dv_create failure in this process. */
+ * the last dv_create failure of the calling thread. */
 const char *dv_last_error(const dv_ctx *ctx);
 
 #ifdef __cplusplus

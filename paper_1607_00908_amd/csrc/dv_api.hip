@@ -15,11 +15,30 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "dv.h"
 #include "dv_internal.h"
+
+// Completion event of one launch, shared by the contexts whose frames it
+// carried (a group launch serves several).
+struct LaunchEv {
+    hipEvent_t e = nullptr;
+    ~LaunchEv() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+using EvRef = std::shared_ptr<LaunchEv>;
+
+// Frames [.., end) of results page `page` are complete when `ev` is.
+struct PageLaunch {
+    EvRef ev;
+    int page;
+    int end;
+};
 
 struct dv_ctx {
     dv_config cfg;
@@ -32,7 +51,7 @@ struct dv_ctx {
     Fields pending;          // queued field pointers
     int npending;
     int last;                // slot of the most recent frame sent to the device
-    std::vector<void *> allocs;
+    void *region;            // every device buffer of the context (one allocation)
     SeqState *h_state;       // pinned mirrors of the headers
     FrameState *h_frame;
     int32_t *d_edge_scratch; // [2 * K_max] for the couple-list getter
@@ -42,6 +61,24 @@ struct dv_ctx {
     bool pushed;
     Prof prof;
     std::string err;
+    // results pages: page p holds the records of up to pg_cap frames in
+    // pinned host memory (written by the device) and their flips in device
+    // memory.  Frames fill the current page in push order; when the next
+    // launch does not fit, the other page is emptied and becomes current.
+    bool keep_results;         // DV_KEEP_RESULTS: no frame is dropped unread
+    int pg_cap;                // frames per page: max(batch, 8)
+    FrameOut *h_pg[2];         // host view of the records
+    int32_t *d_pgf[2];         // flips of each page
+    int cur_pg;
+    int pg_n[2];               // frames placed in each page
+    int pg_rd[2];              // frames of each page returned by dv_get_results
+    int last_pg, last_pos;     // record of the most recent frame
+    std::deque<PageLaunch> inflight;  // launches with unread frames, oldest first
+    // results moved to host memory before their page was reused, unread
+    std::vector<dv_frame_info> sp_info;
+    std::vector<dv_flip> sp_flips;
+    size_t sp_head_info, sp_head_flips;
+    hipStream_t copy_stream;   // device-to-host copies of completed results
 };
 
 namespace {
@@ -54,14 +91,15 @@ dv_status fail(dv_ctx *c, dv_status s, const std::string &msg) {
     return s;
 }
 
-template <class T>
-bool dalloc(dv_ctx *c, T **p, size_t count) {
-    void *q = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
-    c->allocs.push_back(q);
-    *p = static_cast<T *>(q);
-    return true;
+void place_comp(Carve &cv, CompBuf &C, size_t K, int maxdeg) {
+    C.qx = cv.take<int32_t>(K);
+    C.qy = cv.take<int32_t>(K);
+    C.fx = cv.take<double>(K);
+    C.fy = cv.take<double>(K);
+    C.n = cv.take<int32_t>(K);
+    C.root = cv.take<int32_t>(K);
+    C.amb = cv.take<int32_t>(K);
+    C.adj = cv.take<int32_t>(K * maxdeg);
 }
 
 void drop_events(dv_ctx *c) {
@@ -70,6 +108,114 @@ void drop_events(dv_ctx *c) {
         delete[] c->prof.ev;
     }
     c->prof = Prof();
+}
+
+dv_status device_fail(dv_ctx *c, const char *what, hipError_t e) {
+    return fail(c, DV_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+dv_frame_info to_info(const FrameOut &r) {
+    dv_frame_info fi;
+    std::memset(&fi, 0, sizeof(fi));
+    fi.frame = r.frame;
+    fi.status = r.status;
+    fi.n_components = r.K;
+    fi.n_edges = r.status == 0 ? r.E : 0;
+    fi.n_flips = r.n_flips;
+    fi.n_breaking = r.n_break;
+    fi.n_excluded_past = r.excl_past;
+    fi.n_excluded_now = r.excl_now;
+    fi.n_ambiguous_centroids = r.amb;
+    fi.global_trigger = (uint32_t)r.trigger;
+    return fi;
+}
+
+// Records and flips of frames [a, b) of page p (their launches complete) into
+// host memory; the page's flips of consecutive frames are contiguous.
+dv_status read_frames(dv_ctx *c, int p, int a, int b, dv_frame_info *info, dv_flip *flips, int *nfl) {
+    const FrameOut *R = c->h_pg[p];
+    const int f0 = R[a].flip_off;
+    int f = f0;
+    for (int i = a; i < b; ++i) {
+        if (R[i].flip_off != f || R[i].n_flips < 0)
+            return fail(c, DV_ERR_INTERNAL, "results page records are inconsistent");
+        f += R[i].n_flips;
+        info[i - a] = to_info(R[i]);
+    }
+    *nfl = f - f0;
+    if (f > f0) {
+        hipError_t e = hipMemcpyAsync(flips, c->d_pgf[p] + (size_t)6 * f0, (size_t)(f - f0) * sizeof(dv_flip),
+                                      hipMemcpyDeviceToHost, c->copy_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->copy_stream);
+        if (e != hipSuccess) return device_fail(c, "results copy failed", e);
+    }
+    return DV_OK;
+}
+
+// Move the unread frames of page p to host memory (waits for their launches).
+dv_status spill(dv_ctx *c, int p) {
+    for (auto it = c->inflight.rbegin(); it != c->inflight.rend(); ++it)
+        if (it->page == p) {
+            const hipError_t e = hipEventSynchronize(it->ev->e);
+            if (e != hipSuccess) return device_fail(c, "results wait failed", e);
+            break;   // stream order: the page's earlier launches are complete too
+        }
+    const int a = c->pg_rd[p], b = c->pg_n[p];
+    if (b > a) {
+        const FrameOut *R = c->h_pg[p];
+        const int nf = R[b - 1].flip_off + R[b - 1].n_flips - R[a].flip_off;
+        const size_t i0 = c->sp_info.size(), f0 = c->sp_flips.size();
+        c->sp_info.resize(i0 + (b - a));
+        c->sp_flips.resize(f0 + (size_t)std::max(nf, 0));
+        int got = 0;
+        dv_status s = read_frames(c, p, a, b, c->sp_info.data() + i0, c->sp_flips.data() + f0, &got);
+        if (s != DV_OK) return s;
+    }
+    c->pg_rd[p] = b;
+    return DV_OK;
+}
+
+// Page position of the next k frames of c (k <= pg_cap): the current page, or
+// the other one emptied when they do not fit.  Returns the position word of
+// the first frame (DV_PG_*); the others follow it.
+dv_status take_page(dv_ctx *c, int k, uint32_t *ps0) {
+    int p = c->cur_pg;
+    bool fresh = c->pg_n[p] == 0;
+    if (c->pg_n[p] + k > c->pg_cap) {
+        const int o = 1 - p;
+        if (c->keep_results && c->pg_rd[o] < c->pg_n[o]) {
+            dv_status s = spill(c, o);
+            if (s != DV_OK) return s;
+        }
+        for (auto it = c->inflight.begin(); it != c->inflight.end();)
+            it = it->page == o ? c->inflight.erase(it) : it + 1;
+        p = o;
+        c->cur_pg = o;
+        c->pg_n[o] = 0;
+        c->pg_rd[o] = 0;
+        fresh = true;
+    }
+    *ps0 = (uint32_t)c->pg_n[p] | ((uint32_t)p << 6) | (fresh ? 128u : 0u);
+    return DV_OK;
+}
+
+// After a launch that placed k frames of c in its current page.
+void note_launch(dv_ctx *c, int k, const EvRef &ev) {
+    const int p = c->cur_pg;
+    c->last_pg = p;
+    c->last_pos = c->pg_n[p] + k - 1;
+    c->pg_n[p] += k;
+    if (c->keep_results) c->inflight.push_back(PageLaunch{ev, p, c->pg_n[p]});
+}
+
+// Completion event of a launch just enqueued on stream s.
+dv_status record_launch(dv_ctx *c, hipStream_t s, EvRef *out) {
+    auto ev = std::make_shared<LaunchEv>();
+    hipError_t e = hipEventCreateWithFlags(&ev->e, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev->e, s);
+    if (e != hipSuccess) return device_fail(c, "event record failed", e);
+    *out = ev;
+    return DV_OK;
 }
 
 // send the queued frames to the device
@@ -81,7 +227,11 @@ dv_status flush(dv_ctx *c) {
     std::memset(&G, 0, sizeof(G));
     G.D = c->d_tab;
     G.n = n;
+    uint32_t ps0 = 0;
+    dv_status ts = take_page(c, n, &ps0);
+    if (ts != DV_OK) return ts;
     for (int i = 0; i < n; ++i) G.idx[i] = i;
+    for (int i = 0; i < n; ++i) G.pslot[i] = ps0 + (uint32_t)i;
     for (int i = 0; i <= n; ++i) {
         G.tbase[i] = i * H.ncells;
         G.bbase[i] = i * H.nty;
@@ -101,6 +251,12 @@ dv_status flush(dv_ctx *c) {
     c->last = n - 1;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    EvRef ev;
+    if (c->keep_results) {
+        dv_status rs = record_launch(c, c->stream, &ev);
+        if (rs != DV_OK) return rs;
+    }
+    note_launch(c, n, ev);
     return DV_OK;
 }
 
@@ -116,12 +272,19 @@ void release(dv_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_events(c);
-    for (void *p : c->allocs) (void)hipFree(p);
-    c->allocs.clear();
+    if (c->region) (void)hipFree(c->region);
+    c->region = nullptr;
     if (c->h_state) (void)hipHostFree(c->h_state);
     if (c->h_frame) (void)hipHostFree(c->h_frame);
     c->h_state = nullptr;
     c->h_frame = nullptr;
+    c->inflight.clear();
+    for (int p = 0; p < 2; ++p) {
+        if (c->h_pg[p]) (void)hipHostFree(c->h_pg[p]);
+        c->h_pg[p] = nullptr;
+    }
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    c->copy_stream = nullptr;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
 }
@@ -142,7 +305,7 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->max_degree != 0 && (cfg->max_degree < 4 || cfg->max_degree > 64))
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
-    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y))
+    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y | DV_KEEP_RESULTS))
         return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
         return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 64]");
@@ -174,6 +337,81 @@ dv_status ready(dv_ctx *c) {
 
 }  // namespace
 
+dv_status check_config(const dv_config *cfg) { return check_cfg(cfg); }
+
+dv_status fail_global(dv_status s, const char *msg) { return fail(nullptr, s, msg); }
+
+Bufs table_base(const dv_config &cfg) {
+    Bufs B;
+    std::memset(&B, 0, sizeof(B));
+    B.lx = cfg.lx;
+    B.ly = cfg.ly;
+    B.ntx = (B.lx + DV_TILE - 1) / DV_TILE;
+    B.nty = (B.ly + DV_TILE - 1) / DV_TILE;
+    B.thr = cfg.threshold;
+    B.phase = cfg.phase;
+    B.conn = cfg.connectivity;
+    B.kmax = cfg.max_components;
+    B.maxdeg = cfg.max_degree;
+    B.ncells = B.ntx * B.nty;
+    B.keep_maps = (cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
+    B.classify = (cfg.flags & DV_CLASSIFY) ? 1 : 0;
+    B.open_x = (cfg.flags & DV_OPEN_X) ? 1 : 0;
+    B.open_y = (cfg.flags & DV_OPEN_Y) ? 1 : 0;
+    return B;
+}
+
+void place_slot(Carve &cv, Bufs &b) {
+    const size_t N = (size_t)b.lx * b.ly, tiles = (size_t)b.ncells, K = (size_t)b.kmax;
+    const size_t segs = (size_t)b.ly * b.ntx;
+    b.parent = cv.take<int32_t>(N);
+    b.lab16 = cv.take<uint16_t>(tiles * DV_TILE_SITES);
+    b.pieces = cv.take<uint16_t>(tiles * DV_TILE_SITES);
+    b.npieces = cv.take<int32_t>(tiles);
+    b.seg_mask = cv.take<uint32_t>(segs);
+    b.seg_prefix = cv.take<int32_t>(segs);
+    b.band_sum = cv.take<int32_t>(b.nty);
+    b.acc_x = cv.take<long long>(K);
+    b.acc_y = cv.take<long long>(K);
+    b.acc_n = cv.take<int32_t>(K);
+    b.acc_amb = cv.take<int32_t>(K);
+    b.acc_root = cv.take<int32_t>(K);
+    b.cell_count = cv.take<int32_t>(tiles);
+    b.cell_start = cv.take<int32_t>(tiles + 1);
+    b.cell_items = cv.take<int32_t>(K);
+    b.cell_q = cv.take<int2>(K);
+    b.comp_cell = cv.take<int32_t>(K);
+    b.comp_slot = cv.take<int32_t>(K);
+    b.tpairs = cv.take<int2>(tiles * DV_TILE_PAIRS);
+    b.tpair_n = cv.take<int32_t>(tiles);
+    b.cnt = cv.take<int32_t>(K);
+    b.inv = cv.take<int32_t>(K);
+    b.fs = cv.take<FrameState>(1);
+    place_comp(cv, b.cur, K, b.maxdeg);
+    b.phi = cv.take<int32_t>(K);
+    b.trigger = cv.take<int32_t>(K);
+    b.nb = cv.take<int32_t>(K);
+    b.na = cv.take<int32_t>(K);
+    b.ob = cv.take<int32_t>(K);
+    b.oa = cv.take<int32_t>(K);
+    b.act = cv.take<int32_t>(K);
+    b.ecnt = cv.take<int32_t>(K);
+    b.ebnd = cv.take<int32_t>(K);
+    b.stage = cv.take<int32_t>(K * b.maxdeg * 12);
+    b.labels = b.keep_maps ? cv.take<int32_t>(N) : nullptr;
+    b.owner = b.keep_maps ? cv.take<int32_t>(N) : nullptr;
+}
+
+void place_shared(Carve &cv, Bufs &B, int page_frames) {
+    const size_t K = (size_t)B.kmax;
+    B.st = cv.take<SeqState>(1);
+    place_comp(cv, B.past[0], K, B.maxdeg);
+    place_comp(cv, B.past[1], K, B.maxdeg);
+    // a frame has at most K_max * max_degree flips (breaking ones are couples of
+    // the past rows, arising ones of the now rows, each row holding max_degree)
+    for (int p = 0; p < 2; ++p) B.pg_flips[p] = cv.take<int32_t>((size_t)page_frames * K * B.maxdeg * 6);
+}
+
 extern "C" {
 
 dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
@@ -201,6 +439,16 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     c->h_frame = nullptr;
     c->d_tab = nullptr;
     c->d_obst = nullptr;
+    c->region = nullptr;
+    c->keep_results = (c->cfg.flags & DV_KEEP_RESULTS) != 0;
+    c->pg_cap = std::max(c->batch, 8);
+    c->h_pg[0] = c->h_pg[1] = nullptr;
+    c->d_pgf[0] = c->d_pgf[1] = nullptr;
+    c->cur_pg = 0;
+    c->pg_n[0] = c->pg_n[1] = c->pg_rd[0] = c->pg_rd[1] = 0;
+    c->last_pg = c->last_pos = 0;
+    c->sp_head_info = c->sp_head_flips = 0;
+    c->copy_stream = nullptr;
     if (hipSetDevice(c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, DV_ERR_DEVICE, "hipSetDevice failed");
@@ -217,59 +465,47 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     }
 
     // shared part of the slot table
-    Bufs B;
-    std::memset(&B, 0, sizeof(B));
-    B.lx = c->cfg.lx;
-    B.ly = c->cfg.ly;
-    B.ntx = (B.lx + DV_TILE - 1) / DV_TILE;
-    B.nty = (B.ly + DV_TILE - 1) / DV_TILE;
-    B.thr = c->cfg.threshold;
-    B.phase = c->cfg.phase;
-    B.conn = c->cfg.connectivity;
-    B.kmax = c->cfg.max_components;
-    B.maxdeg = c->cfg.max_degree;
-    B.ncells = B.ntx * B.nty;
-    B.keep_maps = (c->cfg.flags & DV_KEEP_MAPS) ? 1 : 0;
-    B.classify = (c->cfg.flags & DV_CLASSIFY) ? 1 : 0;
-    B.open_x = (c->cfg.flags & DV_OPEN_X) ? 1 : 0;
-    B.open_y = (c->cfg.flags & DV_OPEN_Y) ? 1 : 0;
-    const size_t N = (size_t)B.lx * B.ly, tiles = (size_t)B.ncells, K = (size_t)B.kmax;
-    const size_t segs = (size_t)B.ly * B.ntx;
-    auto comp_alloc = [&](CompBuf &C) {
-        return dalloc(c, &C.qx, K) && dalloc(c, &C.qy, K) && dalloc(c, &C.fx, K) &&
-               dalloc(c, &C.fy, K) && dalloc(c, &C.n, K) && dalloc(c, &C.root, K) &&
-               dalloc(c, &C.amb, K) && dalloc(c, &C.adj, K * B.maxdeg);
-    };
-    bool ok = dalloc(c, &B.st, 1) && comp_alloc(B.past[0]) && comp_alloc(B.past[1]) &&
-              dalloc(c, &c->d_tab, DV_MAX_BATCH) && dalloc(c, &c->d_edge_scratch, 2 * K) &&
-              dalloc(c, &c->d_edge_ab, K * B.maxdeg) && dalloc(c, &c->d_edge_total, 1);
+    Bufs B = table_base(c->cfg);
+    const size_t N = (size_t)B.lx * B.ly, K = (size_t)B.kmax;
+    // every device buffer in one region: measured first, then placed
     uint8_t *obst = nullptr;   // one mask for every slot (no obstacle until set)
-    if (ok && (c->cfg.flags & DV_OBSTACLES)) {
-        ok = dalloc(c, &obst, N);
+    auto layout = [&](Carve &cv) {
+        place_shared(cv, B, c->pg_cap);
+        c->d_tab = cv.take<Bufs>(DV_MAX_BATCH);
+        c->d_edge_scratch = cv.take<int32_t>(2 * K);
+        c->d_edge_ab = cv.take<int32_t>(K * B.maxdeg);
+        c->d_edge_total = cv.take<int32_t>(1);
+        obst = (c->cfg.flags & DV_OBSTACLES) ? cv.take<uint8_t>(N) : nullptr;
         B.obst = obst;
         c->d_obst = obst;
+        for (int k = 0; k < c->batch; ++k) {
+            c->h_tab[k] = B;
+            place_slot(cv, c->h_tab[k]);
+        }
+    };
+    Carve measure;
+    layout(measure);
+    bool ok = hipMalloc(&c->region, measure.off) == hipSuccess;
+    if (ok) {
+        Carve cv;
+        cv.base = static_cast<char *>(c->region);
+        layout(cv);
     }
-    // per-slot buffers
+    // results-page records: pinned host memory that the device writes
+    for (int p = 0; ok && p < 2; ++p) {
+        ok = hipHostMalloc((void **)&c->h_pg[p], sizeof(FrameOut) * DV_MAX_BATCH,
+                           hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+             hipHostGetDevicePointer((void **)&B.pg_info[p], c->h_pg[p], 0) == hipSuccess;
+        if (ok) {
+            std::memset(c->h_pg[p], 0, sizeof(FrameOut) * DV_MAX_BATCH);
+            c->d_pgf[p] = B.pg_flips[p];
+        }
+    }
     for (int k = 0; ok && k < c->batch; ++k) {
-        Bufs &b = c->h_tab[k];
-        b = B;
-        ok = dalloc(c, &b.parent, N) && dalloc(c, &b.lab16, tiles * DV_TILE_SITES) &&
-             dalloc(c, &b.pieces, tiles * DV_TILE_SITES) && dalloc(c, &b.npieces, tiles) &&
-             dalloc(c, &b.seg_mask, segs) && dalloc(c, &b.seg_prefix, segs) &&
-             dalloc(c, &b.band_sum, (size_t)B.nty) && dalloc(c, &b.acc_x, K) &&
-             dalloc(c, &b.acc_y, K) && dalloc(c, &b.acc_n, K) && dalloc(c, &b.acc_amb, K) &&
-             dalloc(c, &b.acc_root, K) && dalloc(c, &b.cell_count, tiles) &&
-             dalloc(c, &b.cell_start, tiles + 1) && dalloc(c, &b.cell_items, K) &&
-             dalloc(c, &b.cell_q, K) && dalloc(c, &b.comp_cell, K) && dalloc(c, &b.comp_slot, K) &&
-             dalloc(c, &b.tpairs, tiles * DV_TILE_PAIRS) && dalloc(c, &b.tpair_n, tiles) &&
-             dalloc(c, &b.cnt, K) && dalloc(c, &b.inv, K) && dalloc(c, &b.fs, 1) &&
-             comp_alloc(b.cur) && dalloc(c, &b.phi, K) && dalloc(c, &b.trigger, K) &&
-             dalloc(c, &b.nb, K) && dalloc(c, &b.na, K) && dalloc(c, &b.ob, K) &&
-             dalloc(c, &b.oa, K) && dalloc(c, &b.flips, K * B.maxdeg * 6) &&
-             dalloc(c, &b.act, K) && dalloc(c, &b.ecnt, K) && dalloc(c, &b.ebnd, K) &&
-             dalloc(c, &b.stage, K * B.maxdeg * 12);
-        if (ok && B.keep_maps) ok = dalloc(c, &b.labels, N) && dalloc(c, &b.owner, N);
+        c->h_tab[k].pg_info[0] = B.pg_info[0];
+        c->h_tab[k].pg_info[1] = B.pg_info[1];
     }
+    if (ok) ok = hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok && (hipHostMalloc((void **)&c->h_state, sizeof(SeqState)) != hipSuccess ||
                hipHostMalloc((void **)&c->h_frame, sizeof(FrameState)) != hipSuccess))
         ok = false;
@@ -367,14 +603,137 @@ dv_status dv_get_flips(dv_ctx *c, dv_flip *host_out, int32_t capacity, int32_t *
     if (!c || !n_out || capacity < 0) return DV_ERR_ARG;
     dv_status s = ready(c);
     if (s != DV_OK) return s;
-    const int n = c->h_frame->n_flips;
+    const FrameOut &r = c->h_pg[c->last_pg][c->last_pos];
+    const int n = r.n_flips;
     *n_out = n;
     if (n > capacity) return fail(c, DV_ERR_CAPACITY, "flip buffer too small");
     if (n > 0) {
         if (!host_out) return fail(c, DV_ERR_ARG, "host_out is NULL");
-        if (hipMemcpy(host_out, c->h_tab[c->last].flips, (size_t)n * sizeof(dv_flip), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(host_out, c->d_pgf[c->last_pg] + (size_t)6 * r.flip_off, (size_t)n * sizeof(dv_flip),
+                      hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, DV_ERR_DEVICE, "copy failed");
     }
+    return DV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Unread frames whose launches are complete (all of them after a drain):
+// the spilled ones, then those of the older page, then the current page's.
+struct Avail {
+    int spill;           // frames in the spill store
+    int pages[2];        // page order: older first
+    int end[2];          // readable end of each page (frames [pg_rd, end))
+};
+
+Avail available(dv_ctx *c, bool all_done) {
+    Avail a;
+    a.spill = (int)(c->sp_info.size() - c->sp_head_info);
+    a.pages[0] = 1 - c->cur_pg;
+    a.pages[1] = c->cur_pg;
+    a.end[0] = a.end[1] = 0;
+    int done[2] = {c->pg_rd[0], c->pg_rd[1]};
+    if (all_done) {
+        done[0] = c->pg_n[0];
+        done[1] = c->pg_n[1];
+    } else {
+        for (const PageLaunch &L : c->inflight) {
+            if (hipEventQuery(L.ev->e) != hipSuccess) break;   // later launches are later on the stream
+            done[L.page] = std::max(done[L.page], L.end);
+        }
+    }
+    for (int k = 0; k < 2; ++k) a.end[k] = std::max(done[a.pages[k]], c->pg_rd[a.pages[k]]);
+    return a;
+}
+
+dv_status results_prologue(dv_ctx *c, int32_t wait) {
+    if (!c->keep_results) return fail(c, DV_ERR_STATE, "context made without DV_KEEP_RESULTS");
+    (void)hipSetDevice(c->device);
+    if (wait) return drain(c);
+    return DV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dv_status dv_results_ready(dv_ctx *c, int32_t wait, int32_t *n_frames, int32_t *n_flips) {
+    if (!c || !n_frames || !n_flips) return DV_ERR_ARG;
+    dv_status s = results_prologue(c, wait);
+    if (s != DV_OK) return s;
+    const Avail a = available(c, wait != 0);
+    long long nf = a.spill, nfl = (long long)(c->sp_flips.size() - c->sp_head_flips);
+    for (int k = 0; k < 2; ++k) {
+        const int p = a.pages[k];
+        for (int i = c->pg_rd[p]; i < a.end[k]; ++i) nfl += c->h_pg[p][i].n_flips;
+        nf += a.end[k] - c->pg_rd[p];
+    }
+    if (nfl > INT32_MAX) return fail(c, DV_ERR_CAPACITY, "more than 2^31 flips unread");
+    *n_frames = (int32_t)nf;
+    *n_flips = (int32_t)nfl;
+    return DV_OK;
+}
+
+dv_status dv_get_results(dv_ctx *c, int32_t wait, dv_frame_info *infos, int32_t cap_frames,
+                         int32_t *n_frames, dv_flip *flips, int32_t cap_flips, int32_t *n_flips) {
+    if (!c || !n_frames || !n_flips || cap_frames < 0 || cap_flips < 0) return DV_ERR_ARG;
+    if ((cap_frames > 0 && !infos) || (cap_flips > 0 && !flips)) return DV_ERR_ARG;
+    *n_frames = 0;
+    *n_flips = 0;
+    dv_status s = results_prologue(c, wait);
+    if (s != DV_OK) return s;
+    const Avail a = available(c, wait != 0);
+    int nf = 0, nfl = 0;
+    bool all = true;
+    // spilled frames first (oldest)
+    while (c->sp_head_info < c->sp_info.size()) {
+        const dv_frame_info &fi = c->sp_info[c->sp_head_info];
+        if (nf + 1 > cap_frames || (long long)nfl + fi.n_flips > cap_flips) {
+            all = false;
+            break;
+        }
+        infos[nf++] = fi;
+        if (fi.n_flips > 0)
+            std::memcpy(flips + nfl, c->sp_flips.data() + c->sp_head_flips, (size_t)fi.n_flips * sizeof(dv_flip));
+        nfl += fi.n_flips;
+        c->sp_head_flips += fi.n_flips;
+        ++c->sp_head_info;
+    }
+    if (c->sp_head_info == c->sp_info.size()) {
+        c->sp_info.clear();
+        c->sp_flips.clear();
+        c->sp_head_info = c->sp_head_flips = 0;
+    }
+    for (int k = 0; all && k < 2; ++k) {
+        const int p = a.pages[k];
+        const int a0 = c->pg_rd[p];
+        int b = a0, add = 0;
+        while (b < a.end[k]) {
+            const int f = c->h_pg[p][b].n_flips;
+            if (nf + (b - a0) + 1 > cap_frames || (long long)nfl + add + f > cap_flips) {
+                all = false;
+                break;
+            }
+            add += f;
+            ++b;
+        }
+        if (b > a0) {
+            int got = 0;
+            s = read_frames(c, p, a0, b, infos + nf, flips + nfl, &got);
+            if (s != DV_OK) return s;
+            nf += b - a0;
+            nfl += got;
+            c->pg_rd[p] = b;
+        }
+    }
+    // launches whose frames have all been read
+    while (!c->inflight.empty() && c->inflight.front().end <= c->pg_rd[c->inflight.front().page])
+        c->inflight.pop_front();
+    *n_frames = nf;
+    *n_flips = nfl;
+    if (!all) return fail(c, DV_ERR_CAPACITY, "result buffers too small for every ready frame");
     return DV_OK;
 }
 
@@ -582,10 +941,13 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
     G.D = g->d_tab;
     G.n = n;
     bool alike = true;
+    bool keep = false;
     for (int i = 0; i < n; ++i) {
         const int k = members[i];
         dv_status s = flush(g->m[k]);
+        if (s == DV_OK) s = take_page(g->m[k], 1, &G.pslot[i]);
         if (s != DV_OK) return s;
+        keep = keep || g->m[k]->keep_results;
         const Bufs &b = g->h_tab[k];
         F.p[i] = fields[i];
         G.idx[i] = k;
@@ -605,13 +967,18 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
     launch_voronoi(G, g->stream, g->prof);
     launch_compare(G, g->stream, g->prof);
     const hipError_t e = hipGetLastError();
+    EvRef ev;
+    dv_status rs = DV_OK;
+    if (e == hipSuccess && keep) rs = record_launch(g->m[members[0]], g->stream, &ev);
     for (int i = 0; i < n; ++i) {
         dv_ctx *c = g->m[members[i]];
         c->last = 0;
         c->pushed = true;
         if (e != hipSuccess) fail(c, DV_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+        else note_launch(c, 1, ev);
     }
-    return e == hipSuccess ? DV_OK : DV_ERR_DEVICE;
+    if (e != hipSuccess) return DV_ERR_DEVICE;
+    return rs;
 }
 
 dv_status dv_group_push(dv_group *g, const float *const *fields) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dv.h"
+
 #define DV_TILE 32                 // tile edge in sites (labelling, colouring)
 #define DV_TILE_SITES (DV_TILE * DV_TILE)
 #define DV_BLOCK 256               // threads per tile workgroup
@@ -38,7 +40,23 @@ struct FrameState {
     int32_t global_trigger;
     int32_t K_past;        // K of the past frame it was compared with (0: none)
     int32_t E_now;         // undirected couples of the frame
+    int32_t nb_acc;        // breaking couples found by the row comparison
+    int32_t na_acc;        // arising couples found by the row comparison
     int32_t pad;
+};
+
+// Result record of one frame in a results page: written by the device into
+// pinned host memory, read by the host once the launch has completed.
+struct FrameOut {
+    long long frame;       // accepted frames of the sequence up to and including this one
+    int32_t status;        // 0 accepted, else DV_ERR_CAPACITY
+    int32_t K, E;          // components (raw when rejected), undirected couples
+    int32_t n_flips, n_break;
+    int32_t excl_past, excl_now;
+    int32_t amb;           // components crossing their own antipodal line
+    int32_t trigger;       // global trigger
+    int32_t flip_off;      // first flip of the frame in the page's flip array
+    int32_t pad[3];
 };
 
 // Sequence header (device memory).  Two past buffers alternate: buffer `sel`
@@ -50,6 +68,7 @@ struct SeqState {
     int32_t K[2];          // components held by each past buffer
     int32_t E[2];          // undirected couples held by each past buffer
     int32_t done_place;    // blocks of k_place that have finished (last one commits)
+    int32_t pg_fill[2];    // flips held by each results page
     int32_t pad;
     int64_t frame;         // accepted frames
 };
@@ -111,14 +130,23 @@ struct Bufs {
     int32_t *nb, *na;      // [K_max] breaking / arising count per now row
     int32_t *ob, *oa;      // [K_max] their exclusive prefixes
     int32_t *stage;        // [K_max][2 * max_degree][6] flips of each row, row order
-    int32_t *flips;        // [K_max * max_degree][6]
     // event classification (when classify): per now label
     int32_t *act;          // [K_max] the row changed (an end of a flip)
     int32_t *ecnt;         // [K_max] active points connected in either graph
     int32_t *ebnd;         // [K_max] bit 0: boundary point of the now graph, bit 1: of the past
     CompBuf past[2];       // shared by the slots
     SeqState *st;          // shared by the slots
+    // results pages (shared by the slots): every frame's record and flips,
+    // kept until the host has read them
+    FrameOut *pg_info[2];  // [page frames] records, pinned host memory (device view)
+    int32_t *pg_flips[2];  // [page frames * K_max * max_degree][6] flips, device memory
 };
+
+// Results-page position of a launch entry: bits 0-5 the frame's record, bit 6
+// the page, bit 7 set when the page starts empty with this launch.
+#define DV_PG_POS(v) ((int)((v) & 63u))
+#define DV_PG_PAGE(v) ((int)(((v) >> 6) & 1u))
+#define DV_PG_FRESH(v) ((int)(((v) >> 7) & 1u))
 
 // Field pointers of the frames of one launch.
 struct Fields {
@@ -141,6 +169,7 @@ struct Batch {
     int classify;          // some entry classifies events
     int geom;              // some entry has walls or obstacles (general kernels)
     int idx[DV_MAX_ENTRIES];        // table row of each entry
+    uint32_t pslot[DV_MAX_ENTRIES]; // results-page position of each entry (DV_PG_*)
     int tbase[DV_MAX_ENTRIES + 1];  // first flat tile of each entry
     int bbase[DV_MAX_ENTRIES + 1];  // first flat band (32 rows) of each entry
 };
@@ -189,6 +218,34 @@ struct Prof {
         }
     }
 };
+
+// Bump placement of device buffers in one region, each piece 256-byte
+// aligned; with a null base it only measures the region.
+struct Carve {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += (count ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+// Buffers of one batch slot (one frame), and those shared by the slots of a
+// sequence (past components, sequence header, results-page flips of
+// page_frames frames each; the page records are placed by the caller).  B
+// must hold the lattice, K_max, max_degree, the tile counts and keep_maps.
+// (dv_api.hip)
+void place_slot(Carve &cv, Bufs &b);
+void place_shared(Carve &cv, Bufs &B, int page_frames);
+// Checks of a configuration done before any device work, and the error text
+// returned by dv_last_error(NULL) (dv_api.hip).
+dv_status check_config(const dv_config *cfg);
+dv_status fail_global(dv_status s, const char *msg);
+// Slot-table fields of a configuration (lattice, tiles, threshold, flags):
+// every pointer null (dv_api.hip).
+Bufs table_base(const dv_config &cfg);
 
 // Launchers (all on stream s).
 // k_label.hip

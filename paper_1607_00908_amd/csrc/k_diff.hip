@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch
 }
 
 __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch G) {
-    __shared__ int s_red[2][4];
+    __shared__ int s_red[4][4];
     const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[G.idx[i]];
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
     for (int q = i + 1; q < nb_frames; ++q)
         if (Dt[G.idx[q]].seq == B.seq && Dt[G.idx[q]].fs->err == 0) keep = false;
     const int D = B.maxdeg;
-    int e2 = 0, exn = 0;
+    int e2 = 0, exn = 0, tb = 0, ta = 0;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
     for (int n = blockIdx.x * (blockDim.x >> 6) + wid; n < KN; n += nwaves) {
         const int m = lane < D ? gmem(N.adj)[(size_t)n * D + lane] : DV_EMPTY;
@@ -158,26 +158,38 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
         if (lane == 0) {
             gmem(B.nb)[n] = cb;
             gmem(B.na)[n] = ca;
+            tb += cb;
+            ta += ca;
             if (B.classify) gmem(B.act)[n] = actv;
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         e2 += __shfl_down(e2, o, 64);
         exn += __shfl_down(exn, o, 64);
+        tb += __shfl_down(tb, o, 64);
+        ta += __shfl_down(ta, o, 64);
     }
     if (lane == 0) {
         s_red[0][wid] = e2;
         s_red[1][wid] = exn;
+        s_red[2][wid] = tb;
+        s_red[3][wid] = ta;
     }
     __syncthreads();
     if (t == 0) {
-        int a = 0, b = 0;
+        int a = 0, b = 0, c = 0, d = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
             a += s_red[0][w];
             b += s_red[1][w];
+            c += s_red[2][w];
+            d += s_red[3][w];
         }
         if (a) atomicAdd(&fs->E2_acc, a);
         if (b) atomicAdd(&fs->excl_acc, b);
+        // flip totals of the frame: the next launch places every frame's flips
+        // after those of the frames before it in the results page
+        if (c) atomicAdd(&fs->nb_acc, c);
+        if (d) atomicAdd(&fs->na_acc, d);
     }
 }
 
@@ -288,6 +300,21 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
     const int t = threadIdx.x;
+    // results page of the frame: the flips of the page before it are those
+    // the page held before the launch and those of the earlier frames of the
+    // same sequence in the launch (all of one sequence share one page)
+    const uint32_t ps = G.pslot[i];
+    const int pg = DV_PG_PAGE(ps);
+    const SeqState *sq0 = B.st;
+    int base = DV_PG_FRESH(ps) ? 0 : sq0->pg_fill[pg];
+    long long frame_no = sq0->frame;
+    for (int j = 0; j < i; ++j) {
+        const Bufs &Bj = Dt[G.idx[j]];
+        if (Bj.seq != B.seq || Bj.fs->err) continue;
+        base += Bj.fs->nb_acc + Bj.fs->na_acc;
+        ++frame_no;
+    }
+    int *const flips = B.pg_flips[pg] + (size_t)6 * base;
     if (fs->err) {
         if (t == 0) {
             fs->status = 2;   // DV_ERR_CAPACITY; the frame is not a past
@@ -300,6 +327,7 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
             fs->E_now = 0;
         }
     } else {
+        ++frame_no;
         const int KN = fs->K_now;
         const PastOf PO = past_of(Dt, G, i);
         const int D = B.maxdeg;
@@ -311,8 +339,8 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
             const int cb = B.nb[n], ca = B.na[n];
             if (cb == 0 && ca == 0) continue;
             const int *stg = B.stage + (size_t)n * (2 * D) * 6;
-            int *fb = B.flips + (size_t)6 * B.ob[n];
-            int *fa = B.flips + (size_t)6 * (nbk + B.oa[n]);
+            int *fb = flips + (size_t)6 * B.ob[n];
+            int *fa = flips + (size_t)6 * (nbk + B.oa[n]);
             // records are 24 bytes: copied as 8-byte words, loads issued together
             copy_words(reinterpret_cast<const int2 *>(stg), reinterpret_cast<int2 *>(fb), 3 * cb);
             copy_words(reinterpret_cast<const int2 *>(stg + 6 * D), reinterpret_cast<int2 *>(fa), 3 * ca);
@@ -334,6 +362,23 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
             fs->global_trigger = (nbk + nar) > 0 ? 1 : 0;
         }
     }
+    if (t == 0) {
+        // the frame's result record (host memory, read after the launch)
+        FrameOut r;
+        r.frame = frame_no;
+        r.status = fs->status;
+        r.K = fs->K_now;
+        r.E = fs->E_now;
+        r.n_flips = fs->n_flips;
+        r.n_break = fs->n_break;
+        r.excl_past = fs->n_excl_past;
+        r.excl_now = fs->n_excl_now;
+        r.amb = fs->n_amb;
+        r.trigger = fs->global_trigger;
+        r.flip_off = base;
+        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        B.pg_info[pg][DV_PG_POS(ps)] = r;
+    }
     // the last block to finish commits every sequence of the launch (every
     // block has read the sequence headers by now); the ticket is kept in the
     // first entry's header
@@ -354,11 +399,20 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
         for (int j = k + 1; j < nb_frames; ++j)
             if (Dt[G.idx[j]].seq == q) last = false;
         if (last) {
-            int a = -1, acc = 0;
-            for (int j = 0; j <= k; ++j)
-                if (Dt[G.idx[j]].seq == q && Dt[G.idx[j]].fs->err == 0) { a = j; ++acc; }
+            int a = -1, acc = 0, nfl = 0;
+            for (int j = 0; j <= k; ++j) {
+                const FrameState *fj = Dt[G.idx[j]].fs;
+                if (Dt[G.idx[j]].seq == q && fj->err == 0) {
+                    a = j;
+                    ++acc;
+                    nfl += fj->nb_acc + fj->na_acc;
+                }
+            }
+            SeqState *sq = Dt[G.idx[k]].st;
+            const uint32_t pk = G.pslot[k];
+            const int p = DV_PG_PAGE(pk);
+            sq->pg_fill[p] = (DV_PG_FRESH(pk) ? 0 : sq->pg_fill[p]) + nfl;
             if (a >= 0) {
-                SeqState *sq = Dt[G.idx[k]].st;
                 const int nxt = 1 - sq->sel;
                 sq->K[nxt] = Dt[G.idx[a]].fs->K_now;
                 sq->E[nxt] = Dt[G.idx[a]].fs->E2_acc / 2;

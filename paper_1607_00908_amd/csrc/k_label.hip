@@ -255,6 +255,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         fs->n_amb = 0;
         fs->E2_acc = 0;
         fs->excl_acc = 0;
+        fs->nb_acc = 0;
+        fs->na_acc = 0;
     }
     if (t == 0) {
         B.cell_count[tile] = 0;

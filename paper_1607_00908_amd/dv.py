@@ -25,6 +25,7 @@ CLASSIFY = 2
 OBSTACLES = 4
 OPEN_X = 8
 OPEN_Y = 16
+KEEP_RESULTS = 32
 FLIP_BULK, FLIP_BOUNDARY = 1, 2
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = range(7)
@@ -33,7 +34,7 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
            "dv_get_matching", "dv_set_obstacles", "dv_group_create", "dv_group_push", "dv_group_push_some",
-           "dv_group_destroy",
+           "dv_group_destroy", "dv_results_ready", "dv_get_results",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
 DEFAULT_BATCH = 32   # what max_batch = 0 selects
@@ -90,6 +91,10 @@ def load(path: str = LIB_PATH):
     lib.dv_get_flips.argtypes = [vp, vp, i32, i32p]
     lib.dv_get_info.restype = i32
     lib.dv_get_info.argtypes = [vp, ctypes.POINTER(DVFrameInfo)]
+    lib.dv_results_ready.restype = i32
+    lib.dv_results_ready.argtypes = [vp, i32, i32p, i32p]
+    lib.dv_get_results.restype = i32
+    lib.dv_get_results.argtypes = [vp, i32, vp, i32, i32p, vp, i32, i32p]
     lib.dv_sync.restype = i32
     lib.dv_sync.argtypes = [vp]
     lib.dv_destroy.restype = None
@@ -146,6 +151,12 @@ class FrameInfo:
     global_trigger: int
 
 
+def _frame_info(fi: DVFrameInfo) -> FrameInfo:
+    return FrameInfo(fi.frame, fi.status, fi.n_components, fi.n_edges, fi.n_flips,
+                     fi.n_breaking, fi.n_excluded_past, fi.n_excluded_now,
+                     fi.n_ambiguous_centroids, fi.global_trigger)
+
+
 class Detector:
     """One detection context (one sequence of frames) on one device.
 
@@ -155,7 +166,9 @@ class Detector:
     kernels start after it, so a field produced there is complete when they
     read it.  ``max_batch``: frames queued and sent to the device together
     (0: the library's default).  ``classify``: fill the flips' event flags
-    (FLIP_BULK, FLIP_BOUNDARY).  ``open_x`` / ``open_y``: walls across that
+    (FLIP_BULK, FLIP_BOUNDARY).  ``keep_results``: every frame's record and
+    flips are kept until ``results`` returns them (no frame of a batch is lost
+    unread).  ``open_x`` / ``open_y``: walls across that
     axis instead of the periodic wrap.  ``obstacles``: a [ly, lx] mask
     (nonzero = obstacle; numpy array or device tensor) set at creation; it can
     be replaced later with ``set_obstacles`` (the context then holds a mask
@@ -166,11 +179,12 @@ class Detector:
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
                  device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0,
                  classify: bool = False, open_x: bool = False, open_y: bool = False,
-                 obstacles=None, with_obstacles: bool = False):
+                 obstacles=None, with_obstacles: bool = False, keep_results: bool = False):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
         flags = ((KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0)
                  | (OPEN_X if open_x else 0) | (OPEN_Y if open_y else 0)
+                 | (KEEP_RESULTS if keep_results else 0)
                  | (OBSTACLES if (with_obstacles or obstacles is not None) else 0))
         cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
                        int(connectivity), int(max_components), int(max_degree), int(device),
@@ -276,9 +290,33 @@ class Detector:
         fi = DVFrameInfo()
         self._check(self.lib.dv_get_info(self.h, ctypes.byref(fi)), allow=(ERR_CAPACITY,))
         self._field_refs.clear()
-        return FrameInfo(fi.frame, fi.status, fi.n_components, fi.n_edges, fi.n_flips,
-                         fi.n_breaking, fi.n_excluded_past, fi.n_excluded_now,
-                         fi.n_ambiguous_centroids, fi.global_trigger)
+        return _frame_info(fi)
+
+    def results(self, wait: bool = True):
+        """Every unread frame, oldest first: a list of (FrameInfo, flips int32
+        [F, 6]).  ``wait``: send the queued frames and wait for all of them;
+        else only frames already complete on the device.  Needs
+        ``keep_results``."""
+        nf, nfl = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self.lib.dv_results_ready(self.h, int(bool(wait)), ctypes.byref(nf),
+                                              ctypes.byref(nfl)))
+        if wait:
+            self._field_refs.clear()
+        if nf.value == 0:
+            return []
+        infos = (DVFrameInfo * nf.value)()
+        flips = np.zeros((max(nfl.value, 1), 6), dtype=np.int32)
+        got_f, got_fl = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self.lib.dv_get_results(self.h, 0, infos, nf.value, ctypes.byref(got_f),
+                                            _ptr(flips), nfl.value, ctypes.byref(got_fl)),
+                    allow=(ERR_CAPACITY,))
+        out, o = [], 0
+        for k in range(got_f.value):
+            fi = _frame_info(infos[k])
+            out.append((fi, flips[o:o + fi.n_flips]))
+            o += fi.n_flips
+        assert o == got_fl.value
+        return out
 
     # -- measurement -----------------------------------------------------------
     def set_profile(self, stage, capacity: int = 4096):

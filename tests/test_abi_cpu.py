@@ -47,7 +47,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
     dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
-    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=32), dict(flags=0x80000000),
+    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=64), dict(flags=0x80000000),
     dict(max_batch=-1), dict(max_batch=65)])
 def test_invalid_config_is_rejected_on_the_host(bad):
     lib = dv.load()
@@ -73,6 +73,8 @@ def test_null_arguments():
     assert lib.dv_set_obstacles(None, None, 0) == dv.ERR_ARG
     n = ctypes.c_int32(0)
     assert lib.dv_get_flips(None, None, 0, ctypes.byref(n)) == dv.ERR_ARG
+    assert lib.dv_results_ready(None, 1, ctypes.byref(n), ctypes.byref(n)) == dv.ERR_ARG
+    assert lib.dv_get_results(None, 1, None, 0, ctypes.byref(n), None, 0, ctypes.byref(n)) == dv.ERR_ARG
     lib.dv_destroy(None)   # NULL-safe
     assert lib.dv_status_str(2) == b"capacity exceeded"
 

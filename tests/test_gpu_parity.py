@@ -66,6 +66,29 @@ def check_frame(det, now, ref, lx, ly, maps=True):
         assert len(phi) == 0
 
 
+def check_results(res, refs, tag=""):
+    """Every frame's record and flips from Detector.results() (push order)
+    against the oracle's (now, diff) of the same frame; a None entry in refs
+    skips the oracle comparison of that frame, whose record must still say
+    accepted.  Frames are numbered by the accepted frames up to them."""
+    assert len(res) == len(refs), (tag, len(res), len(refs))
+    for k, ((fi, fl), r) in enumerate(zip(res, refs)):
+        assert fi.status == 0, (tag, k, fi)
+        assert fi.frame == k + 1, (tag, k, fi.frame)
+        assert len(fl) == fi.n_flips
+        if r is None:
+            continue
+        now, ref = r
+        assert fi.n_components == now.K, (tag, k)
+        assert fi.n_edges == len(now.edges), (tag, k)
+        assert fi.n_ambiguous_centroids == int(now.comps["amb"].sum()), (tag, k)
+        assert np.array_equal(fl, ref.flips), (tag, k, "flips")
+        assert fi.n_breaking == int(np.sum(ref.flips[:, 4] == -1)), (tag, k)
+        assert fi.n_excluded_past == ref.excluded_past, (tag, k)
+        assert fi.n_excluded_now == ref.excluded_now, (tag, k)
+        assert fi.global_trigger == ref.global_trigger, (tag, k)
+
+
 def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag="",
                  classify=False, open_x=False, open_y=False, obstacles=None):
     ly, lx = fields[0].shape
@@ -73,15 +96,18 @@ def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=
         kmax = lx * ly
     det = dv.Detector(lx, ly, thr, phase, conn, max_components=kmax, max_degree=max_degree,
                       keep_maps=maps, classify=classify, open_x=open_x, open_y=open_y,
-                      obstacles=obstacles)
+                      obstacles=obstacles, keep_results=True)
     seq = oracle.Sequence(thr, phase, conn, NTHREADS, classify_events=classify,
                           obstacles=obstacles, open_x=open_x, open_y=open_y)
+    refs = []
     for i, f in enumerate(fields):
         say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase} open={int(open_x)}{int(open_y)}"
             f" obstacles={obstacles is not None}")
         det.push(torch.from_numpy(np.ascontiguousarray(f)).to("cuda"))
         now, ref = seq.push(f)
+        refs.append((now, ref))
         check_frame(det, now, ref, lx, ly, maps)
+    check_results(det.results(), refs, tag)
     det.close()
     return now
 
@@ -199,15 +225,75 @@ def test_batched_bursts_match_the_oracle(depth):
     n = max(11, 2 * depth + 3)
     frames = list(sim.frames(n))
     dev = [torch.from_numpy(f).cuda() for f in frames]
-    det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=depth)
+    det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=depth, keep_results=True)
     seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
+    refs = []
     for k, f in enumerate(frames):
         now, ref = seq.push(f)
+        refs.append((now, ref))
         det.push(dev[k])
         if k in (0, depth, n - 1):
             say(f"  [batch{depth}] burst ends at frame {k}")
             check_frame(det, now, ref, lx, ly)
     assert det.info().frame == len(frames)
+    # every frame's flips, also those inside a batch
+    check_results(det.results(), refs, f"batch{depth}")
+    det.close()
+
+
+@pytest.mark.parametrize("depth,collect_every", [(4, 3), (8, 5), (32, 7), (2, 1)])
+def test_results_collected_while_pushing(depth, collect_every):
+    """Results read with and without waiting while frames are still being
+    pushed (pages of unread frames reused, frames moved to host memory first):
+    together, every frame exactly once, in push order, equal to the oracle."""
+    lx, ly = 130, 110
+    sim = synth.DiskSim(lx, ly, 20, 4.0, 7.0, 0.6, 3e-3, seed=191 + depth)
+    n = 3 * depth + 5
+    frames = list(sim.frames(n))
+    dev = [torch.from_numpy(f).cuda() for f in frames]
+    det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=depth, keep_results=True)
+    seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
+    refs = [seq.push(f) for f in frames]
+    got = []
+    for k in range(n):
+        det.push(dev[k])
+        if k % collect_every == collect_every - 1:
+            got += det.results(wait=(k // collect_every) % 2 == 1)
+    got += det.results(wait=True)
+    assert det.results(wait=True) == []
+    check_results(got, refs, f"collect{depth}/{collect_every}")
+    det.close()
+
+
+def test_results_capacity_returns_whole_frames():
+    """Small result buffers: whole frames while they fit, the rest stays
+    unread for the next call."""
+    import ctypes
+    lx, ly = 120, 120
+    sim = synth.DiskSim(lx, ly, 24, 4.0, 7.0, 0.8, 4e-3, seed=5)
+    frames = list(sim.frames(9))
+    det = dv.Detector(lx, ly, 0.5, max_components=256, max_batch=4, keep_results=True)
+    for f in frames:
+        det.push(torch.from_numpy(f).cuda())
+    seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
+    refs = [seq.push(f) for f in frames]
+    nf, nfl = ctypes.c_int32(0), ctypes.c_int32(0)
+    assert det.lib.dv_results_ready(det.h, 1, ctypes.byref(nf), ctypes.byref(nfl)) == dv.OK
+    assert nf.value == 9 and nfl.value == sum(len(r.flips) for _, r in refs)
+    infos = (dv.DVFrameInfo * 2)()
+    fl = np.zeros((max(nfl.value, 1), 6), np.int32)
+    gf, gfl = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = det.lib.dv_get_results(det.h, 0, infos, 2, ctypes.byref(gf), fl.ctypes.data_as(ctypes.c_void_p),
+                                nfl.value, ctypes.byref(gfl))
+    assert st == dv.ERR_CAPACITY and gf.value == 2
+    assert gfl.value == len(refs[0][1].flips) + len(refs[1][1].flips)
+    first = [(dv._frame_info(infos[k]), None) for k in range(2)]
+    rest = det.results(wait=False)
+    assert len(rest) == 7
+    assert [fi.frame for fi, _ in first + rest] == list(range(1, 10))
+    for (fi, f), (now, ref) in zip(rest, refs[2:]):
+        assert fi.n_components == now.K
+        assert np.array_equal(f, ref.flips)
     det.close()
 
 
@@ -218,7 +304,7 @@ def test_rejection_inside_a_batch():
     a, b, c, d = list(sim.frames(4))
     noise = (synth.tiny_random_field(120, 100, 5) > 0.85).astype(np.float32)
     dev = [torch.from_numpy(x).cuda() for x in (a, b, noise, c)]
-    det = dv.Detector(120, 100, 0.5, max_components=64, max_batch=3)
+    det = dv.Detector(120, 100, 0.5, max_components=64, max_batch=3, keep_results=True)
     for x in dev:
         det.push(x)
     got = det.flips()
@@ -232,13 +318,25 @@ def test_rejection_inside_a_batch():
     det.push(dev[1])
     ref = oracle.compare(oracle.frame(d, 0.5), oracle.frame(b, 0.5))
     assert np.array_equal(det.flips(), ref.flips)
+    # every frame's record: the rejections are reported where they happened
+    res = det.results()
+    assert [fi.status for fi, _ in res] == [0, 0, dv.ERR_CAPACITY, 0, 0, dv.ERR_CAPACITY, 0]
+    assert [fi.frame for fi, _ in res] == [1, 2, 2, 3, 4, 4, 5]
+    fa, fb, fc, fd = (oracle.frame(x, 0.5) for x in (a, b, c, d))
+    want = [oracle.compare(None, fa), oracle.compare(fa, fb), None, oracle.compare(fb, fc),
+            oracle.compare(fc, fd), None, oracle.compare(fd, fb)]
+    for k, ((fi, fl), w) in enumerate(zip(res, want)):
+        if w is None:
+            assert len(fl) == 0 and fi.n_flips == 0
+        else:
+            assert np.array_equal(fl, w.flips), k
     det.close()
 
 
 def _group(sizes, kmax=512, max_batch=2):
     stream = torch.cuda.Stream()
-    dets = [dv.Detector(lx, ly, 0.5, max_components=kmax, max_batch=max_batch, stream=stream)
-            for lx, ly in sizes]
+    dets = [dv.Detector(lx, ly, 0.5, max_components=kmax, max_batch=max_batch, stream=stream,
+                        keep_results=True) for lx, ly in sizes]
     return dets, dv.Group(dets)
 
 
@@ -251,12 +349,16 @@ def test_group_of_uneven_lattices_matches_the_oracle():
     frames = [list(sm.frames(4)) for sm in sims]
     dets, grp = _group(sizes)
     seqs = [oracle.Sequence(0.5, 0, 8, NTHREADS) for _ in sizes]
+    refs = [[] for _ in sizes]
     for k in range(4):
         say(f"  [group] frame {k}")
         grp.push([torch.from_numpy(frames[i][k]).cuda() for i in range(len(sizes))])
         for i, (lx, ly) in enumerate(sizes):
             now, ref = seqs[i].push(frames[i][k])
+            refs[i].append((now, ref))
             check_frame(dets[i], now, ref, lx, ly)
+    for i in range(len(sizes)):
+        check_results(dets[i].results(), refs[i], f"group member {i}")
     grp.close()
     for d in dets:
         d.close()
@@ -301,10 +403,12 @@ def test_group_bursts_and_single_pushes_mix():
     for i, (lx, ly) in enumerate(sizes):
         order = [0, 1, 2, 3, 4, 5] if i == 1 else [0, 1, 2, 4, 5]
         seq = oracle.Sequence(0.5, 0, 8, NTHREADS)
-        for k in order:
-            now, ref = seq.push(frames[i][k])
+        refs = [seq.push(frames[i][k]) for k in order]
+        now, ref = refs[-1]
         check_frame(dets[i], now, ref, lx, ly)
         assert dets[i].info().frame == len(order)
+        # every frame of every member, group pushes and single pushes alike
+        check_results(dets[i].results(), refs, f"mix member {i}")
     grp.close()
     for d in dets:
         d.close()
@@ -320,6 +424,7 @@ def test_group_subsets_as_frames_arrive():
     frames = [list(sm.frames(5)) for sm in sims]
     dets, grp = _group(sizes, max_batch=1)
     seqs = [oracle.Sequence(0.5, 0, 8, NTHREADS) for _ in sizes]
+    refs = [[] for _ in sizes]
     nxt = [0] * len(sizes)
     schedule = [[0, 1, 2, 3], [2, 0], [3], [1, 3, 0], [0], [2, 1], [3, 2, 1], [1, 0]]
     for step, members in enumerate(schedule):
@@ -328,8 +433,11 @@ def test_group_subsets_as_frames_arrive():
         grp.push_some(members, [torch.from_numpy(frames[m][nxt[m]]).cuda() for m in members])
         for m in members:
             now, ref = seqs[m].push(frames[m][nxt[m]])
+            refs[m].append((now, ref))
             nxt[m] += 1
             check_frame(dets[m], now, ref, *sizes[m])
+    for m in range(len(sizes)):
+        check_results(dets[m].results(), refs[m], f"subset member {m}")
     grp.close()
     for d in dets:
         d.close()
@@ -395,13 +503,14 @@ def test_event_flags_disks1024_batched():
     frames = list(sim.frames(9))
     dev = torch.from_numpy(np.stack(frames)).cuda()
     det = dv.Detector(1024, 1024, spec["threshold"], spec["phase"], 8, max_components=4096,
-                      classify=True)
+                      classify=True, keep_results=True)
     for k in range(len(frames)):
         det.push(dev[k])
     seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS, classify_events=True)
-    seq.push(frames[-2])
-    now, ref = seq.push(frames[-1])
+    refs = [seq.push(f) for f in frames]
+    now, ref = refs[-1]
     check_frame(det, now, ref, 1024, 1024)
+    check_results(det.results(), refs, "events-disks1024")
     det.close()
 
 
@@ -444,16 +553,23 @@ def test_disks1024_batched_burst():
     """Twenty full-size frames pushed back to back in the benchmark's launch
     configuration (default batch); the last comparison against the oracle."""
     sim, spec = synth.workload("disks1024")
-    frames = list(sim.frames(20))
+    frames = list(sim.frames(40))
     dev = torch.from_numpy(np.stack(frames)).cuda()
-    det = dv.Detector(1024, 1024, spec["threshold"], spec["phase"], 8, max_components=4096)
+    det = dv.Detector(1024, 1024, spec["threshold"], spec["phase"], 8, max_components=4096,
+                      keep_results=True)
     for k in range(len(frames)):
         det.push(dev[k])
     seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS)
-    seq.push(frames[-2])
-    now, ref = seq.push(frames[-1])
+    refs = []
+    for k, f in enumerate(frames):
+        if k % 10 == 0:
+            say(f"  [disks1024 burst] oracle frame {k}")
+        refs.append(seq.push(f))
+    now, ref = refs[-1]
     check_frame(det, now, ref, 1024, 1024)
     assert det.info().frame == len(frames)
+    # every frame: a full batch of 32 and a partial one of 8
+    check_results(det.results(), refs, "disks1024 burst")
     det.close()
 
 
@@ -464,12 +580,52 @@ def test_grf1024_frames():
     run_sequence(list(sim.frames(4)), 1.0, kmax=8192, tag="grf1024")
 
 
+@pytest.mark.timeout(600)
 def test_grf4096_full_size():
-    """Full-size random-field frames (16.8 M sites, ~9k components): labels,
-    centres, colour map, couples and flips against the oracle."""
+    """Full-size random-field frames (16.8 M sites, ~9k components), frames
+    0-4 (four comparisons): labels, centres, colour map, couples and flips
+    against the oracle."""
     sim, spec = synth.workload("grf4096")
-    fields = list(sim.frames(2))
+    fields = list(sim.frames(5))
     run_sequence(fields, spec["threshold"], kmax=32768, tag="grf4096")
+
+
+@pytest.mark.timeout(600)
+def test_grf4096_batched_burst():
+    """The benchmark's launch shape at 4096^2: 34 frames pushed back to back
+    with the default batch of 32 (a full launch and a partial one).  Every
+    frame's record and flips equal those of the same frames pushed one per
+    launch; frames 30-33 (four comparisons, across the batch boundary) equal
+    the oracle's."""
+    sim, spec = synth.workload("grf4096")
+    frames = list(sim.frames(34))
+    say("  [grf4096 burst] frames generated")
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    det = dv.Detector(4096, 4096, spec["threshold"], spec["phase"], 8, max_components=32768,
+                      keep_results=True, keep_maps=False)
+    for k in range(len(frames)):
+        det.push(dev[k])
+    batched = det.results()
+    assert len(batched) == 34
+    det.close()
+    det1 = dv.Detector(4096, 4096, spec["threshold"], spec["phase"], 8, max_components=32768,
+                       keep_results=True, keep_maps=False, max_batch=1)
+    for k in range(len(frames)):
+        det1.push(dev[k])
+    alone = det1.results()
+    det1.close()
+    say("  [grf4096 burst] GPU runs done")
+    for k, ((fa, la), (fb, lb)) in enumerate(zip(batched, alone)):
+        assert fa == fb, k
+        assert np.array_equal(la, lb), k
+    seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS)
+    refs = [None] * 34
+    seq.push(frames[29])
+    for k in range(30, 34):
+        say(f"  [grf4096 burst] oracle frame {k}")
+        refs[k] = seq.push(frames[k])
+    check_results(batched, refs, "grf4096 burst")
+    assert sum(1 for fi, _ in batched if fi.n_flips > 0) > 20
 
 
 def test_sparse_cluster_exercises_candidate_overflow():
@@ -505,7 +661,8 @@ def test_few_far_centres_mix_integer_and_float_colouring():
 
 def test_serving_results_equal_alone_and_in_the_mix():
     """Frames of six streams arriving in a random order are served in mixed
-    batches; every frame's flips and counts equal those of the same stream run
+    batches with two steps in flight; every served frame's record and flips
+    equal the oracle's for its own stream and those of the same stream run
     alone, frame by frame."""
     from paper_1607_00908_amd import serve
     rng = np.random.default_rng(12)
@@ -513,9 +670,9 @@ def test_serving_results_equal_alone_and_in_the_mix():
     nf = 5
     frames = [list(sm.frames(nf)) for sm, _ in fields]
     srv = serve.Server(reserve_bytes=0)
-    sids = [srv.admit(sp["lx"], sp["ly"], sp["threshold"], sp["phase"],
-                      max_components=4 * sp["k_expect"] + 256) for _, sp in fields]
-    assert all(s is not None for s in sids)
+    sids = [srv.open(sp["lx"], sp["ly"], sp["threshold"], sp["phase"],
+                     max_components=4 * sp["k_expect"] + 256) for _, sp in fields]
+    assert all(srv.admitted(s) for s in sids)
     # arrivals: a random interleaving of the streams' frames, in per-stream order
     order = [i for i in range(len(fields)) for _ in range(nf)]
     rng.shuffle(order)
@@ -524,22 +681,59 @@ def test_serving_results_equal_alone_and_in_the_mix():
     for step_i, i in enumerate(order):
         srv.submit(sids[i], torch.from_numpy(frames[i][nxt[i]]).cuda(), tag=(i, nxt[i]))
         nxt[i] += 1
-        if rng.random() < 0.5 or step_i == len(order) - 1:
-            while srv.pending():
-                for sid, tag, ta, td, info, fl in srv.step():
-                    mixed[tag] = (info.n_components, info.n_edges, info.n_flips, fl)
-    srv.close()
+        if rng.random() < 0.5:
+            for sid, tag, ta, td, info, fl in srv.step():
+                mixed[tag] = (info, fl)
+    for sid, tag, ta, td, info, fl in srv.drain():
+        mixed[tag] = (info, fl)
+    srv.shutdown()
     assert len(mixed) == len(order)
     for i, (_, sp) in enumerate(fields):
+        seq = oracle.Sequence(sp["threshold"], sp["phase"], 8, NTHREADS)
+        refs = [seq.push(f) for f in frames[i]]
+        check_results([mixed[(i, k)] for k in range(nf)], refs, f"served stream {i}")
         det = dv.Detector(sp["lx"], sp["ly"], sp["threshold"], sp["phase"], 8,
-                          max_components=4 * sp["k_expect"] + 256, max_batch=1)
+                          max_components=4 * sp["k_expect"] + 256, max_batch=1, keep_results=True)
         for k in range(nf):
             det.push(torch.from_numpy(frames[i][k]).cuda())
-            info, fl = det.info(), det.flips()
-            K, E, F, got = mixed[(i, k)]
-            assert (K, E, F) == (info.n_components, info.n_edges, info.n_flips), (i, k)
-            assert np.array_equal(got, fl), (i, k)
+        alone = det.results()
         det.close()
+        for k in range(nf):
+            assert alone[k][0] == mixed[(i, k)][0], (i, k)
+            assert np.array_equal(alone[k][1], mixed[(i, k)][1]), (i, k)
+
+
+def test_serving_admission_and_retirement():
+    """A byte budget admits two streams at a time: the third waits (its frames
+    queue) until a stream closes and retires, then it is admitted and served.
+    Every frame of every stream equals the oracle's."""
+    from paper_1607_00908_amd import serve
+    fields = synth.mixed_fields(3, seed=9, l_min=64, l_max=128)
+    nf = 4
+    frames = [list(sm.frames(nf)) for sm, _ in fields]
+    need = [serve.context_bytes(sp["lx"], sp["ly"], 4 * sp["k_expect"] + 256) for _, sp in fields]
+    srv = serve.Server(reserve_bytes=0, budget_bytes=max(need[0] + need[1], need[0] + need[2],
+                                                         need[1] + need[2]) + 1)
+    sids = [srv.open(sp["lx"], sp["ly"], sp["threshold"], sp["phase"],
+                     max_components=4 * sp["k_expect"] + 256) for _, sp in fields]
+    assert srv.admitted(sids[0]) and srv.admitted(sids[1]) and not srv.admitted(sids[2])
+    got = {i: [] for i in range(3)}
+    for k in range(nf):
+        for i in range(3):
+            srv.submit(sids[i], torch.from_numpy(frames[i][k]).cuda(), tag=(i, k))
+    for sid, tag, ta, td, info, fl in srv.drain():
+        got[tag[0]].append((info, fl))
+    # stream 2 is still waiting for memory: none of its frames was served
+    assert len(got[0]) == nf and len(got[1]) == nf and got[2] == []
+    assert srv.pending() == nf
+    srv.close(sids[0])
+    assert sids[0] not in srv.streams and srv.admitted(sids[2])
+    for sid, tag, ta, td, info, fl in srv.drain():
+        got[tag[0]].append((info, fl))
+    srv.shutdown()
+    for i, (_, sp) in enumerate(fields):
+        seq = oracle.Sequence(sp["threshold"], sp["phase"], 8, NTHREADS)
+        check_results(got[i], [seq.push(f) for f in frames[i]], f"admission stream {i}")
 
 
 # ------------------------------------------------------------ walls and obstacles
@@ -598,21 +792,25 @@ def test_channel2048_batched_burst():
     frames = list(sim.frames(18))
     dev = torch.from_numpy(np.stack(frames)).cuda()
     det = dv.Detector(2048, 1024, spec["threshold"], spec["phase"], 8, max_components=8192,
-                      open_x=True, obstacles=obst, classify=True)
+                      open_x=True, obstacles=obst, classify=True, keep_results=True)
     seq = oracle.Sequence(spec["threshold"], spec["phase"], 8, NTHREADS, classify_events=True,
                           obstacles=obst, open_x=True)
+    refs = []
     for k in range(2):
         say(f"  [channel2048] frame {k}")
         det.push(dev[k])
         now, ref = seq.push(frames[k])
+        refs.append((now, ref))
         check_frame(det, now, ref, 2048, 1024)
     for k in range(2, len(frames)):
         det.push(dev[k])
     say("  [channel2048] burst done")
-    seq.push(frames[-2])
-    now, ref = seq.push(frames[-1])
+    for k in range(2, len(frames)):
+        refs.append(seq.push(frames[k]))
+    now, ref = refs[-1]
     check_frame(det, now, ref, 2048, 1024)
     assert det.info().frame == len(frames)
+    check_results(det.results(), refs, "channel2048 burst")
     det.close()
 
 
