@@ -276,6 +276,34 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
  * NULL is accepted. */
 void dv_group_destroy(dv_group *g);
 
+/* ---- no allocation ---- */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result
+ * of
+ *     dv_create(cfg) ; dv_push_frame(past_field) ; dv_push_frame(now_field) ;
+ *     dv_get_info -> *info_device ; dv_get_flips -> flips_device ; dv_destroy
+ * computed with no allocation and no synchronisation.  Every buffer is carved
+ * from one static device array of 48 MiB per device (held from the first call
+ * on that device until the process ends); a configuration whose buffers do not
+ * fit returns DV_ERR_CAPACITY before any device work (512 x 512 sites with
+ * max_components 2048 and max_degree 48 fit; 1024 x 1024 sites with
+ * max_components 4096 do not).
+ * cfg: as for dv_create; DV_OBSTACLES is refused (DV_ERR_ARG), DV_KEEP_MAPS,
+ * DV_KEEP_RESULTS and max_batch are ignored.  hip_stream: the stream the
+ * work is ordered on (NULL: the null stream); the fields are read and the
+ * outputs written in that stream's order.  Outputs in device memory:
+ * *info_device receives the now frame's dv_frame_info (status DV_ERR_CAPACITY
+ * when it was rejected; n_flips may exceed capacity), flips_device the first
+ * min(n_flips, capacity) flips in dv_flip order.  Calls on one device share
+ * the array: calls whose work overlaps on the device (other streams, other
+ * threads) race and must be ordered by the caller.  Errors (DV_ERR_ARG,
+ * DV_ERR_CAPACITY, DV_ERR_DEVICE) are returned before or at the launch; the
+ * text is dv_last_error(NULL). */
+dv_status dv_compare_static(const dv_config *cfg, void *hip_stream, const float *past_field_device,
+                            const float *now_field_device, dv_flip *flips_device, int32_t capacity,
+                            dv_frame_info *info_device);
+
 /* ---- measurement ---- */
 
 /* Stages of the per-frame procedure, in launch order: threshold and cluster
@@ -302,7 +330,7 @@ const char *dv_stage_name(int32_t stage);
 /* Text of a status code (errors of the calls above). */
 const char *dv_status_str(dv_status s);
 /* Text of the last error on this context ("" when none).  NULL ctx: text of
- * the last dv_create failure of the calling thread. */
+ * the last dv_create or dv_compare_static failure of the calling thread. */
 const char *dv_last_error(const dv_ctx *ctx);
 
 #ifdef __cplusplus

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdv.so")
-SOURCES = ["dv_api.hip", "k_label.hip", "k_voronoi.hip", "k_diff.hip"]
+SOURCES = ["dv_api.hip", "dv_static.hip", "k_label.hip", "k_voronoi.hip", "k_diff.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

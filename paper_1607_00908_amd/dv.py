@@ -34,7 +34,7 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
            "dv_get_matching", "dv_set_obstacles", "dv_group_create", "dv_group_push", "dv_group_push_some",
-           "dv_group_destroy", "dv_results_ready", "dv_get_results",
+           "dv_group_destroy", "dv_results_ready", "dv_get_results", "dv_compare_static",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
 DEFAULT_BATCH = 32   # what max_batch = 0 selects
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.dv_results_ready.argtypes = [vp, i32, i32p, i32p]
     lib.dv_get_results.restype = i32
     lib.dv_get_results.argtypes = [vp, i32, vp, i32, i32p, vp, i32, i32p]
+    lib.dv_compare_static.restype = i32
+    lib.dv_compare_static.argtypes = [ctypes.POINTER(DVConfig), vp, vp, vp, vp, i32, vp]
     lib.dv_sync.restype = i32
     lib.dv_sync.argtypes = [vp]
     lib.dv_destroy.restype = None
