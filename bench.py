@@ -174,7 +174,7 @@ def trace_from(csv_path: str, title: str, command: str):
             if grid == "?,?,?":
                 grid = row.get("Grid_Size", "?")
             dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
-            short = re.sub(r"\(.*", "", name).replace("(anonymous namespace)::", "")
+            short = re.sub(r"\(.*", "", name.replace("(anonymous namespace)::", "")).strip()
             groups[(short, grid)].append(dur)
     rows = sorted(groups.items(), key=lambda kv: (-max(int(x) if x.isdigit() else 0
                                                        for x in kv[0][1].split(",")),
@@ -508,6 +508,8 @@ def main():
     ap.add_argument("--stage", default="owner_edges", help="stage timed for the roofline")
     ap.add_argument("--max-batch", type=int, default=0,
                     help="frames per launch of each stage (0: the library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick max_batch with the autotuner (timed over the candidates first)")
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -570,6 +572,18 @@ def main():
     torch.cuda.synchronize()
     maps = not args.flips_only
     kmax = 32768 if N > (1 << 22) else 4096
+    autotune = None
+    if args.autotune:
+        from paper_1607_00908_amd import tune
+        cands = tuple(b for b in tune.CANDIDATES if b >= (8 if N >= (1 << 22) else 1))
+        t_us = tune.tune_batch(
+            lambda b: dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
+                                  keep_maps=maps, max_batch=b, keep_results=True, **geom),
+            [ring[i] for i in range(ring.shape[0])], candidates=cands, frames=64)
+        args.max_batch = tune.choose(t_us)
+        autotune = {"us_per_frame": {str(k): round(v, 2) for k, v in t_us.items()},
+                    "chosen": args.max_batch, "size_class": tune.size_class(N)}
+        log(f"autotune: {autotune}")
     batch = args.max_batch or dv.DEFAULT_BATCH
     det = dv.Detector(lx, ly, spec["threshold"], spec["phase"], 8, max_components=kmax,
                       keep_maps=maps, max_batch=args.max_batch, keep_results=True, **geom)
@@ -670,6 +684,8 @@ def main():
         "roofline": roofline,
         "unbatched": unbatched,
     }
+    if autotune:
+        out["autotune"] = autotune
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or (1 if N < (1 << 24) else min(16, host_cpu()[2]))
         log(f"cpu baseline (oracle, {threads} thread(s)) ...")

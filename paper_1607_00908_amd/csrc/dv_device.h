@@ -245,3 +245,45 @@ __device__ int block_exclusive_scan(const int *in, int *out, int n, int *wsum /*
     }
     return carry;
 }
+
+// The same, each thread taking a contiguous run of up to PER elements per
+// pass (PER * blockDim.x elements a pass: one pass for the usual sizes), the
+// loads of a run issued together.
+template <int PER>
+__device__ int block_exclusive_scan_wide(const int *in, int *out, int n, int *wsum /* LDS [16] */) {
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+    const int nthr = (int)blockDim.x;
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += nthr * PER) {
+        const int m = min(n - c0, nthr * PER);
+        const int per = (m + nthr - 1) / nthr;
+        const int b = c0 + t * per;
+        const int e = min(b + per, c0 + m);
+        int v[PER];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            v[k] = b + k < e ? in[b + k] : 0;
+            sum += v[k];
+        }
+        int x = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int before = carry + x - sum;
+        for (int w = 0; w < wid; ++w) before += wsum[w];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (b + k < e) out[b + k] = before;
+            before += v[k];
+        }
+        int tot = 0;
+        for (int w = 0; w < nw; ++w) tot += wsum[w];
+        carry += tot;
+    }
+    return carry;
+}

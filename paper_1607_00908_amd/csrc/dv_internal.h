@@ -187,10 +187,30 @@ __device__ __forceinline__ int entry_of(const int *base, int per, int n, int idx
     return lo;
 }
 
-// Past of entry i of a launch: the last earlier entry of the same sequence
-// whose stage errors are clear, else the sequence's past buffer.  Returns the
-// entry index, or -1 for the past buffer.
-__device__ __forceinline__ int past_slot(const Bufs *D, const Batch &G, int i) {
+// Entries of the launch that belong to sequence `seq` and passed their stage
+// checks, as a bit mask over entry indices: lane j of the calling wave loads
+// entry j, so every lane of the wave must make the call.
+__device__ __forceinline__ unsigned long long accepted_entries(const Bufs *D, const Batch &G, int seq) {
+    const int lane = threadIdx.x & 63;
+    bool m = false;
+    if (lane < G.n) {
+        const Bufs &Bj = D[G.idx[lane]];
+        m = Bj.seq == seq && Bj.fs->err == 0;
+    }
+    return __ballot(m);
+}
+
+// Past of entry i of a launch, given the mask of accepted entries of its
+// sequence: the last earlier one, else -1 for the sequence's past buffer.
+__device__ __forceinline__ int past_slot(unsigned long long accepted, int i) {
+    const unsigned long long m = accepted & ((1ull << i) - 1ull);
+    return m ? 63 - __clzll(m) : -1;
+}
+
+// The same by a walk over the earlier entries with uniform (scalar) loads:
+// cheaper where many waves each need it, since the entries' headers stay in
+// the scalar cache.
+__device__ __forceinline__ int past_slot_walk(const Bufs *D, const Batch &G, int i) {
     const int q = D[G.idx[i]].seq;
     for (int j = i - 1; j >= 0; --j)
         if (D[G.idx[j]].seq == q && D[G.idx[j]].fs->err == 0) return j;

@@ -37,9 +37,10 @@ struct PastOf {
     bool valid;
 };
 
-__device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) {
+// (every lane of the calling wave must make the call)
+
+__device__ __forceinline__ PastOf past_of_slot(const Bufs *D, const Batch &G, int i, int j) {
     PastOf r;
-    const int j = past_slot(D, G, i);
     if (j >= 0) {
         r.C = D[G.idx[j]].cur;
         r.K = D[G.idx[j]].fs->K_now;
@@ -51,6 +52,18 @@ __device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) 
         r.valid = st->past_valid != 0;
     }
     return r;
+}
+
+// Past of frame i (every lane of the calling wave must make the call: lane j
+// loads entry j); for one-block-per-frame kernels.
+__device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i,
+                                          unsigned long long accepted) {
+    return past_of_slot(D, G, i, past_slot(accepted, i));
+}
+
+// (by the scalar walk: the per-row kernels run many waves per frame)
+__device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) {
+    return past_of_slot(D, G, i, past_slot_walk(D, G, i));
 }
 
 #define MATCH_LANES 16
@@ -79,7 +92,6 @@ __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch
 
 __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int s_red[4][4];
-    const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
@@ -92,7 +104,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
     // the sequence's last accepted frame of the launch leaves its copy for the
     // next launch
     bool keep = true;
-    for (int q = i + 1; q < nb_frames; ++q)
+    for (int q = i + 1; q < G.n; ++q)
         if (Dt[G.idx[q]].seq == B.seq && Dt[G.idx[q]].fs->err == 0) keep = false;
     const int D = B.maxdeg;
     int e2 = 0, exn = 0, tb = 0, ta = 0;
@@ -295,25 +307,41 @@ __device__ __forceinline__ void copy_words(const int2 *__restrict__ src, int2 *_
 __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int wsum[16];
     __shared__ int s_last;
+    __shared__ int s_before[2];
     const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
     const int t = threadIdx.x;
     // results page of the frame: the flips of the page before it are those
-    // the page held before the launch and those of the earlier frames of the
-    // same sequence in the launch (all of one sequence share one page)
+    // the page held before the launch and those of the earlier accepted frames
+    // of the same sequence in the launch (all of one sequence share one page);
+    // lane j of the first wave takes entry j (at most 64 entries)
+    if (t < 64) {
+        int nfl = 0, acc = 0;
+        if (t < i) {
+            const Bufs &Bj = Dt[G.idx[t]];
+            const FrameState *fj = Bj.fs;
+            if (Bj.seq == B.seq && fj->err == 0) {
+                nfl = fj->nb_acc + fj->na_acc;
+                acc = 1;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            nfl += __shfl_xor(nfl, o, 64);
+            acc += __shfl_xor(acc, o, 64);
+        }
+        if (t == 0) {
+            s_before[0] = nfl;
+            s_before[1] = acc;
+        }
+    }
+    __syncthreads();
     const uint32_t ps = G.pslot[i];
     const int pg = DV_PG_PAGE(ps);
     const SeqState *sq0 = B.st;
-    int base = DV_PG_FRESH(ps) ? 0 : sq0->pg_fill[pg];
-    long long frame_no = sq0->frame;
-    for (int j = 0; j < i; ++j) {
-        const Bufs &Bj = Dt[G.idx[j]];
-        if (Bj.seq != B.seq || Bj.fs->err) continue;
-        base += Bj.fs->nb_acc + Bj.fs->na_acc;
-        ++frame_no;
-    }
+    const int base = (DV_PG_FRESH(ps) ? 0 : sq0->pg_fill[pg]) + s_before[0];
+    long long frame_no = sq0->frame + s_before[1];
     int *const flips = B.pg_flips[pg] + (size_t)6 * base;
     if (fs->err) {
         if (t == 0) {
@@ -329,11 +357,11 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     } else {
         ++frame_no;
         const int KN = fs->K_now;
-        const PastOf PO = past_of(Dt, G, i);
+        const PastOf PO = past_of(Dt, G, i, accepted_entries(Dt, G, B.seq));
         const int D = B.maxdeg;
-        const int nbk = block_exclusive_scan(B.nb, B.ob, KN, wsum);
+        const int nbk = block_exclusive_scan_wide<16>(B.nb, B.ob, KN, wsum);
         __syncthreads();
-        const int nar = block_exclusive_scan(B.na, B.oa, KN, wsum);
+        const int nar = block_exclusive_scan_wide<16>(B.na, B.oa, KN, wsum);
         __syncthreads();
         for (int n = t; n < KN; n += blockDim.x) {
             const int cb = B.nb[n], ca = B.na[n];
@@ -392,30 +420,45 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
     __syncthreads();
     if (!s_last) return;
     if (t == 0) tk->done_place = 0;
-    // thread k commits the sequence whose last entry in the launch is k
-    if (t < nb_frames) {
-        const int k = t, q = Dt[G.idx[k]].seq;
-        bool last = true;
-        for (int j = k + 1; j < nb_frames; ++j)
-            if (Dt[G.idx[j]].seq == q) last = false;
-        if (last) {
-            int a = -1, acc = 0, nfl = 0;
-            for (int j = 0; j <= k; ++j) {
-                const FrameState *fj = Dt[G.idx[j]].fs;
-                if (Dt[G.idx[j]].seq == q && fj->err == 0) {
-                    a = j;
-                    ++acc;
-                    nfl += fj->nb_acc + fj->na_acc;
-                }
+    // lane k of the first wave takes entry k and commits its sequence when k
+    // is the sequence's last entry in the launch; the entries' values reach
+    // the other lanes by shuffles
+    if (t < 64) {
+        const int k = t;
+        int q = -1, ok = 0, nfl = 0, Kn = 0, E2 = 0;
+        if (k < nb_frames) {
+            const Bufs &Bk = Dt[G.idx[k]];
+            const FrameState *fk = Bk.fs;
+            q = Bk.seq;
+            ok = fk->err == 0;
+            if (ok) {
+                nfl = fk->nb_acc + fk->na_acc;
+                Kn = fk->K_now;
+                E2 = fk->E2_acc;
             }
+        }
+        bool last = k < nb_frames;
+        int acc = 0, sum = 0, Ka = -1, E2a = 0;
+        for (int j = 0; j < nb_frames; ++j) {
+            const int qj = __shfl(q, j, 64), okj = __shfl(ok, j, 64), nj = __shfl(nfl, j, 64);
+            const int Kj = __shfl(Kn, j, 64), Ej = __shfl(E2, j, 64);
+            if (j > k && qj == q) last = false;
+            if (j <= k && qj == q && okj) {
+                ++acc;
+                sum += nj;
+                Ka = Kj;
+                E2a = Ej;
+            }
+        }
+        if (last) {
             SeqState *sq = Dt[G.idx[k]].st;
             const uint32_t pk = G.pslot[k];
             const int p = DV_PG_PAGE(pk);
-            sq->pg_fill[p] = (DV_PG_FRESH(pk) ? 0 : sq->pg_fill[p]) + nfl;
-            if (a >= 0) {
+            sq->pg_fill[p] = (DV_PG_FRESH(pk) ? 0 : sq->pg_fill[p]) + sum;
+            if (acc > 0) {
                 const int nxt = 1 - sq->sel;
-                sq->K[nxt] = Dt[G.idx[a]].fs->K_now;
-                sq->E[nxt] = Dt[G.idx[a]].fs->E2_acc / 2;
+                sq->K[nxt] = Ka;
+                sq->E[nxt] = E2a / 2;
                 sq->sel = nxt;
                 sq->past_valid = 1;
                 sq->frame += acc;

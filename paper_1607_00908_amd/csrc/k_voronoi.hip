@@ -171,7 +171,12 @@ struct OwnerLds {
     // centres seen in the first pass: label, Q.8 centre, squared distance
     // to the tile centre
     int tmp[TMP_CAP];
-    int2 tmpq[TMP_CAP];
+    union {
+        int2 tmpq[TMP_CAP];
+        // (after the candidate list is built) inner-frame queries of each
+        // thread's sites, bit 4i + r as in the thread's own mask
+        unsigned pendw[DV_BLOCK];
+    };
     long long tmpd[TMP_CAP];
     int ntmp;
     int nout;      // distinct couples written to the tile's list
@@ -475,45 +480,48 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         // every candidate as well
         const int R0 = 3;
         const Span sx0 = span_cells(tx, R0, B.ntx, ox), sy0 = span_cells(ty, R0, B.nty, oy);
-        {   // one thread per cell of the square walks the cell's centres
-            const int n0x = sx0.hi0 - sx0.lo0 + 1, ncx = n0x + (sx0.n == 2 ? sx0.hi1 - sx0.lo1 + 1 : 0);
+        {   // the centres of the square's cells, lane-parallel: each row of cells
+            // of a column span is one contiguous range of the cell-ordered
+            // arrays, so wave 0 loads the (at most 7 x 2) range bounds, then one
+            // centre per lane over the concatenated ranges (two dependent load
+            // rounds); list slots are the concatenation order and the bound is
+            // one wave minimum, no atomics
             const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
-            // (at most 7 x 7 cells: wave 0 holds them all; list slots come
-            // from ballots and the bound from one wave minimum, no atomics)
             if (t < 64) {
-                int e = 0, e1 = 0;
-                if (t < ncx * ncy) {
-                    const int ix = t % ncx, iy = t / ncx;
-                    const int cellx = ix < n0x ? sx0.lo0 + ix : sx0.lo1 + (ix - n0x);
+                const int nrng = ncy * sx0.n;
+                int e0 = 0, cnt = 0;
+                if (t < nrng) {
+                    const int iy = t / sx0.n, c = t - iy * sx0.n;
                     const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
                     const auto cs = gmem(B.cell_start);
-                    e = cs[celly * B.ntx + cellx];
-                    e1 = cs[celly * B.ntx + cellx + 1];
+                    e0 = cs[celly * B.ntx + sx0.lo(c)];
+                    cnt = cs[celly * B.ntx + sx0.hi(c) + 1] - e0;
                 }
+                int inc = cnt;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(inc, o, 64);
+                    if (t >= o) inc += y;
+                }
+                const int total = __shfl(inc, 63, 64);
+                const int pre = inc - cnt;
                 unsigned long long dmin = ~0ull;
-                int base = 0;
-                while (__ballot(e < e1)) {
-                    const bool has = e < e1;
-                    int2 q = make_int2(0, 0);
-                    int lab = 0;
-                    long long d = 0;
-                    if (has) {
-                        q = ld_int2(B.cell_q, e);
-                        lab = gmem(B.cell_items)[e];
-                        d = d2q(tcx, tcy, q.x, q.y, MX, MY);
+                for (int f0 = 0; f0 < total; f0 += 64) {
+                    const int f = f0 + t;
+                    // range of item f: the last one whose exclusive prefix is <= f
+                    int r = 0;
+                    for (int k = 1; k < nrng; ++k) r = __shfl(pre, k, 64) <= f ? k : r;
+                    const int e = __shfl(e0, r, 64) + f - __shfl(pre, r, 64);
+                    if (f < total) {
+                        const int2 q = ld_int2(B.cell_q, e);
+                        const int lab = gmem(B.cell_items)[e];
+                        const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
                         dmin = min(dmin, (unsigned long long)d);
-                    }
-                    const unsigned long long bm = __ballot(has);
-                    if (has) {
-                        const int slot = base + __popcll(bm & ((1ull << t) - 1ull));
-                        if (slot < TMP_CAP) {
-                            S.tmp[slot] = lab;
-                            S.tmpq[slot] = q;
-                            S.tmpd[slot] = d;
+                        if (f < TMP_CAP) {
+                            S.tmp[f] = lab;
+                            S.tmpq[f] = q;
+                            S.tmpd[f] = d;
                         }
                     }
-                    base += __popcll(bm);
-                    ++e;
                 }
                 for (int o = 32; o > 0; o >>= 1) {
                     const unsigned long long other = __shfl_xor(dmin, o, 64);
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 }
                 if (t == 0) {
                     S.best = dmin;
-                    S.ntmp = base;
+                    S.ntmp = total;
                 }
             }
             __syncthreads();
@@ -657,7 +665,8 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     for (int a = 0; a < 6; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) g[a][b] = S.own[(ys + a) * 34 + cx + b];
-    unsigned pend = 0;   // bit 4i + r: site i needs the colour of inner-frame point r
+    // vertex sites of the thread (frame gaps >= 3): bit i for row ys + i
+    unsigned vmask = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ys + i;
@@ -676,16 +685,49 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
             const int a = f[k], b = f[(k + 1) & 7];
             gaps += (a != b && (!GEOM || (a != DV_EMPTY && b != DV_EMPTY))) ? 1 : 0;
         }
-        if (gaps < 3) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int tg = f[2 * r];
-            const int pa = f[(2 * r + 2) & 7], pb = f[(2 * r + 7) & 7];
-            if ((!GEOM || tg != DV_EMPTY) && pa != pb && tg != ckk) emit(min(ckk, tg), max(ckk, tg));
-            const int dg = f[2 * r + 1];
-            if ((!GEOM || dg != DV_EMPTY) && dg != ckk && pa != pb && pa != tg) pend |= 1u << (4 * i + r);
+        vmask |= gaps >= 3 ? 1u << i : 0u;
+    }
+    // The neighbour rules at the wave's vertex sites, which are few: the
+    // sites are listed in lane order (a wave prefix of the per-lane counts)
+    // and each takes four lanes, lane r applying the first- and
+    // second-neighbour rules of frame direction r (spx, spy, smx, smy rotated
+    // by quarter turns).  A second-neighbour candidate goes to the mask of
+    // the thread owning the site (bit 4i + r), read back below.
+    S.pendw[t] = 0u;
+    {
+        const int cnt = __popc(vmask);
+        int inc = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        const int total = __shfl(inc, 63, 64);
+        for (int p0 = 0; p0 < total; p0 += 16) {
+            const int item = min(p0 + (lane >> 2), total - 1), r = lane & 3;
+            // lane holding the item: the first one whose inclusive count exceeds it
+            int L = 0;
+            for (int step = 32; step > 0; step >>= 1)
+                L += __shfl(inc, L + step - 1, 64) <= item ? step : 0;
+            unsigned m = (unsigned)__shfl((int)vmask, L, 64);
+            for (int k = item - (__shfl(inc, L, 64) - __shfl(cnt, L, 64)); k > 0; --k) m &= m - 1;
+            const int i = __ffs(m) - 1;
+            const int tl = (t & ~63) | L;
+            const int c = (4 * (tl >> 5) + i + 1) * 34 + (tl & 31) + 1;
+            const int k0 = 2 * r, k1 = (2 * r + 2) & 7, k7 = (2 * r + 7) & 7;
+            const int ckk = S.own[c];
+            const int tg = S.own[c + fry(k0) * 34 + frx(k0)];
+            const int pa = S.own[c + fry(k1) * 34 + frx(k1)], pb = S.own[c + fry(k7) * 34 + frx(k7)];
+            const int dg = S.own[c + fry(k0 + 1) * 34 + frx(k0 + 1)];
+            if (p0 + (lane >> 2) < total) {
+                if ((!GEOM || tg != DV_EMPTY) && pa != pb && tg != ckk) emit(min(ckk, tg), max(ckk, tg));
+                if ((!GEOM || dg != DV_EMPTY) && dg != ckk && pa != pb && pa != tg)
+                    atomicOr(&S.pendw[tl], 1u << (4 * i + r));
+            }
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const unsigned pend = S.pendw[t];   // bit 4i + r: site i needs the colour of inner-frame point r
     // inner-frame queries: numbered by a block scan of the per-thread counts,
     // written to LDS in chunks, each answered by one thread
     {

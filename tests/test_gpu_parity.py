@@ -736,6 +736,19 @@ def test_serving_admission_and_retirement():
         check_results(got[i], [seq.push(f) for f in frames[i]], f"admission stream {i}")
 
 
+def test_batch_autotuner_times_every_candidate():
+    """The autotuner times each candidate batch on device frames (every
+    frame's results read back) and picks one of them."""
+    from paper_1607_00908_amd import tune
+    sim = synth.DiskSim(256, 256, 40, 4.0, 7.0, 0.4, 2e-3, seed=44)
+    fields = [torch.from_numpy(f).cuda() for f in sim.frames(6)]
+    t = tune.tune_batch(lambda b: dv.Detector(256, 256, 0.5, max_components=512, max_batch=b,
+                                              keep_results=True),
+                        fields, candidates=(1, 4, 16), frames=16, warmup=4)
+    assert sorted(t) == [1, 4, 16] and all(v > 0 for v in t.values())
+    assert tune.choose(t) in (1, 4, 16)
+
+
 # ------------------------------------------------------------ walls and obstacles
 @pytest.mark.parametrize("seed", range(24))
 def test_walls_and_obstacles_fuzz_small_lattices(seed):
