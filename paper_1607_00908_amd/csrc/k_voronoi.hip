@@ -135,6 +135,8 @@ __device__ __forceinline__ void row_insert(gint *row, int maxdeg, int v, FrameSt
     atomicOr(&fs->err, DV_E_DEGREE);
 }
 
+typedef short sh2 __attribute__((ext_vector_type(2)));   // packed 16-bit pair
+
 #define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
 #define QCAP 512        // inner-frame queries answered per chunk
 #define TMP_CAP 128     // centres kept from the first pass
@@ -154,11 +156,13 @@ struct OwnerLds {
     // or as 32-bit integers when every kept one is near the tile (imode)
     union {
         struct { double sx[DV_CAND_CAP], sy[DV_CAND_CAP], sk[DV_CAND_CAP]; };
-        struct { int ix[DV_CAND_CAP], iy[DV_CAND_CAP], ik[DV_CAND_CAP]; };
+        // (ixy: x in the low 16 bits, y in the high 16, for the packed dot product)
+        struct { int ixy[DV_CAND_CAP], ik[DV_CAND_CAP]; };
     };
     int sl[DV_CAND_CAP];
     uint8_t keep[DV_CAND_CAP];   // the candidate is not beaten everywhere in the window
     int nkeep;                   // candidates kept (the ordered list's length)
+    int fast;                    // the one-pass candidate list of the usual case was built
     int far;                     // some kept candidate is beyond the 32-bit range
     int imode;                   // the ordered list holds 32-bit integers
     int ncand;
@@ -316,11 +320,44 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     // inside 32-bit range, so the same exact comparison runs on integers.
     // That applies to the only evaluation of a tile (no overflow chunks);
     // otherwise the float64 form is used.
-    auto eval_owners = [&](bool last) {
-        if (t == 0) { S.nkeep = 0; S.far = 0; }
-        __syncthreads();
+    auto eval_owners = [&](bool last, bool inited) {
+        if (!inited) {
+            if (t == 0) { S.nkeep = 0; S.far = 0; }
+            __syncthreads();
+        }
         const int nc = min(S.ncand, DV_CAND_CAP);
-        {   // 16 lanes per candidate i, lane j of the group takes the rivals j, j + 16, ...
+        if (nc <= 16) {   // the first wave: 4 lanes per candidate i, lane j of the group
+                          // takes the rivals j, j + 4, ...
+            if (t < 64) {
+                const int i = t >> 2, gj = t & 3;
+                bool beaten = false;
+                if (i < nc) {
+                    const double cx = (double)S.cx[i], cy = (double)S.cy[i];
+                    const double cc = fma(cx, cx, cy * cy);
+#pragma unroll 1
+                    for (int j = gj; j < nc && !beaten; j += 4) {
+                        if (j == i) continue;
+                        const double jx = (double)S.cx[j], jy = (double)S.cy[j];
+                        const double ax = 2.0 * (jx - cx), ay = 2.0 * (jy - cy);
+                        const double f = fma(ax, ax >= 0.0 ? (double)wxlo : (double)wxhi,
+                                             fma(ay, ay >= 0.0 ? (double)wylo : (double)wyhi,
+                                                 cc - fma(jx, jx, jy * jy)));
+                        beaten = f > 0.0;
+                    }
+                }
+                const unsigned long long b = __ballot(beaten);
+                const unsigned grp = (unsigned)(b >> (t & 60)) & 0xfu;
+                const bool kept = gj == 0 && i < nc && !grp;
+                if (gj == 0 && i < nc) S.keep[i] = grp ? 0 : 1;
+                const bool farc = kept && (abs(S.cx[i]) > 23170 || abs(S.cy[i]) > 23170);
+                const int nkept = __popcll(__ballot(kept));
+                const bool anyfar = __ballot(farc) != 0ull;
+                if (t == 0) {
+                    S.nkeep = nkept;
+                    S.far = anyfar ? 1 : 0;
+                }
+            }
+        } else {   // 16 lanes per candidate i, lane j of the group takes the rivals j, j + 16, ...
             const int gi = t >> 4, gj = t & 15;
 #pragma unroll 1
             for (int i0 = 0; i0 < nc; i0 += DV_BLOCK / 16) {
@@ -364,8 +401,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
             }
             const int ix = S.cx[c], iy = S.cy[c];
             if (im) {
-                S.ix[r] = ix;
-                S.iy[r] = iy;
+                S.ixy[r] = (int)(((unsigned)iy << 16) | ((unsigned)ix & 0xffffu));
                 S.ik[r] = ix * ix + iy * iy;
             } else {
                 const double x = (double)ix, y = (double)iy;
@@ -379,22 +415,26 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         __syncthreads();
         const int nk = S.nkeep;
         if (im) {
-            // the only evaluation: strict comparison, ties to the first (lowest label)
-            int m2x[WSITES], m2y[WSITES], bi[WSITES];
+            // the only evaluation: strict comparison, ties to the first (lowest
+            // label).  -2 w and the candidate are 16-bit pairs (|2 w| <= 16384,
+            // |c| <= 23170), so e = -2 w . c + |c|^2 is one packed dot product
+            // with exact 32-bit accumulation
+            sh2 m2[WSITES];
+            int bi[WSITES];
 #pragma unroll
             for (int i = 0; i < WSITES; ++i) {
                 const int w = t + i * DV_BLOCK;
                 const int wy = (w * wmagic) >> 16, wx = w - wy * W;
-                m2x[i] = -512 * (wx - 1);
-                m2y[i] = -512 * (wy - 1);
+                m2[i] = sh2{(short)(-512 * (wx - 1)), (short)(-512 * (wy - 1))};
                 bi[i] = INT_MAX;
             }
             for (int c = 0; c < nk; ++c) {
-                const int cx = S.ix[c], cy = S.iy[c], kk = S.ik[c];
+                const sh2 cq = __builtin_bit_cast(sh2, S.ixy[c]);
+                const int kk = S.ik[c];
                 const int lab = S.sl[c];
 #pragma unroll
                 for (int i = 0; i < WSITES; ++i) {
-                    const int e = __mul24(m2x[i], cx) + __mul24(m2y[i], cy) + kk;
+                    const int e = __builtin_amdgcn_sdot2(m2[i], cq, kk, false);
                     const bool lt = e < bi[i];
                     bi[i] = lt ? e : bi[i];
                     bl[i] = lt ? lab : bl[i];
@@ -471,102 +511,112 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     };
     // radius around the tile centre that holds every centre able to own a
     // window site or inner-frame point: bound + twice the window's half diagonal
-    const double hx = 0.5 * (tw + 1), hy = 0.5 * (th + 1);
-    const double hdiag2 = 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
+    auto hdiag2 = [&]() {
+        const double hx = 0.5 * (tw + 1), hy = 0.5 * (th + 1);
+        return 2.0 * sqrt(hx * hx + hy * hy) + 2.0;
+    };
 
     if (K > 0) {
-        // --- usual case, one pass: the 7x7 cells around the tile give a bound
-        // (nearest centre seen) and, when they cover the radius it implies,
-        // every candidate as well
+        // --- usual case, one pass by the first wave: the 7x7 cells around the
+        // tile give a bound (nearest centre seen) and, when they cover the
+        // radius it implies, every candidate as well; the other waves wait at
+        // the barrier
         const int R0 = 3;
         const Span sx0 = span_cells(tx, R0, B.ntx, ox), sy0 = span_cells(ty, R0, B.nty, oy);
-        {   // the centres of the square's cells, lane-parallel: each row of cells
-            // of a column span is one contiguous range of the cell-ordered
-            // arrays, so wave 0 loads the (at most 7 x 2) range bounds, then one
-            // centre per lane over the concatenated ranges (two dependent load
-            // rounds); list slots are the concatenation order and the bound is
-            // one wave minimum, no atomics
+        if (t < 64) {
+            // the centres of the square's cells, lane-parallel: each row of
+            // cells of a column span is one contiguous range of the cell-ordered
+            // arrays, so the lanes load the (at most 7 x 2) range bounds, then
+            // one centre per lane over the concatenated ranges (two dependent
+            // load rounds); the bound is one wave minimum
             const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
-            if (t < 64) {
-                const int nrng = ncy * sx0.n;
-                int e0 = 0, cnt = 0;
-                if (t < nrng) {
-                    const int iy = t / sx0.n, c = t - iy * sx0.n;
-                    const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
-                    const auto cs = gmem(B.cell_start);
-                    e0 = cs[celly * B.ntx + sx0.lo(c)];
-                    cnt = cs[celly * B.ntx + sx0.hi(c) + 1] - e0;
-                }
-                int inc = cnt;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(inc, o, 64);
-                    if (t >= o) inc += y;
-                }
-                const int total = __shfl(inc, 63, 64);
-                const int pre = inc - cnt;
-                unsigned long long dmin = ~0ull;
-                for (int f0 = 0; f0 < total; f0 += 64) {
-                    const int f = f0 + t;
-                    // range of item f: the last one whose exclusive prefix is <= f
-                    int r = 0;
-                    for (int k = 1; k < nrng; ++k) r = __shfl(pre, k, 64) <= f ? k : r;
-                    const int e = __shfl(e0, r, 64) + f - __shfl(pre, r, 64);
-                    if (f < total) {
-                        const int2 q = ld_int2(B.cell_q, e);
-                        const int lab = gmem(B.cell_items)[e];
-                        const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
-                        dmin = min(dmin, (unsigned long long)d);
-                        if (f < TMP_CAP) {
-                            S.tmp[f] = lab;
-                            S.tmpq[f] = q;
-                            S.tmpd[f] = d;
-                        }
+            const int nrng = ncy * sx0.n;
+            int e0 = 0, cnt = 0;
+            if (t < nrng) {
+                const int iy = t / sx0.n, c = t - iy * sx0.n;
+                const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
+                const auto cs = gmem(B.cell_start);
+                e0 = cs[celly * B.ntx + sx0.lo(c)];
+                cnt = cs[celly * B.ntx + sx0.hi(c) + 1] - e0;
+            }
+            int inc = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(inc, o, 64);
+                if (t >= o) inc += y;
+            }
+            const int total = __shfl(inc, 63, 64);
+            const int pre = inc - cnt;
+            unsigned long long dmin = ~0ull;
+            // the lane's item of the first 64 stays in registers; later ones
+            // (more than 64 centres in the square) go to LDS
+            int2 q0 = make_int2(0, 0);
+            int lab0 = 0;
+            long long d0 = 0;
+            for (int f0 = 0; f0 < total; f0 += 64) {
+                const int f = f0 + t;
+                // range of item f: the last one whose exclusive prefix is <= f
+                int r = 0;
+                for (int k = 1; k < nrng; ++k) r = __shfl(pre, k, 64) <= f ? k : r;
+                const int e = __shfl(e0, r, 64) + f - __shfl(pre, r, 64);
+                if (f < total) {
+                    const int2 q = ld_int2(B.cell_q, e);
+                    const int lab = gmem(B.cell_items)[e];
+                    const long long d = d2q(tcx, tcy, q.x, q.y, MX, MY);
+                    dmin = min(dmin, (unsigned long long)d);
+                    if (f0 == 0) {
+                        q0 = q;
+                        lab0 = lab;
+                        d0 = d;
+                    } else if (f < TMP_CAP) {
+                        S.tmp[f] = lab;
+                        S.tmpq[f] = q;
+                        S.tmpd[f] = d;
                     }
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    const unsigned long long other = __shfl_xor(dmin, o, 64);
-                    dmin = other < dmin ? other : dmin;
-                }
-                if (t == 0) {
-                    S.best = dmin;
-                    S.ntmp = total;
-                }
             }
-            __syncthreads();
-        }
-        bool done = false;
-        if (S.best != ~0ull && S.ntmp <= TMP_CAP) {
-            const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
-            const int wlx = lx - DV_TILE * (B.ntx - 1), wly = ly - DV_TILE * (B.nty - 1);
-            const double cov_x = span_full(sx0, B.ntx) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wlx);
-            const double cov_y = span_full(sy0, B.nty) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wly);
-            if (rho <= cov_x && rho <= cov_y) {
-                const double rq2 = (256.0 * rho) * (256.0 * rho);
-                const int n = S.ntmp;
-                // one atomic per wave for the list slots of its images
-                const int lane = t & 63;
-                for (int j0 = 0; j0 < n; j0 += DV_BLOCK) {
-                    const int j = j0 + t;
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long other = __shfl_xor(dmin, o, 64);
+                dmin = other < dmin ? other : dmin;
+            }
+            // the bound covers the candidates' radius: the list is built here
+            bool fast = dmin != ~0ull && total <= TMP_CAP;
+            double rq2 = 0.0;
+            if (fast) {
+                const double rho = sqrt((double)dmin) / 256.0 + hdiag2();
+                const int wlx = lx - DV_TILE * (B.ntx - 1), wly = ly - DV_TILE * (B.nty - 1);
+                const double cov_x = span_full(sx0, B.ntx) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wlx);
+                const double cov_y = span_full(sy0, B.nty) ? 1e30 : (double)(DV_TILE * (R0 - 1) + wly);
+                fast = rho <= cov_x && rho <= cov_y;
+                rq2 = (256.0 * rho) * (256.0 * rho);
+            }
+            if (fast) {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                int nc = 0;   // list slots taken so far (every lane the same)
+                for (int f0 = 0; f0 < total; f0 += 64) {
+                    const int f = f0 + t;
+                    int2 q = q0;
+                    int lab = lab0;
+                    long long d = d0;
+                    if (f0 > 0 && f < total) {
+                        q = S.tmpq[f];
+                        lab = S.tmp[f];
+                        d = S.tmpd[f];
+                    }
                     unsigned mxk = 0, myk = 0;
-                    int rx = 0, ry = 0, lab = 0;
-                    if (j < n && (double)S.tmpd[j] <= rq2) {
-                        const int2 q = S.tmpq[j];
+                    int rx = 0, ry = 0;
+                    if (f < total && (double)d <= rq2) {
                         rx = q.x - OX;
                         ry = q.y - OY;
-                        lab = S.tmp[j];
                         image_masks(rx, ry, mxk, myk);
                     }
                     const int c = __popc(mxk) * __popc(myk);
                     int x = c;
                     for (int o = 1; o < 64; o <<= 1) {
                         const int y = __shfl_up(x, o, 64);
-                        if (lane >= o) x += y;
+                        if (t >= o) x += y;
                     }
-                    const int wtot = __shfl(x, 63, 64);
-                    int wbase = 0;
-                    if (lane == 0 && wtot) wbase = atomicAdd(&S.ncand, wtot);
-                    wbase = __shfl(wbase, 0, 64);
-                    int slot = wbase + x - c;
+                    int slot = nc + x - c;
                     for (unsigned a = mxk; a; a &= a - 1) {
                         const int cx = rx + (__ffs(a) - 2) * MX;
                         for (unsigned b = myk; b; b &= b - 1) {
@@ -578,17 +628,26 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                             ++slot;
                         }
                     }
+                    nc += __shfl(x, 63, 64);
                 }
-                __syncthreads();
-                done = S.ncand <= DV_CAND_CAP;
-                __syncthreads();
-                if (!done && t == 0) S.ncand = 0;
-                __syncthreads();
+                if (t == 0) S.ncand = nc;
+            }
+            if (t == 0) {
+                S.best = dmin;
+                S.ntmp = total;
+                S.fast = fast ? 1 : 0;
+                S.nkeep = 0;
+                S.far = 0;
             }
         }
+        __syncthreads();
+        const bool done = S.fast && S.ncand <= DV_CAND_CAP;
         if (!done) {
-            // --- general case: a growing square of cells for the bound, then
-            // every cell meeting the disc, evaluated in LDS-sized chunks
+            // --- general case (from an empty list): a growing square of cells
+            // for the bound, then every cell meeting the disc, evaluated in
+            // LDS-sized chunks
+            if (t == 0) S.ncand = 0;
+            __syncthreads();
             for (int R = R0;; R *= 2) {
                 if (S.best != ~0ull) break;
                 const Span sx = span_cells(tx, 2 * R, B.ntx, ox), sy = span_cells(ty, 2 * R, B.nty, oy);
@@ -600,7 +659,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                             [](int) {});
                 if (span_full(sx, B.ntx) && span_full(sy, B.nty)) break;
             }
-            const double rho = sqrt((double)S.best) / 256.0 + hdiag2;
+            const double rho = sqrt((double)S.best) / 256.0 + hdiag2();
             const double rq2 = (256.0 * rho) * (256.0 * rho);
             const double px = tcx / 256.0, py = tcy / 256.0;
             const Span sx = span_sites((int)floor(px - rho), (int)floor(px + rho), lx, ox);
@@ -614,14 +673,14 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 [&](int m) {
                     // evaluate and empty the list when this batch could overflow it
                     if (S.ncand + m * IMG_MAX > DV_CAND_CAP) {
-                        eval_owners(false);
+                        eval_owners(false, false);
                         __syncthreads();
                         if (t == 0) { S.ncand = 0; S.nchunks += 1; }
                         __syncthreads();
                     }
                 });
         }
-        eval_owners(true);
+        eval_owners(true, done);
     }
     // window sites with no colour: beyond a wall, and obstacles
 #pragma unroll
@@ -763,13 +822,13 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 const int qsx = sxy & 31, qsy = sxy >> 5;
                 int m;
                 if (in_lds && imode) {
-                    // (the 32-bit form of the evaluation; |2 q| <= 16384 as for the sites)
-                    const int qx = -2 * (256 * qsx + inx(r)), qy = -2 * (256 * qsy + iny(r));
+                    // (the packed form of the evaluation; |2 q| <= 16128 as for the sites)
+                    const sh2 q2 = sh2{(short)(-2 * (256 * qsx + inx(r))), (short)(-2 * (256 * qsy + iny(r)))};
                     int bee = INT_MAX;
                     m = DV_EMPTY;
                     // the single chunk is ordered by label: ties keep the first
                     for (int k = 0; k < ncl; ++k) {
-                        const int e = __mul24(qx, S.ix[k]) + __mul24(qy, S.iy[k]) + S.ik[k];
+                        const int e = __builtin_amdgcn_sdot2(q2, __builtin_bit_cast(sh2, S.ixy[k]), S.ik[k], false);
                         const bool lt = e < bee;
                         bee = lt ? e : bee;
                         m = lt ? S.sl[k] : m;
