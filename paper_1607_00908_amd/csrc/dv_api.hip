@@ -371,6 +371,7 @@ void place_slot(Carve &cv, Bufs &b) {
     b.seg_mask = cv.take<uint32_t>(segs);
     b.seg_prefix = cv.take<int32_t>(segs);
     b.band_sum = cv.take<int32_t>(b.nty);
+    b.band_pre = cv.take<int32_t>(b.nty);
     b.acc_x = cv.take<long long>(K);
     b.acc_y = cv.take<long long>(K);
     b.acc_n = cv.take<int32_t>(K);

@@ -28,7 +28,6 @@ struct FrameState {
     uint32_t err;          // DV_E_* bits of the frame
     int32_t rows_dirty;    // rows of the slot's adjacency that may hold entries
     int32_t n_amb;         // components crossing their own antipodal line
-    int32_t done_fin;      // blocks of k_finalize that have finished (last one resets)
     int32_t E2_acc;        // sum of now row lengths (2E)
     int32_t excl_acc;      // now points dropped by the isomorphism
     // outputs of the comparison with the past
@@ -42,7 +41,7 @@ struct FrameState {
     int32_t E_now;         // undirected couples of the frame
     int32_t nb_acc;        // breaking couples found by the row comparison
     int32_t na_acc;        // arising couples found by the row comparison
-    int32_t pad;
+    int32_t pad[2];
 };
 
 // Result record of one frame in a results page: written by the device into
@@ -67,7 +66,7 @@ struct SeqState {
     int32_t past_valid;
     int32_t K[2];          // components held by each past buffer
     int32_t E[2];          // undirected couples held by each past buffer
-    int32_t done_place;    // blocks of k_place that have finished (last one commits)
+    int32_t pad0;
     int32_t pg_fill[2];    // flips held by each results page
     int32_t pad;
     int64_t frame;         // accepted frames
@@ -109,6 +108,7 @@ struct Bufs {
     uint32_t *seg_mask;    // [ly][ntx] component-root bits per (row, tile column)
     int32_t *seg_prefix;   // [ly][ntx] roots before each segment within its band
     int32_t *band_sum;     // [nty] roots per band of 32 rows
+    int32_t *band_pre;     // [nty] roots in the bands before each band
     // component accumulation (self-cleaning: finalize zeroes what it reads)
     long long *acc_x, *acc_y;
     int32_t *acc_n, *acc_amb, *acc_root;

@@ -21,11 +21,12 @@
 //             neighbours in either graph, boundary points of either graph.
 //   k_place   one block per frame: scans the per-row counts and places the
 //             staged flips in canonical order (breaking first, then arising,
-//             each by (a, b)).  Kept past and now points correspond one to
-//             one, so the number of dropped past points is
-//             K_past - (K_now - dropped now points).  The last block to
-//             finish commits every sequence of the launch: its spare past
-//             buffer becomes the past when any of its frames was accepted.
+//             each by (a, b)) in the results page, and writes the frame's
+//             record.  Kept past and now points correspond one to one, so the
+//             number of dropped past points is K_past - (K_now - dropped now
+//             points).
+//   k_commit  every sequence of the launch: its spare past buffer becomes the
+//             past when any of its frames was accepted.
 #include "dv_device.h"
 
 namespace {
@@ -306,9 +307,7 @@ __device__ __forceinline__ void copy_words(const int2 *__restrict__ src, int2 *_
 
 __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int wsum[16];
-    __shared__ int s_last;
     __shared__ int s_before[2];
-    const int nb_frames = G.n;
     const int i = blockIdx.z;
     const Bufs &B = Dt[G.idx[i]];
     FrameState *fs = B.fs;
@@ -407,62 +406,54 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
         B.pg_info[pg][DV_PG_POS(ps)] = r;
     }
-    // the last block to finish commits every sequence of the launch (every
-    // block has read the sequence headers by now); the ticket is kept in the
-    // first entry's header
-    __syncthreads();
-    SeqState *tk = Dt[G.idx[0]].st;
-    if (t == 0) {
-        __threadfence();
-        s_last = atomicAdd(&tk->done_place, 1) == nb_frames - 1;
-        if (s_last) __threadfence();
+}
+
+// Commit of every sequence of the launch, after k_place (a kernel of its own:
+// a last-block ticket in k_place would need a device-wide release in every
+// block).  Lane k of one wave takes entry k and commits its sequence when k is
+// the sequence's last entry in the launch: the spare past buffer becomes the
+// past when any of its frames was accepted; the entries' values reach the
+// other lanes by shuffles.
+__global__ __launch_bounds__(64) void k_commit(const Bufs *__restrict__ Dt, Batch G) {
+    const int nb_frames = G.n;
+    const int k = threadIdx.x;
+    int q = -1, ok = 0, nfl = 0, Kn = 0, E2 = 0;
+    if (k < nb_frames) {
+        const Bufs &Bk = Dt[G.idx[k]];
+        const FrameState *fk = Bk.fs;
+        q = Bk.seq;
+        ok = fk->err == 0;
+        if (ok) {
+            nfl = fk->nb_acc + fk->na_acc;
+            Kn = fk->K_now;
+            E2 = fk->E2_acc;
+        }
     }
-    __syncthreads();
-    if (!s_last) return;
-    if (t == 0) tk->done_place = 0;
-    // lane k of the first wave takes entry k and commits its sequence when k
-    // is the sequence's last entry in the launch; the entries' values reach
-    // the other lanes by shuffles
-    if (t < 64) {
-        const int k = t;
-        int q = -1, ok = 0, nfl = 0, Kn = 0, E2 = 0;
-        if (k < nb_frames) {
-            const Bufs &Bk = Dt[G.idx[k]];
-            const FrameState *fk = Bk.fs;
-            q = Bk.seq;
-            ok = fk->err == 0;
-            if (ok) {
-                nfl = fk->nb_acc + fk->na_acc;
-                Kn = fk->K_now;
-                E2 = fk->E2_acc;
-            }
+    bool last = k < nb_frames;
+    int acc = 0, sum = 0, Ka = -1, E2a = 0;
+    for (int j = 0; j < nb_frames; ++j) {
+        const int qj = __shfl(q, j, 64), okj = __shfl(ok, j, 64), nj = __shfl(nfl, j, 64);
+        const int Kj = __shfl(Kn, j, 64), Ej = __shfl(E2, j, 64);
+        if (j > k && qj == q) last = false;
+        if (j <= k && qj == q && okj) {
+            ++acc;
+            sum += nj;
+            Ka = Kj;
+            E2a = Ej;
         }
-        bool last = k < nb_frames;
-        int acc = 0, sum = 0, Ka = -1, E2a = 0;
-        for (int j = 0; j < nb_frames; ++j) {
-            const int qj = __shfl(q, j, 64), okj = __shfl(ok, j, 64), nj = __shfl(nfl, j, 64);
-            const int Kj = __shfl(Kn, j, 64), Ej = __shfl(E2, j, 64);
-            if (j > k && qj == q) last = false;
-            if (j <= k && qj == q && okj) {
-                ++acc;
-                sum += nj;
-                Ka = Kj;
-                E2a = Ej;
-            }
-        }
-        if (last) {
-            SeqState *sq = Dt[G.idx[k]].st;
-            const uint32_t pk = G.pslot[k];
-            const int p = DV_PG_PAGE(pk);
-            sq->pg_fill[p] = (DV_PG_FRESH(pk) ? 0 : sq->pg_fill[p]) + sum;
-            if (acc > 0) {
-                const int nxt = 1 - sq->sel;
-                sq->K[nxt] = Ka;
-                sq->E[nxt] = E2a / 2;
-                sq->sel = nxt;
-                sq->past_valid = 1;
-                sq->frame += acc;
-            }
+    }
+    if (last) {
+        SeqState *sq = Dt[G.idx[k]].st;
+        const uint32_t pk = G.pslot[k];
+        const int p = DV_PG_PAGE(pk);
+        sq->pg_fill[p] = (DV_PG_FRESH(pk) ? 0 : sq->pg_fill[p]) + sum;
+        if (acc > 0) {
+            const int nxt = 1 - sq->sel;
+            sq->K[nxt] = Ka;
+            sq->E[nxt] = E2a / 2;
+            sq->sel = nxt;
+            sq->past_valid = 1;
+            sq->frame += acc;
         }
     }
 }
@@ -545,6 +536,7 @@ void launch_compare(const Batch &G, hipStream_t s, Prof &P) {
     }
     P.begin(ST_PLACE, s);
     hipLaunchKernelGGL(k_place, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, s, G.D, G);
     P.end(ST_PLACE, s);
 }
 

@@ -395,7 +395,9 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
 // component root (the smallest linear index of the component); component
 // roots set their bit in the band's (row, tile column) segment words, which
 // are then scanned in raster order.  seg_prefix holds the number of roots
-// before each segment within the band, band_sum the band's total.
+// before each segment within the band, band_sum the band's total; k_bandpre
+// then writes band_pre (roots in the bands before each band), K and the
+// capacity check.
 // Segment (y, tile column c) covers sites y*lx + 32c .. 32c+31, so raster
 // order of segments is the row-major order of the [ly][ntx] arrays.
 __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Batch G) {
@@ -453,6 +455,22 @@ __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Ba
     if (t == 0) B.band_sum[ty] = carry;
 }
 
+// One block per frame: the band totals become prefixes (roots in the bands
+// before each band), and K and the capacity check are published.  (A kernel
+// of its own: a last-block ticket in k_resolve would need a device-wide
+// release in every band's block.)
+__global__ __launch_bounds__(1024) void k_bandpre(const Bufs *__restrict__ D, Batch G) {
+    const Bufs &B = D[G.idx[blockIdx.z]];
+    __shared__ int wsum[16];
+    const int K = block_exclusive_scan(B.band_sum, B.band_pre, B.nty, wsum);
+    if (threadIdx.x == 0) {
+        FrameState *fs = B.fs;
+        fs->K_now = K;
+        if (K > B.kmax) atomicOr(&fs->err, DV_E_KMAX);
+        fs->rows_dirty = min(K, B.kmax);
+    }
+}
+
 __device__ __forceinline__ int wrap_off(int v, int L) {
     // v in (-L, L) -> signed minimum image in [-floor(L/2), L-1-floor(L/2)]
     const int h = L >> 1;
@@ -472,12 +490,9 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     __shared__ int prank[DV_TILE_SITES / 2];
     __shared__ uint32_t pxy[DV_TILE_SITES / 2];
     __shared__ int psx[DV_TILE_SITES / 2], psy[DV_TILE_SITES / 2], pn[DV_TILE_SITES / 2];
-    __shared__ int wsum[16];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ uint16_t runs[DV_TILE_SITES / 2];   // (row << 5) | first column of each run
     __shared__ int nruns;
-    extern __shared__ int boff[];   // [nty] roots in the bands before each band
-    FrameState *fs = B.fs;
     const int tile = blockIdx.x - G.tbase[e];
     const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
@@ -500,14 +515,6 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const int y = ry + 8 * i;
         L[y * 32 + cx] = (cx < tw && y < th) ? u[i] : (uint16_t)0xffff;
     }
-    // roots in the bands before each band (exclusive prefix of band totals);
-    // the first block publishes K and the capacity check
-    const int K = block_exclusive_scan(B.band_sum, boff, B.nty, wsum);
-    if (tile == 0 && t == 0) {
-        fs->K_now = K;
-        if (K > B.kmax) atomicOr(&fs->err, DV_E_KMAX);
-        fs->rows_dirty = min(K, B.kmax);
-    }
     __syncthreads();
 
     // each piece (thread t takes slot t; at most 512) looks up the component
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const int gx = G % lx, gy = G / lx;
         const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
         const uint32_t below = (1u << (gx & 31)) - 1u;
-        const int rank = boff[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
+        const int rank = gmem(B.band_pre)[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
                          __popc(gmem(B.seg_mask)[seg] & below);
         prank[k] = rank;
         pxy[k] = (uint32_t)gx | ((uint32_t)gy << 16);
@@ -641,9 +648,10 @@ void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, dim3(G.bands), dim3(1024), 0, s, G.D, G);
+    hipLaunchKernelGGL(k_bandpre, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    if (G.geom) hipLaunchKernelGGL(k_relabel<true>, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
-    else hipLaunchKernelGGL(k_relabel<false>, dim3(G.tiles), dim3(DV_BLOCK), G.nty * sizeof(int), s, G.D, G);
+    if (G.geom) hipLaunchKernelGGL(k_relabel<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
+    else hipLaunchKernelGGL(k_relabel<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
     P.end(ST_RELABEL, s);
 }

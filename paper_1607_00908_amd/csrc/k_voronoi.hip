@@ -2,8 +2,9 @@
 // (Sec. 3.1 last step, Sec. 3.2.1 and Sec. 3.2.2 of the paper).
 //
 //   k_finalize      exact Q.8 and float64 centres from the integer sums;
-//                   counts the centres of each bucket cell; the last block to
-//                   finish builds the grid (cell offsets, centres by cell)
+//                   counts the centres of each bucket cell
+//   k_grid          one block per frame builds the grid (cell offsets,
+//                   centres by cell)
 //   k_owner_edges   one block per tile: candidate centres from the grid,
 //                   nearest centre of every site of the tile and its one-site
 //                   ring (LDS), owner map, frame-gap vertex test and the first /
@@ -28,8 +29,6 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
 
 __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, Batch G) {
     const Bufs &B = D[G.idx[blockIdx.z]];
-    __shared__ int wsum[16];
-    __shared__ int s_last;
     FrameState *fs = B.fs;
     const bool ok = fs->err == 0;
     const int K = fs->K_now;
@@ -77,19 +76,18 @@ __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, B
             B.acc_amb[k] = 0;
         }
     }
-    // the last block to finish sees every count and builds the grid
-    // release: the barrier completes the block's stores, one thread writes
-    // the cache back and takes a ticket; acquire likewise in the last block
-    __syncthreads();
-    if (t == 0) {
-        __threadfence();
-        s_last = atomicAdd(&fs->done_fin, 1) == (int)gridDim.x - 1;
-        if (s_last) __threadfence();
-    }
-    __syncthreads();
-    if (!s_last) return;
-    if (t == 0) fs->done_fin = 0;
-    if (!ok) return;
+}
+
+// One block per frame: the bucket grid from the cell counts (offsets, centres
+// by cell).  (A kernel of its own: a last-block ticket in k_finalize would
+// need a device-wide release in every block.)
+__global__ __launch_bounds__(1024) void k_grid(const Bufs *__restrict__ D, Batch G) {
+    const Bufs &B = D[G.idx[blockIdx.z]];
+    __shared__ int wsum[16];
+    const FrameState *fs = B.fs;
+    if (fs->err) return;
+    const int K = fs->K_now, t = threadIdx.x;
+    const CompBuf C = B.cur;
     const int total = block_exclusive_scan(B.cell_count, B.cell_start, B.ncells, wsum);
     if (t == 0) B.cell_start[B.ncells] = total;
     __syncthreads();
@@ -922,6 +920,7 @@ void launch_voronoi(const Batch &G, hipStream_t s, Prof &P) {
     const int fgrid = (int)std::min<long long>((G.kmax + 1023) / 1024, 256);
     P.begin(ST_FINALIZE, s);
     hipLaunchKernelGGL(k_finalize, dim3(fgrid, 1, G.n), dim3(1024), 0, s, G.D, G);
+    hipLaunchKernelGGL(k_grid, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
     P.end(ST_FINALIZE, s);
     P.begin(ST_OWNER_EDGES, s);
     if (G.geom) hipLaunchKernelGGL(k_owner_edges<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);

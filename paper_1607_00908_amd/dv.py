@@ -307,7 +307,7 @@ class Detector:
         if nf.value == 0:
             return []
         infos = (DVFrameInfo * nf.value)()
-        flips = np.zeros((max(nfl.value, 1), 6), dtype=np.int32)
+        flips = np.empty((max(nfl.value, 1), 6), dtype=np.int32)
         got_f, got_fl = ctypes.c_int32(0), ctypes.c_int32(0)
         self._check(self.lib.dv_get_results(self.h, 0, infos, nf.value, ctypes.byref(got_f),
                                             _ptr(flips), nfl.value, ctypes.byref(got_fl)),
