@@ -365,6 +365,7 @@ void place_slot(Carve &cv, Bufs &b) {
     const size_t N = (size_t)b.lx * b.ly, tiles = (size_t)b.ncells, K = (size_t)b.kmax;
     const size_t segs = (size_t)b.ly * b.ntx;
     b.parent = cv.take<int32_t>(N);
+    b.bpc = cv.take<uint16_t>(tiles * DV_BORDER);
     b.lab16 = cv.take<uint16_t>(tiles * DV_TILE_SITES);
     b.pieces = cv.take<uint16_t>(tiles * DV_TILE_SITES);
     b.npieces = cv.take<int32_t>(tiles);

@@ -9,6 +9,7 @@
 
 #define DV_TILE 32                 // tile edge in sites (labelling, colouring)
 #define DV_TILE_SITES (DV_TILE * DV_TILE)
+#define DV_BORDER (4 * DV_TILE)    // border entries of a tile: top row, bottom row, left, right column
 #define DV_BLOCK 256               // threads per tile workgroup
 #define DV_EMPTY 0x77777777        // MAXLINK: empty row slot / no colour
 #define DV_CAND_CAP 128            // candidate centre images held in LDS per chunk
@@ -97,7 +98,10 @@ struct Bufs {
     int32_t classify;      // fill the flips' event flags
     int32_t open_x, open_y;  // 1: walls across that axis instead of wrapping
     const uint8_t *obst;   // [N] obstacle sites (nonzero), or null: none
-    int32_t *parent;       // [N] union-find over tile-border sites and piece roots
+    int32_t *parent;       // [N] union-find over piece roots (linear site indices)
+    uint16_t *bpc;         // [tiles][DV_BORDER] tile-local piece root of every tile-border
+                           // site (0xffff outside): top row, bottom row, left column,
+                           // right column, 32 entries each
     int32_t *labels;       // [N] output label map
     int32_t *owner;        // [N] output colour map
     uint16_t *lab16;       // [tiles][32][32] piece slot of every site (its index in the

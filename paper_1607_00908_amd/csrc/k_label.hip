@@ -1,13 +1,14 @@
 // Cluster labelling and centre-of-mass sums (Sec. 3.1 of the paper).
 //
 // The lattice is cut into 32x32 tiles.  Per frame:
-//   k_tile_ccl   threshold + union-find of each tile in LDS; every tile-border
-//                site and every tile-local root ("piece") gets an entry in the
-//                global parent array (global linear site indices); pieces take
-//                slots in the tile's piece list, and every inside site's slot
-//                goes to a 16-bit map;
-//   k_merge      unions across tile borders and the periodic seams (none
-//                across a wall);
+//   k_tile_ccl   threshold + union-find of each tile in LDS; every tile-local
+//                root ("piece") gets an entry in the global parent array
+//                (global linear site indices) and a slot in the tile's piece
+//                list; every inside site's slot goes to a 16-bit map, and the
+//                piece root of every tile-border site to the tile's 128-entry
+//                border array (whole lines, read by k_merge);
+//   k_merge      unions of pieces across tile borders and the periodic seams
+//                (none across a wall);
 //   k_resolve    per band of 32 rows: each piece finds its global root;
 //                component roots (the smallest linear index of each component)
 //                are marked in a bitmap of (row, tile column) segments, which
@@ -285,31 +286,36 @@ __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ 
         gmem(B.parent)[g] = g;
     }
     __syncthreads();
-    // the 16-bit map holds each inside site's piece slot
+    // the 16-bit map holds each inside site's piece slot, the border array
+    // each border site's piece root (an outside site is marked, so that
+    // merging needs no field)
+    auto bp = gmem(B.bpc) + (size_t)tile * DV_BORDER;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i, s = y * 32 + cx;
         int r = L[s];
         if (r >= 0) r = L[r];   // the run start's root
         if (cx >= tw || y >= th) continue;
-        const bool border = cx == 0 || y == 0 || cx == tw - 1 || y == th - 1;
         gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : slot_of[r];
-        if (!border || r == s) continue;
-        // an outside border site is marked so that merging needs no field
-        gmem(B.parent)[(y0 + y) * B.lx + x0 + cx] = r < 0 ? -1 : (y0 + (r >> 5)) * B.lx + x0 + (r & 31);
+        const uint16_t v = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
+        if (y == 0) bp[cx] = v;
+        if (y == th - 1) bp[DV_TILE + cx] = v;
+        if (cx == 0) bp[2 * DV_TILE + y] = v;
+        if (cx == tw - 1) bp[3 * DV_TILE + y] = v;
     }
     if (t == 0) B.npieces[tile] = npc;
 }
 
-// Unions between inside sites of neighbouring tiles (every tile-border site
-// holds an ancestor of its piece, at least its piece root, or -1 when
-// outside).  One wave per tile: lane j < 32 takes row j of the tile's last
-// column against the next column (periodic); lane 32 + j takes column j of
-// the last row against the next row.  Together they cover every adjacent
-// pair that crosses a tile border, including the diagonal pairs at tile
-// corners and the periodic seams; a pair across a wall is not formed.  Uniting two sites is uniting the values they hold, so the pairs of
-// held values are united, and a pair equal to one the previous thread of the
-// same line unites is skipped (two pieces usually touch along many sites).
+// Unions between inside sites of neighbouring tiles (the border arrays hold
+// the piece root of every tile-border site, or 0xffff when outside).  One
+// wave per tile: lane j < 32 takes row j of the tile's last column against
+// the next column (periodic); lane 32 + j takes column j of the last row
+// against the next row.  Together they cover every adjacent pair that
+// crosses a tile border, including the diagonal pairs at tile corners and
+// the periodic seams; a pair across a wall is not formed.  Uniting two sites
+// is uniting their pieces, so the pairs of piece roots are united, and a
+// pair equal to one the previous thread of the same line unites is skipped
+// (two pieces usually touch along many sites).
 __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], bool conn8, bool active,
                                            int lane) {
     // pairs of this thread: up to three (ps, pu[k])
@@ -355,36 +361,47 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
     const int lx = B.lx, ly = B.ly;
     const int lane = threadIdx.x & 63;
     const int j = lane & 31;
+    const auto bp = gmem(B.bpc);
+    const int ntx = B.ntx;
+    // piece root (linear index) of the site (x, y) from entry `at` of its
+    // tile's border array, -1 outside
+    auto piece = [&](int x, int y, int at) -> int {
+        const int xt = x & ~(DV_TILE - 1), yt = y & ~(DV_TILE - 1);
+        const int v = bp[(size_t)((yt >> 5) * ntx + (xt >> 5)) * DV_BORDER + at];
+        return v == 0xffff ? -1 : (yt + (v >> 5)) * lx + xt + (v & 31);
+    };
     int ps = -1, pu[3] = {-1, -1, -1};
     bool active;
     if (lane < 32) {
-        // row j of the last column against the next column
+        // row j of the last column against the next column (the first
+        // column of its tile: left-column entries)
         const int x = x0 + tw - 1, y = y0 + j;
         active = j < th && !(GEOM && B.open_x && x + 1 == lx);
         if (active) {
             const int xn = (x + 1 == lx) ? 0 : x + 1;
-            ps = gmem(B.parent)[y * lx + x];
+            ps = piece(x, y, 3 * DV_TILE + j);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int yn = y + k - 1;
                 const bool cut = GEOM && B.open_y && (yn < 0 || yn >= ly);
                 yn = yn < 0 ? yn + ly : (yn >= ly ? yn - ly : yn);
-                pu[k] = cut ? -1 : gmem(B.parent)[yn * lx + xn];
+                pu[k] = cut ? -1 : piece(xn, yn, 2 * DV_TILE + (yn & (DV_TILE - 1)));
             }
         }
     } else {
-        // column j of the last row against the next row
+        // column j of the last row against the next row (the first row of
+        // its tile: top-row entries)
         const int x = x0 + j, y = y0 + th - 1;
         active = j < tw && !(GEOM && B.open_y && y + 1 == ly);
         if (active) {
             const int yn = (y + 1 == ly) ? 0 : y + 1;
-            ps = gmem(B.parent)[y * lx + x];
+            ps = piece(x, y, DV_TILE + j);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 int xn = x + k - 1;
                 const bool cut = GEOM && B.open_x && (xn < 0 || xn >= lx);
                 xn = xn < 0 ? xn + lx : (xn >= lx ? xn - lx : xn);
-                pu[k] = cut ? -1 : gmem(B.parent)[yn * lx + xn];
+                pu[k] = cut ? -1 : piece(xn, yn, xn & (DV_TILE - 1));
             }
         }
     }
