@@ -368,6 +368,7 @@ void place_slot(Carve &cv, Bufs &b) {
     b.bpc = cv.take<uint16_t>(tiles * DV_BORDER);
     b.lab16 = cv.take<uint16_t>(tiles * DV_TILE_SITES);
     b.pieces = cv.take<uint16_t>(tiles * DV_TILE_SITES);
+    b.prec = cv.take<int2>(tiles * (DV_TILE_SITES / 2));
     b.npieces = cv.take<int32_t>(tiles);
     b.seg_mask = cv.take<uint32_t>(segs);
     b.seg_prefix = cv.take<int32_t>(segs);

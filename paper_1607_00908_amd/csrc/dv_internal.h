@@ -108,6 +108,8 @@ struct Bufs {
                            // tile's piece list), 0xffff outside
                            // (tile-major: a tile's 2 KB are contiguous)
     uint16_t *pieces;      // [tiles][DV_TILE_SITES] tile-local root site of each piece slot
+    int2 *prec;            // [tiles][DV_TILE_SITES / 2] per piece slot: canonical rank of
+                           // its component, component root (x | y << 16)
     int32_t *npieces;      // [tiles]
     uint32_t *seg_mask;    // [ly][ntx] component-root bits per (row, tile column)
     int32_t *seg_prefix;   // [ly][ntx] roots before each segment within its band

@@ -13,6 +13,8 @@
 //                component roots (the smallest linear index of each component)
 //                are marked in a bitmap of (row, tile column) segments, which
 //                is scanned in raster order within the band;
+//   k_rank       per piece: the canonical rank of its component (roots before
+//                it in raster order) and the component root's coordinates;
 //   k_relabel    reads the piece slots written by k_tile_ccl, writes
 //                canonical labels and accumulates exact integer offsets from
 //                each component's root (signed minimum image) per piece, then
@@ -488,6 +490,35 @@ __global__ __launch_bounds__(1024) void k_bandpre(const Bufs *__restrict__ D, Ba
     }
 }
 
+// RANK_LANES lanes per tile (a tile has few pieces in the usual case): every
+// piece's canonical rank (the component roots before its root in raster
+// order) and its component root, by piece slot, so that k_relabel reads them
+// with its first loads.  The component root's piece records the root for the
+// centre.
+#define RANK_LANES 8
+__global__ __launch_bounds__(256) void k_rank(const Bufs *__restrict__ D, Batch G) {
+    const int gt = blockIdx.x * (256 / RANK_LANES) + threadIdx.x / RANK_LANES;
+    if (gt >= G.tiles) return;
+    const int e = entry_of(G.tbase, G.tpe, G.n, gt);
+    const Bufs &B = D[G.idx[e]];
+    const int tile = gt - G.tbase[e];
+    const int x0 = (tile % B.ntx) * DV_TILE, y0 = (tile / B.ntx) * DV_TILE;
+    const int lx = B.lx, j = threadIdx.x % RANK_LANES;
+    const int np = gmem(B.npieces)[tile];
+    for (int k = j; k < np; k += RANK_LANES) {
+        const int r = gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + k];
+        const int g = (y0 + (r >> 5)) * lx + x0 + (r & 31);
+        const int Gr = gmem(B.parent)[g];    // component root (compressed)
+        const int gx = Gr % lx, gy = Gr / lx;
+        const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
+        const uint32_t below = (1u << (gx & 31)) - 1u;
+        const int rank = gmem(B.band_pre)[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
+                         __popc(gmem(B.seg_mask)[seg] & below);
+        st_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + k, rank, gx | (gy << 16));
+        if (Gr == g && rank < B.kmax) gmem(B.acc_root)[rank] = Gr;
+    }
+}
+
 __device__ __forceinline__ int wrap_off(int v, int L) {
     // v in (-L, L) -> signed minimum image in [-floor(L/2), L-1-floor(L/2)]
     const int h = L >> 1;
@@ -526,31 +557,23 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         u[i] = gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + (ok ? y * 32 + cx : 0)];
     }
     const int np = gmem(B.npieces)[tile];
-    const int proot = t < np ? gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + t] : 0;
+    // (slot t is read whether or not it is in use: the slots of a tile are
+    // all allocated)
+    const int2 pr0 = ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + t);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
         L[y * 32 + cx] = (cx < tw && y < th) ? u[i] : (uint16_t)0xffff;
     }
-    __syncthreads();
-
-    // each piece (thread t takes slot t; at most 512) looks up the component
-    // root and its canonical rank
+    // each piece (thread t takes slot t; at most 512): rank and component
+    // root as k_rank found them
     for (int k = t; k < np; k += DV_BLOCK) {
-        const int r = k == t ? proot : gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + k];
-        const int g = (y0 + (r >> 5)) * lx + x0 + (r & 31);
-        const int G = gmem(B.parent)[g];    // component root (compressed)
-        const int gx = G % lx, gy = G / lx;
-        const size_t seg = (size_t)gy * B.ntx + (gx >> 5);
-        const uint32_t below = (1u << (gx & 31)) - 1u;
-        const int rank = gmem(B.band_pre)[gy / DV_TILE] + gmem(B.seg_prefix)[seg] +
-                         __popc(gmem(B.seg_mask)[seg] & below);
-        prank[k] = rank;
-        pxy[k] = (uint32_t)gx | ((uint32_t)gy << 16);
+        const int2 pr = k == t ? pr0 : ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + k);
+        prank[k] = pr.x;
+        pxy[k] = (uint32_t)pr.y;
         psx[k] = 0;
         psy[k] = 0;
         pn[k] = 0;
-        if (G == g && rank < B.kmax) gmem(B.acc_root)[rank] = G;
     }
     __syncthreads();
 
@@ -666,6 +689,7 @@ void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, dim3(G.bands), dim3(1024), 0, s, G.D, G);
     hipLaunchKernelGGL(k_bandpre, dim3(1, 1, G.n), dim3(1024), 0, s, G.D, G);
+    hipLaunchKernelGGL(k_rank, dim3((G.tiles + 256 / RANK_LANES - 1) / (256 / RANK_LANES)), dim3(256), 0, s, G.D, G);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
     if (G.geom) hipLaunchKernelGGL(k_relabel<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
