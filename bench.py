@@ -467,22 +467,37 @@ def timed_run(dv, det, ptrs, steps: int, warmup: int, stage: str | None, batch: 
     """Push `steps` frames (after `warmup`) and return every frame's results;
     the timed region ends when all of them are on the host.  Results are read
     without waiting after each full batch, so the host copies one batch's
-    flips while the next one runs."""
+    flips while the next one runs.  The flips land in one pinned host buffer
+    allocated before the timed region (sized from the warm-up frames; frames
+    that do not fit are read into a fresh array at the end)."""
     import torch
     F = len(ptrs)
     for i in range(warmup):
         det.push(ptrs[i % F])
-    det.results(wait=True)
+    warm = det.results(wait=True)
+    per = max([fi.n_flips for fi, _ in warm] + [0])
+    cap = steps * (2 * per + 256)
+    buf = torch.empty((cap, 6), dtype=torch.int32, pin_memory=True).numpy()
     if stage:
         det.set_profile(stage, capacity=steps)
     torch.cuda.synchronize()
     got = []
+    used = 0
+
+    def take(wait):
+        nonlocal used
+        res = det.results(wait=wait, out=buf[used:])
+        used += sum(fi.n_flips for fi, _ in res)
+        return res
+
     t0 = time.perf_counter()
     for i in range(steps):
         det.push(ptrs[(warmup + i) % F])
         if (i + 1) % batch == 0:
-            got += det.results(wait=False)
-    got += det.results(wait=True)
+            got += take(False)
+    got += take(True)
+    if len(got) < steps:
+        got += det.results(wait=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage_ms, launches = det.get_profile() if stage else (0.0, 0)

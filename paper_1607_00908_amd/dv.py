@@ -294,11 +294,19 @@ class Detector:
         self._field_refs.clear()
         return _frame_info(fi)
 
-    def results(self, wait: bool = True):
+    def results(self, wait: bool = True, out: np.ndarray | None = None):
         """Every unread frame, oldest first: a list of (FrameInfo, flips int32
         [F, 6]).  ``wait``: send the queued frames and wait for all of them;
         else only frames already complete on the device.  Needs
-        ``keep_results``."""
+        ``keep_results``.
+
+        ``out``: a C-contiguous int32 [cap, 6] host array of the caller's
+        (pinned memory makes the copy a direct DMA); the flips are views into
+        it.  Whole frames are returned while they fit; the others stay unread
+        for the next call."""
+        if out is not None and (out.dtype != np.int32 or out.ndim != 2 or out.shape[1] != 6
+                                or not out.flags["C_CONTIGUOUS"] or not out.flags["WRITEABLE"]):
+            raise ValueError("out must be a writeable C-contiguous int32 array of shape [cap, 6]")
         nf, nfl = ctypes.c_int32(0), ctypes.c_int32(0)
         self._check(self.lib.dv_results_ready(self.h, int(bool(wait)), ctypes.byref(nf),
                                               ctypes.byref(nfl)))
@@ -307,10 +315,15 @@ class Detector:
         if nf.value == 0:
             return []
         infos = (DVFrameInfo * nf.value)()
-        flips = np.empty((max(nfl.value, 1), 6), dtype=np.int32)
+        if out is None:
+            flips = np.empty((max(nfl.value, 1), 6), dtype=np.int32)
+            cap = nfl.value
+        else:
+            flips = out
+            cap = min(out.shape[0], nfl.value)
         got_f, got_fl = ctypes.c_int32(0), ctypes.c_int32(0)
         self._check(self.lib.dv_get_results(self.h, 0, infos, nf.value, ctypes.byref(got_f),
-                                            _ptr(flips), nfl.value, ctypes.byref(got_fl)),
+                                            _ptr(flips), cap, ctypes.byref(got_fl)),
                     allow=(ERR_CAPACITY,))
         out, o = [], 0
         for k in range(got_f.value):

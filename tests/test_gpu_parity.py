@@ -288,12 +288,28 @@ def test_results_capacity_returns_whole_frames():
     assert st == dv.ERR_CAPACITY and gf.value == 2
     assert gfl.value == len(refs[0][1].flips) + len(refs[1][1].flips)
     first = [(dv._frame_info(infos[k]), None) for k in range(2)]
-    rest = det.results(wait=False)
+    # a caller-owned pinned buffer that holds the flips of frames 2 and 3
+    sizes = [len(r.flips) for _, r in refs]
+    cap = sizes[2] + sizes[3]
+    fits, acc = 0, 0
+    for n in sizes[2:]:
+        if acc + n > cap:
+            break
+        acc += n
+        fits += 1
+    out = torch.full((cap, 6), -7, dtype=torch.int32, pin_memory=True).numpy()
+    mid = det.results(wait=False, out=out)
+    assert len(mid) == fits >= 2
+    rest = mid + det.results(wait=False)
     assert len(rest) == 7
     assert [fi.frame for fi, _ in first + rest] == list(range(1, 10))
     for (fi, f), (now, ref) in zip(rest, refs[2:]):
         assert fi.n_components == now.K
         assert np.array_equal(f, ref.flips)
+    for _, f in mid:
+        assert f.size == 0 or np.shares_memory(f, out)
+    with pytest.raises(ValueError):
+        det.results(out=np.zeros((4, 5), np.int32))
     det.close()
 
 
