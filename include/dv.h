@@ -150,6 +150,13 @@ typedef struct {
  * failure *out is NULL. */
 dv_status dv_create(const dv_config *cfg, void *hip_stream, dv_ctx **out);
 
+/* Device memory, in bytes, that dv_create takes for cfg: the one region of
+ * every per-slot and shared buffer of the procedure of Sec. 3.1-3.2.4 (the
+ * results-page records and the sequence header are pinned host memory, not
+ * counted).  Touches no device; DV_ERR_ARG for an invalid cfg or a NULL
+ * bytes. */
+dv_status dv_device_bytes(const dv_config *cfg, uint64_t *bytes);
+
 /* Enqueue one frame: the whole procedure of Sec. 3.1-3.2.4 runs on it.
  * field_device: lx*ly float32 values in device memory,
  * row-major (x fastest), complete in the order of the context's stream at

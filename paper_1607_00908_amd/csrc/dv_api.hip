@@ -417,6 +417,52 @@ void place_shared(Carve &cv, Bufs &B, int page_frames) {
 
 extern "C" {
 
+// The configuration with its defaults filled in (row length a multiple of
+// four: row slots are read four at a time).
+static dv_config normalised(const dv_config &in) {
+    dv_config cfg = in;
+    if (cfg.max_degree == 0) cfg.max_degree = 48;
+    cfg.max_degree = (cfg.max_degree + 3) & ~3;
+    if (cfg.max_batch == 0) cfg.max_batch = DV_DEFAULT_BATCH;
+    return cfg;
+}
+
+// Every device buffer of a context in one region: measured (a Carve with no
+// base), then placed.  c->cfg, c->batch and c->pg_cap are set; B is the
+// shared part of the slot table.
+static void layout_ctx(Carve &cv, dv_ctx *c, Bufs &B) {
+    const size_t N = (size_t)B.lx * B.ly, K = (size_t)B.kmax;
+    place_shared(cv, B, c->pg_cap);
+    c->d_tab = cv.take<Bufs>(DV_MAX_BATCH);
+    c->d_edge_scratch = cv.take<int32_t>(2 * K);
+    c->d_edge_ab = cv.take<int32_t>(K * B.maxdeg);
+    c->d_edge_total = cv.take<int32_t>(1);
+    // one obstacle mask for every slot (no obstacle until set)
+    uint8_t *obst = (c->cfg.flags & DV_OBSTACLES) ? cv.take<uint8_t>(N) : nullptr;
+    B.obst = obst;
+    c->d_obst = obst;
+    for (int k = 0; k < c->batch; ++k) {
+        c->h_tab[k] = B;
+        place_slot(cv, c->h_tab[k]);
+    }
+}
+
+dv_status dv_device_bytes(const dv_config *cfg_in, uint64_t *bytes) {
+    if (!bytes) return fail(nullptr, DV_ERR_ARG, "bytes is NULL");
+    *bytes = 0;
+    dv_status s = check_cfg(cfg_in);
+    if (s != DV_OK) return s;
+    std::unique_ptr<dv_ctx> c(new dv_ctx());
+    c->cfg = normalised(*cfg_in);
+    c->batch = c->cfg.max_batch;
+    c->pg_cap = std::max(c->batch, 8);
+    Bufs B = table_base(c->cfg);
+    Carve measure;
+    layout_ctx(measure, c.get(), B);
+    *bytes = (uint64_t)measure.off;
+    return DV_OK;
+}
+
 dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     if (!out) return fail(nullptr, DV_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -429,11 +475,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
         return fail(nullptr, DV_ERR_ARG, "device ordinal out of range");
 
     dv_ctx *c = new dv_ctx();
-    c->cfg = *cfg_in;
-    if (c->cfg.max_degree == 0) c->cfg.max_degree = 48;
-    // row slots are read four at a time
-    c->cfg.max_degree = (c->cfg.max_degree + 3) & ~3;
-    if (c->cfg.max_batch == 0) c->cfg.max_batch = DV_DEFAULT_BATCH;
+    c->cfg = normalised(*cfg_in);
     c->batch = c->cfg.max_batch;
     c->device = c->cfg.device;
     c->npending = 0;
@@ -470,30 +512,18 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
     // shared part of the slot table
     Bufs B = table_base(c->cfg);
     const size_t N = (size_t)B.lx * B.ly, K = (size_t)B.kmax;
-    // every device buffer in one region: measured first, then placed
-    uint8_t *obst = nullptr;   // one mask for every slot (no obstacle until set)
-    auto layout = [&](Carve &cv) {
-        place_shared(cv, B, c->pg_cap);
-        c->d_tab = cv.take<Bufs>(DV_MAX_BATCH);
-        c->d_edge_scratch = cv.take<int32_t>(2 * K);
-        c->d_edge_ab = cv.take<int32_t>(K * B.maxdeg);
-        c->d_edge_total = cv.take<int32_t>(1);
-        obst = (c->cfg.flags & DV_OBSTACLES) ? cv.take<uint8_t>(N) : nullptr;
-        B.obst = obst;
-        c->d_obst = obst;
-        for (int k = 0; k < c->batch; ++k) {
-            c->h_tab[k] = B;
-            place_slot(cv, c->h_tab[k]);
-        }
-    };
     Carve measure;
-    layout(measure);
+    {
+        Bufs Bm = B;
+        layout_ctx(measure, c, Bm);
+    }
     bool ok = hipMalloc(&c->region, measure.off) == hipSuccess;
     if (ok) {
         Carve cv;
         cv.base = static_cast<char *>(c->region);
-        layout(cv);
+        layout_ctx(cv, c, B);
     }
+    uint8_t *obst = c->d_obst;
     // results-page records: pinned host memory that the device writes
     for (int p = 0; ok && p < 2; ++p) {
         ok = hipHostMalloc((void **)&c->h_pg[p], sizeof(FrameOut) * DV_MAX_BATCH,

@@ -34,7 +34,7 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = rang
 EXPORTS = ("dv_create", "dv_push_frame", "dv_get_flips", "dv_get_info", "dv_sync", "dv_destroy",
            "dv_get_labels", "dv_get_owner", "dv_get_components", "dv_get_edges",
            "dv_get_matching", "dv_set_obstacles", "dv_group_create", "dv_group_push", "dv_group_push_some",
-           "dv_group_destroy", "dv_results_ready", "dv_get_results", "dv_compare_static",
+           "dv_group_destroy", "dv_results_ready", "dv_get_results", "dv_compare_static", "dv_device_bytes",
            "dv_set_profile", "dv_get_profile", "dv_stage_name", "dv_status_str", "dv_last_error")
 
 DEFAULT_BATCH = 32   # what max_batch = 0 selects
@@ -97,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.dv_get_results.argtypes = [vp, i32, vp, i32, i32p, vp, i32, i32p]
     lib.dv_compare_static.restype = i32
     lib.dv_compare_static.argtypes = [ctypes.POINTER(DVConfig), vp, vp, vp, vp, i32, vp]
+    lib.dv_device_bytes.restype = i32
+    lib.dv_device_bytes.argtypes = [ctypes.POINTER(DVConfig), ctypes.POINTER(ctypes.c_uint64)]
     lib.dv_sync.restype = i32
     lib.dv_sync.argtypes = [vp]
     lib.dv_destroy.restype = None
@@ -159,6 +161,33 @@ def _frame_info(fi: DVFrameInfo) -> FrameInfo:
                      fi.n_ambiguous_centroids, fi.global_trigger)
 
 
+def _config(lx, ly, threshold, phase, connectivity, max_components, max_degree, device, keep_maps,
+            max_batch, classify, open_x, open_y, with_obstacles, keep_results) -> DVConfig:
+    flags = ((KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0)
+             | (OPEN_X if open_x else 0) | (OPEN_Y if open_y else 0)
+             | (KEEP_RESULTS if keep_results else 0) | (OBSTACLES if with_obstacles else 0))
+    return DVConfig(ctypes.sizeof(DVConfig), int(lx), int(ly), float(threshold), int(phase),
+                    int(connectivity), int(max_components), int(max_degree), int(device),
+                    flags, int(max_batch))
+
+
+def device_bytes(lx: int, ly: int, threshold: float = 0.5, phase: int = PHASE_ABOVE,
+                 connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
+                 keep_maps: bool = True, max_batch: int = 0, classify: bool = False,
+                 open_x: bool = False, open_y: bool = False, with_obstacles: bool = False,
+                 keep_results: bool = False) -> int:
+    """Device memory a Detector of this configuration allocates (the library's
+    own layout; no device is touched)."""
+    lib = load()
+    cfg = _config(lx, ly, threshold, phase, connectivity, max_components, max_degree, 0, keep_maps,
+                  max_batch, classify, open_x, open_y, with_obstacles, keep_results)
+    out = ctypes.c_uint64(0)
+    st = lib.dv_device_bytes(ctypes.byref(cfg), ctypes.byref(out))
+    if st != OK:
+        raise DVError(st, lib.dv_last_error(None).decode())
+    return int(out.value)
+
+
 class Detector:
     """One detection context (one sequence of frames) on one device.
 
@@ -184,13 +213,9 @@ class Detector:
                  obstacles=None, with_obstacles: bool = False, keep_results: bool = False):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
-        flags = ((KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0)
-                 | (OPEN_X if open_x else 0) | (OPEN_Y if open_y else 0)
-                 | (KEEP_RESULTS if keep_results else 0)
-                 | (OBSTACLES if (with_obstacles or obstacles is not None) else 0))
-        cfg = DVConfig(ctypes.sizeof(DVConfig), self.lx, self.ly, float(threshold), int(phase),
-                       int(connectivity), int(max_components), int(max_degree), int(device),
-                       flags, int(max_batch))
+        cfg = _config(self.lx, self.ly, threshold, phase, connectivity, max_components, max_degree,
+                      device, keep_maps, max_batch, classify, open_x, open_y,
+                      with_obstacles or obstacles is not None, keep_results)
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))

@@ -27,21 +27,13 @@ from . import dv
 MAX_STREAMS = 64          # members of one group
 
 
-def context_bytes(lx: int, ly: int, max_components: int, max_degree: int = 48,
-                  max_batch: int = 1) -> int:
-    """Device memory of a context (maps kept): per site and batch slot the
-    parent, 16-bit piece slots, piece lists, label and owner maps and segment
-    words; per component and slot the frame's component set with its rows, the
-    sums, the grid, the matching and the staged flips; two past component sets
-    and two results pages of max(max_batch, 8) frames (K_max * max_degree flips
-    of 24 bytes each)."""
-    n = lx * ly
-    per_site = 4 + 2 + 2 + 4 + 4 + 1
-    per_comp_slot = (36 + 4 * max_degree) + 28 + 20 + 24 + 16 + 48 * max_degree + 12
-    pages = 2 * max(max_batch, 8)
-    per_comp_shared = 2 * (36 + 4 * max_degree) + pages * 24 * max_degree
-    return (max_batch * (n * per_site + max_components * per_comp_slot)
-            + max_components * per_comp_shared + (1 << 20))
+def context_bytes(lx: int, ly: int, max_components: int, max_degree: int = 0, max_batch: int = 1,
+                  open_x: bool = False, open_y: bool = False, obstacles=None) -> int:
+    """Device memory of a serving context (results kept, no maps), as the
+    library lays it out."""
+    return dv.device_bytes(lx, ly, max_components=max_components, max_degree=max_degree,
+                           keep_maps=False, max_batch=max_batch, keep_results=True,
+                           open_x=open_x, open_y=open_y, with_obstacles=obstacles is not None)
 
 
 @dataclass
@@ -90,7 +82,7 @@ class Server:
         self._next_sid += 1
         params = dict(lx=lx, ly=ly, threshold=threshold, phase=phase,
                       connectivity=connectivity, max_components=max_components, **geometry)
-        self.streams[sid] = _Stream(sid, params, context_bytes(lx, ly, max_components))
+        self.streams[sid] = _Stream(sid, params, context_bytes(lx, ly, max_components, **geometry))
         self.admission.append(sid)
         self._admit()
         return sid

@@ -56,6 +56,32 @@ def test_invalid_config_is_rejected_on_the_host(bad):
     assert st == dv.ERR_ARG
     assert not h.value
     assert lib.dv_last_error(None)
+    n = ctypes.c_uint64(7)
+    assert lib.dv_device_bytes(ctypes.byref(_cfg(**bad)), ctypes.byref(n)) == dv.ERR_ARG
+    assert n.value == 0
+
+
+def test_device_bytes_follows_the_configuration():
+    """The layout size (computed on the host) grows with every quantity that
+    sizes a buffer: sites and batch slots, K_max, the row length, an obstacle
+    mask; each slot holds at least the per-site maps (parent, 16-bit piece
+    slots, piece lists, label and owner maps: 16 B/site)."""
+    lib = dv.load()
+    assert lib.dv_device_bytes(None, None) == dv.ERR_ARG
+    assert lib.dv_device_bytes(ctypes.byref(_cfg()), None) == dv.ERR_ARG
+    b = lambda **kw: dv.device_bytes(**{"lx": 256, "ly": 256, "max_components": 1000,
+                                         "max_batch": 1, **kw})
+    base = b()
+    assert base >= 256 * 256 * 16
+    assert b(lx=512) - base >= 256 * 256 * 16
+    two = b(max_batch=2)
+    assert two - base >= 256 * 256 * 16
+    assert b(max_batch=3) - two == two - base          # slots are all alike
+    assert b(max_components=2000) > base
+    assert b(max_degree=64) > base                      # default rows: 48 slots
+    assert b(max_degree=45) == b(max_degree=48)         # rows rounded up to 4
+    assert b(with_obstacles=True) - base >= 256 * 256   # one byte per site
+    assert b(max_batch=0) == b(max_batch=dv.DEFAULT_BATCH)
 
 
 def test_size_guard():
