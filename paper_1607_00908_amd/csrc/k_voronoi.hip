@@ -135,8 +135,17 @@ __device__ __forceinline__ void row_insert(gint *row, int maxdeg, int v, FrameSt
 
 typedef short sh2 __attribute__((ext_vector_type(2)));   // packed 16-bit pair
 
+// a.x b.x + a.y b.y + c on signed 16-bit pairs, exact in 32 bits.  Written
+// as the three-operand instruction: the compiler's form of the builtin
+// accumulates into its destination, which costs a copy of c for every use
+// when c is shared by several products.
+__device__ __forceinline__ int dot2_acc(sh2 a, sh2 b, int c) {
+    int d;
+    asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 #define PAIR_CAP 256    // couples a tile can collect in LDS before writing through
-#define QCAP 512        // inner-frame queries answered per chunk
 #define TMP_CAP 128     // centres kept from the first pass
 
 #define WSITES 5      // ceil(34*34 / 256) window sites per thread
@@ -185,8 +194,6 @@ struct OwnerLds {
     // couples found by the tile, (a << 32 | b) with a < b
     unsigned long long pair[PAIR_CAP];
     int npair;
-    // inner-frame queries of one chunk: (site << 2) | r
-    int q[QCAP];
 };
 
 // Visit every item (index into the cell-ordered centre arrays) of the cells
@@ -426,18 +433,26 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 m2[i] = sh2{(short)(-512 * (wx - 1)), (short)(-512 * (wy - 1))};
                 bi[i] = INT_MAX;
             }
-            for (int c = 0; c < nk; ++c) {
+            // candidates in order, two per step (the compiler does not unroll
+            // a loop around inline assembly)
+            auto cand = [&](int c) {
                 const sh2 cq = __builtin_bit_cast(sh2, S.ixy[c]);
                 const int kk = S.ik[c];
                 const int lab = S.sl[c];
 #pragma unroll
                 for (int i = 0; i < WSITES; ++i) {
-                    const int e = __builtin_amdgcn_sdot2(m2[i], cq, kk, false);
+                    const int e = dot2_acc(m2[i], cq, kk);
                     const bool lt = e < bi[i];
                     bi[i] = lt ? e : bi[i];
                     bl[i] = lt ? lab : bl[i];
                 }
+            };
+            int c = 0;
+            for (; c + 1 < nk; c += 2) {
+                cand(c);
+                cand(c + 1);
             }
+            if (c < nk) cand(c);
             return;
         }
         double m2x[WSITES], m2y[WSITES];
@@ -785,77 +800,64 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const unsigned pend = S.pendw[t];   // bit 4i + r: site i needs the colour of inner-frame point r
-    // inner-frame queries: numbered by a block scan of the per-thread counts,
-    // written to LDS in chunks, each answered by one thread
+    // Inner-frame queries, which are few: numbered within the wave (a wave
+    // prefix of the per-lane counts) and answered one per lane, 64 at a time.
     {
         const int cnt = __popc(pend);
-        int x = cnt;
+        int inc = cnt;
         for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
         }
-        if (lane == 63) S.wsum[t >> 6] = x;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int w = 0; w < DV_BLOCK / 64; ++w) {
-            if (w < (t >> 6)) before += S.wsum[w];
-            total += S.wsum[w];
-        }
-        before += x - cnt;
-        for (int c0 = 0; c0 < total; c0 += QCAP) {
-            // this thread's queries with numbers in [c0, c0 + QCAP)
-            unsigned rest = pend;
-            for (int j = before; rest; ++j) {
-                const int bit = __ffs(rest) - 1;
-                rest &= rest - 1;
-                if (j >= c0 && j < c0 + QCAP) {
-                    const int i = bit >> 2, r = bit & 3;
-                    S.q[j - c0] = (((ys + i) * 32 + cx) << 2) | r;
+        const int total = __shfl(inc, 63, 64);
+        for (int p0 = 0; p0 < total; p0 += 64) {
+            const int item = min(p0 + lane, total - 1);
+            // lane holding the item: the first one whose inclusive count exceeds it
+            int L = 0;
+            for (int step = 32; step > 0; step >>= 1)
+                L += __shfl(inc, L + step - 1, 64) <= item ? step : 0;
+            unsigned m = (unsigned)__shfl((int)pend, L, 64);
+            for (int k = item - (__shfl(inc, L, 64) - __shfl(cnt, L, 64)); k > 0; --k) m &= m - 1;
+            if (p0 + lane >= total) continue;
+            const int bit = __ffs(m) - 1, r = bit & 3;
+            const int tl = (t & ~63) | L;
+            const int qsx = tl & 31, qsy = 4 * (tl >> 5) + (bit >> 2);
+            int mq;
+            if (in_lds && imode) {
+                // (the packed form of the evaluation; |2 q| <= 16128 as for the sites)
+                const sh2 q2 = sh2{(short)(-2 * (256 * qsx + inx(r))), (short)(-2 * (256 * qsy + iny(r)))};
+                int bee = INT_MAX;
+                mq = DV_EMPTY;
+                // the single chunk is ordered by label: ties keep the first
+                for (int k = 0; k < ncl; ++k) {
+                    const int e = dot2_acc(q2, __builtin_bit_cast(sh2, S.ixy[k]), S.ik[k]);
+                    const bool lt = e < bee;
+                    bee = lt ? e : bee;
+                    mq = lt ? S.sl[k] : mq;
                 }
-            }
-            __syncthreads();
-            const int nq = min(QCAP, total - c0);
-            for (int j = t; j < nq; j += DV_BLOCK) {
-                const int code = S.q[j], r = code & 3, sxy = code >> 2;
-                const int qsx = sxy & 31, qsy = sxy >> 5;
-                int m;
-                if (in_lds && imode) {
-                    // (the packed form of the evaluation; |2 q| <= 16128 as for the sites)
-                    const sh2 q2 = sh2{(short)(-2 * (256 * qsx + inx(r))), (short)(-2 * (256 * qsy + iny(r)))};
-                    int bee = INT_MAX;
-                    m = DV_EMPTY;
-                    // the single chunk is ordered by label: ties keep the first
-                    for (int k = 0; k < ncl; ++k) {
-                        const int e = __builtin_amdgcn_sdot2(q2, __builtin_bit_cast(sh2, S.ixy[k]), S.ik[k], false);
-                        const bool lt = e < bee;
-                        bee = lt ? e : bee;
-                        m = lt ? S.sl[k] : m;
-                    }
-                } else if (in_lds) {
-                    const double qx = -2.0 * (256.0 * qsx + inx(r)), qy = -2.0 * (256.0 * qsy + iny(r));
-                    double bee = 1.0e300;
-                    m = DV_EMPTY;
-                    // the single chunk is ordered by label: ties keep the first
-                    for (int k = 0; k < ncl; ++k) {
-                        const double e = fma(qx, S.sx[k], fma(qy, S.sy[k], S.sk[k]));
-                        const bool lt = e < bee;
-                        bee = lt ? e : bee;
-                        m = lt ? S.sl[k] : m;
-                    }
-                } else {
-                    // (on a walled axis the point is inside: its diagonal
-                    // partner has a colour)
-                    int X = OX + 256 * qsx + inx(r), Y = OY + 256 * qsy + iny(r);
-                    if (X < 0) X += MX;
-                    if (Y < 0) Y += MY;
-                    m = point_nearest(B, X, Y);
+            } else if (in_lds) {
+                const double qx = -2.0 * (256.0 * qsx + inx(r)), qy = -2.0 * (256.0 * qsy + iny(r));
+                double bee = 1.0e300;
+                mq = DV_EMPTY;
+                // the single chunk is ordered by label: ties keep the first
+                for (int k = 0; k < ncl; ++k) {
+                    const double e = fma(qx, S.sx[k], fma(qy, S.sy[k], S.sk[k]));
+                    const bool lt = e < bee;
+                    bee = lt ? e : bee;
+                    mq = lt ? S.sl[k] : mq;
                 }
-                const int c = (qsy + 1) * 34 + qsx + 1;
-                const int ckk = S.own[c];
-                const int dg = S.own[c + fry(2 * r + 1) * 34 + frx(2 * r + 1)];
-                if (m == dg || m == ckk) emit(min(ckk, dg), max(ckk, dg));
+            } else {
+                // (on a walled axis the point is inside: its diagonal
+                // partner has a colour)
+                int X = OX + 256 * qsx + inx(r), Y = OY + 256 * qsy + iny(r);
+                if (X < 0) X += MX;
+                if (Y < 0) Y += MY;
+                mq = point_nearest(B, X, Y);
             }
-            __syncthreads();
+            const int c = (qsy + 1) * 34 + qsx + 1;
+            const int ckk = S.own[c];
+            const int dg = S.own[c + fry(2 * r + 1) * 34 + frx(2 * r + 1)];
+            if (mq == dg || mq == ckk) emit(min(ckk, dg), max(ckk, dg));
         }
     }
     __syncthreads();
