@@ -349,19 +349,16 @@ __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], boo
     }
 }
 
+// The border pairs of tile gt (flat over the launch) that lane `lane` unites:
+// the piece root of its site and of up to three neighbours (-1 when outside
+// or not formed).
 template <bool GEOM>
-__global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch G) {
-    // one wave per tile, four tiles per block
-    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (gt >= G.tiles) return;
-    const int e = entry_of(G.tbase, G.tpe, G.n, gt);
-    const Bufs &B = D[G.idx[e]];
-    const int tile = gt - G.tbase[e];
+__device__ __forceinline__ void border_pairs(const Bufs &B, int tile, int lane, int &ps, int pu[3],
+                                             bool &active) {
     const int tx = tile % B.ntx, ty = tile / B.ntx;
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int lx = B.lx, ly = B.ly;
-    const int lane = threadIdx.x & 63;
     const int j = lane & 31;
     const auto bp = gmem(B.bpc);
     const int ntx = B.ntx;
@@ -372,8 +369,8 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
         const int v = bp[(size_t)((yt >> 5) * ntx + (xt >> 5)) * DV_BORDER + at];
         return v == 0xffff ? -1 : (yt + (v >> 5)) * lx + xt + (v & 31);
     };
-    int ps = -1, pu[3] = {-1, -1, -1};
-    bool active;
+    ps = -1;
+    pu[0] = pu[1] = pu[2] = -1;
     if (lane < 32) {
         // row j of the last column against the next column (the first
         // column of its tile: left-column entries)
@@ -407,7 +404,30 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
             }
         }
     }
-    merge_line(gmem(B.parent), ps, pu, B.conn == 8, active, lane);
+}
+
+// MERGE_TILES tiles per wave, four waves per block: the border loads of all
+// of a wave's tiles are in flight together before their unions.
+#define MERGE_TILES 2
+template <bool GEOM>
+__global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch G) {
+    const int gt0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MERGE_TILES;
+    if (gt0 >= G.tiles) return;
+    const int lane = threadIdx.x & 63;
+    int ps[MERGE_TILES], pu[MERGE_TILES][3];
+    bool active[MERGE_TILES];
+    const Bufs *Bt[MERGE_TILES];
+#pragma unroll
+    for (int m = 0; m < MERGE_TILES; ++m) {
+        const int gt = min(gt0 + m, G.tiles - 1);
+        const int e = entry_of(G.tbase, G.tpe, G.n, gt);
+        Bt[m] = &D[G.idx[e]];
+        border_pairs<GEOM>(*Bt[m], gt - G.tbase[e], lane, ps[m], pu[m], active[m]);
+        active[m] = active[m] && gt0 + m < G.tiles;
+    }
+#pragma unroll
+    for (int m = 0; m < MERGE_TILES; ++m)
+        merge_line(gmem(Bt[m]->parent), ps[m], pu[m], Bt[m]->conn == 8, active[m], lane);
 }
 
 // One block per band of 32 rows: every piece of the band's tiles finds its
@@ -683,8 +703,9 @@ void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     else hipLaunchKernelGGL(k_tile_ccl<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
-    if (G.geom) hipLaunchKernelGGL(k_merge<true>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
-    else hipLaunchKernelGGL(k_merge<false>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G);
+    const int merge_blocks = (G.tiles + 4 * MERGE_TILES - 1) / (4 * MERGE_TILES);
+    if (G.geom) hipLaunchKernelGGL(k_merge<true>, dim3(merge_blocks), dim3(256), 0, s, G.D, G);
+    else hipLaunchKernelGGL(k_merge<false>, dim3(merge_blocks), dim3(256), 0, s, G.D, G);
     P.end(ST_MERGE, s);
     P.begin(ST_RESOLVE, s);
     hipLaunchKernelGGL(k_resolve, dim3(G.bands), dim3(1024), 0, s, G.D, G);
