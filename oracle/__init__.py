@@ -10,6 +10,8 @@ chain the steps in the paper's order:
 * ``frame(field, ...)``  -- Sec. 3.1 and 3.2.1-3.2.2 on one field
 * ``Sequence``           -- keeps the past frame and applies Sec. 3.2.3-3.2.4
 * ``classify``           -- event flags of the flips (Sec. 3.2.4, optional)
+* ``centroids(..., field=)`` -- the density-weighted centroids of Sec. 2
+  (optional variant of the centres)
 
 Geometry: every function takes ``open_x`` / ``open_y`` (that axis has walls
 instead of wrapping; default periodic) and, where sites are coloured or
@@ -62,6 +64,9 @@ def _load():
     lib.or_centroids.restype = None
     lib.or_centroids.argtypes = [_i32p, i32, i32, i32, i32, i32, _i32p, _i32p, _i32p, _i32p,
                                  _f64p, _f64p, _i32p]
+    lib.or_centroids_weighted.restype = None
+    lib.or_centroids_weighted.argtypes = [_i32p, _f32p, i32, i32, i32, i32, _i32p, _i32p, _i32p,
+                                          _f64p, _f64p, ctypes.POINTER(ctypes.c_int64)]
     lib.or_owner.restype = None
     lib.or_owner.argtypes = [i32, i32, i32, _u8p, i32, _i32p, _i32p, _i32p, i32]
     lib.or_colour_at.restype = i32
@@ -116,8 +121,12 @@ def label(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8,
 
 
 def centroids(labels: np.ndarray, K: int, conn: int = 8, open_x: bool = False,
-              open_y: bool = False) -> dict:
-    """Sizes and centres of mass (Sec. 3.1), exact Q.8 and float64."""
+              open_y: bool = False, field: np.ndarray | None = None) -> dict:
+    """Sizes and centres of mass (Sec. 3.1), exact Q.8 and float64.  With
+    ``field``: the centres are the weighted centroids of Sec. 2 with the field
+    as density (quantised weights, ``weights``); sizes and the ambiguity flag
+    are those of the unweighted step, and ``w`` holds each component's total
+    weight."""
     lab = _c32(labels)
     ly, lx = lab.shape
     out = {k: np.zeros(K, dtype=np.int32) for k in ("n", "root", "qx", "qy", "amb")}
@@ -129,7 +138,25 @@ def centroids(labels: np.ndarray, K: int, conn: int = 8, open_x: bool = False,
                              _p(out["qx"], _i32p), _p(out["qy"], _i32p),
                              _p(out["fx"], _f64p), _p(out["fy"], _f64p),
                              _p(out["amb"], _i32p))
+    if field is not None:
+        f = np.ascontiguousarray(field, dtype=np.float32)
+        if f.shape != lab.shape:
+            raise ValueError("field and labels differ in shape")
+        out["w"] = np.zeros(K, dtype=np.int64)
+        if K:
+            _load().or_centroids_weighted(_p(lab, _i32p), _p(f, _f32p), lx, ly,
+                                          _open(open_x, open_y), int(K), _p(out["root"], _i32p),
+                                          _p(out["qx"], _i32p), _p(out["qy"], _i32p),
+                                          _p(out["fx"], _f64p), _p(out["fy"], _f64p),
+                                          _p(out["w"], ctypes.POINTER(ctypes.c_int64)))
     return out
+
+
+def weights(field: np.ndarray) -> np.ndarray:
+    """Quantised site weights of the weighted centroid (Sec. 2 density):
+    floor(256 rho + 1/2) clamped to [1, 65535], int64."""
+    v = np.floor(256.0 * np.asarray(field, dtype=np.float32).astype(np.float64) + 0.5)
+    return np.clip(np.nan_to_num(v, nan=1.0), 1, 65535).astype(np.int64)
 
 
 # ------------------------------------------------------------------- Sec. 3.2.1
@@ -289,11 +316,12 @@ class FrameResult:
 
 def frame(field: np.ndarray, threshold: float, phase: int = 0, conn: int = 8,
           nthreads: int = 0, obstacles=None, open_x: bool = False,
-          open_y: bool = False) -> FrameResult:
-    """Sec. 3.1 then Sec. 3.2.1-3.2.2 on one field."""
+          open_y: bool = False, weighted: bool = False) -> FrameResult:
+    """Sec. 3.1 then Sec. 3.2.1-3.2.2 on one field (``weighted``: the centres
+    are the density-weighted centroids of Sec. 2)."""
     g = dict(open_x=open_x, open_y=open_y)
     lab, K = label(field, threshold, phase, conn, obstacles, **g)
-    comps = centroids(lab, K, conn, **g)
+    comps = centroids(lab, K, conn, **g, field=field if weighted else None)
     ly, lx = lab.shape
     om = owner(lx, ly, comps["qx"], comps["qy"], nthreads, obstacles, **g)
     ab = edges(lx, ly, comps["qx"], comps["qy"], om, **g)
@@ -316,15 +344,16 @@ class Sequence:
 
     def __init__(self, threshold: float, phase: int = 0, conn: int = 8, nthreads: int = 0,
                  classify_events: bool = False, obstacles=None, open_x: bool = False,
-                 open_y: bool = False):
+                 open_y: bool = False, weighted: bool = False):
         self.threshold, self.phase, self.conn, self.nthreads = threshold, phase, conn, nthreads
         self.classify_events = classify_events
         self.obstacles, self.open_x, self.open_y = obstacles, open_x, open_y
+        self.weighted = weighted
         self.past: FrameResult | None = None
 
     def push(self, field: np.ndarray):
         now = frame(field, self.threshold, self.phase, self.conn, self.nthreads,
-                    self.obstacles, self.open_x, self.open_y)
+                    self.obstacles, self.open_x, self.open_y, self.weighted)
         res = compare(self.past, now, self.classify_events)
         self.past = now
         return now, res

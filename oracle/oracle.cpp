@@ -29,6 +29,7 @@
 // OpenMP over sites (each site is computed independently by the same loop).
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <set>
@@ -276,6 +277,70 @@ void or_centroids(const int32_t* labels, int32_t lx, int32_t ly, int32_t conn, i
         fx[l] = cx;
         fy[l] = cy;
         amb[l] = a[l];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2 (centroid equation with a density) -- the weighted variant of the
+// centres: the centroid of a component with the field as its density,
+// z = sum(w_s * y_s) / sum(w_s) over the member sites, y_s the member's
+// position unwrapped as above (minimum image from the root on a periodic
+// axis).  Reading: the density of a site is the field value rho_s quantised
+// to 1/256, w_s = floor(256 rho_s + 1/2), computed in float64 from the
+// float32 value, and clamped to [1, 65535] so that every site weighs
+// something and every sum stays exact in 64-bit integers.  The Q.8 centre
+// rounds 256 * sum(w dx) / sum(w) half up, as the unweighted one does with
+// n; the float64 centre is root + (double)sum(w dx) / (double)sum(w).  With
+// all weights equal this is the unweighted centre.  Sizes stay member counts.
+// ---------------------------------------------------------------------------
+int32_t quantised_weight(float rho) {
+    const double v = std::floor(256.0 * (double)rho + 0.5);
+    if (!(v >= 1.0)) return 1;      // (NaN cannot be inside)
+    if (v > 65535.0) return 65535;
+    return (int32_t)v;
+}
+
+int64_t round_half_up_q8(int64_t S, int64_t W) {
+    // floor(256 S / W + 1/2) = floor((512 S + W) / (2 W)), in 128-bit integers
+    const __int128 num = (__int128)512 * S + W, den = (__int128)2 * W;
+    __int128 q = num / den;
+    if ((num % den) != 0 && num < 0) q -= 1;
+    return (int64_t)q;
+}
+
+void or_centroids_weighted(const int32_t* labels, const float* field, int32_t lx, int32_t ly,
+                           int32_t open, int32_t K, int32_t* root_out, int32_t* qx, int32_t* qy,
+                           double* fx, double* fy, int64_t* wsum) {
+    const int64_t N = (int64_t)lx * ly;
+    std::vector<int64_t> rootv(K, -1), W(K, 0), sx(K, 0), sy(K, 0);
+    for (int64_t s = 0; s < N; ++s) {
+        const int32_t l = labels[s];
+        if (l >= 0 && rootv[l] < 0) rootv[l] = s;
+    }
+    const bool ox = open & 1, oy = open & 2;
+    for (int32_t y = 0; y < ly; ++y)
+        for (int32_t x = 0; x < lx; ++x) {
+            const int64_t s = (int64_t)y * lx + x;
+            const int32_t l = labels[s];
+            if (l < 0) continue;
+            const int64_t rx = rootv[l] % lx, ry = rootv[l] / lx;
+            const int64_t w = quantised_weight(field[s]);
+            W[l] += w;
+            sx[l] += w * axis_off(x - rx, lx, ox);
+            sy[l] += w * axis_off(y - ry, ly, oy);
+        }
+    for (int32_t l = 0; l < K; ++l) {
+        const int64_t rx = rootv[l] % lx, ry = rootv[l] / lx;
+        root_out[l] = (int32_t)rootv[l];
+        qx[l] = (int32_t)pos_mod(256 * rx + round_half_up_q8(sx[l], W[l]), 256LL * lx);
+        qy[l] = (int32_t)pos_mod(256 * ry + round_half_up_q8(sy[l], W[l]), 256LL * ly);
+        double cx = (double)rx + (double)sx[l] / (double)W[l];
+        double cy = (double)ry + (double)sy[l] / (double)W[l];
+        if (cx < 0) cx += lx; else if (cx >= lx) cx -= lx;
+        if (cy < 0) cy += ly; else if (cy >= ly) cy -= ly;
+        fx[l] = cx;
+        fy[l] = cy;
+        wsum[l] = W[l];
     }
 }
 
