@@ -69,7 +69,7 @@ __device__ __forceinline__ PastOf past_of(const Bufs *D, const Batch &G, int i) 
 
 #define MATCH_LANES 16
 __global__ __launch_bounds__(256) void k_match(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[G.idx[blockIdx.z]];
+    const Bufs B = D[G.idx[blockIdx.z]];
     if (B.fs->err) return;
     const PastOf P = past_of(D, G, blockIdx.z);
     if (!P.valid) return;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_diff(const Bufs *__restrict__ Dt, Batch
 __global__ __launch_bounds__(256) void k_events(const Bufs *__restrict__ Dt, Batch G) {
     __shared__ int rowR[4][64], rowT[4][64];
     const int i = blockIdx.z;
-    const Bufs &B = Dt[G.idx[i]];
+    const Bufs B = Dt[G.idx[i]];
     const FrameState *fs = B.fs;
     if (!B.classify || fs->err) return;
     const PastOf PO = past_of(Dt, G, i);

@@ -239,7 +239,7 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
 template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs &B = D[G.idx[e]];
+    const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
     __shared__ int L[DV_TILE_SITES];
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ uint16_t slot_of[DV_TILE_SITES];   // piece slot of each piece root
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch
 // order of segments is the row-major order of the [ly][ntx] arrays.
 __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.bbase, G.bpe, G.n, blockIdx.x);
-    const Bufs &B = D[G.idx[e]];
+    const Bufs B = D[G.idx[e]];
     __shared__ int pre[RES_TILES + 1];
     __shared__ int wsum[16];
     const int ty = blockIdx.x - G.bbase[e], t = threadIdx.x;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Ba
 // of its own: a last-block ticket in k_resolve would need a device-wide
 // release in every band's block.)
 __global__ __launch_bounds__(1024) void k_bandpre(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[G.idx[blockIdx.z]];
+    const Bufs B = D[G.idx[blockIdx.z]];
     __shared__ int wsum[16];
     const int K = block_exclusive_scan(B.band_sum, B.band_pre, B.nty, wsum);
     if (threadIdx.x == 0) {
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_rank(const Bufs *__restrict__ D, Batch 
     const int gt = blockIdx.x * (256 / RANK_LANES) + threadIdx.x / RANK_LANES;
     if (gt >= G.tiles) return;
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
-    const Bufs &B = D[G.idx[e]];
+    const Bufs B = D[G.idx[e]];
     const int tile = gt - G.tbase[e];
     const int x0 = (tile % B.ntx) * DV_TILE, y0 = (tile / B.ntx) * DV_TILE;
     const int lx = B.lx, j = threadIdx.x % RANK_LANES;
@@ -550,7 +550,7 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
 template <bool GEOM>
 __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs &B = D[G.idx[e]];
+    const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
     // piece slot of every site (0xffff outside), as written by k_tile_ccl
     __shared__ uint16_t L[DV_TILE_SITES];
     // per piece (indexed by its slot; a tile has at most 512 pieces): rank,

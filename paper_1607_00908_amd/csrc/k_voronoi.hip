@@ -28,7 +28,7 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[G.idx[blockIdx.z]];
+    const Bufs B = D[G.idx[blockIdx.z]];
     FrameState *fs = B.fs;
     const bool ok = fs->err == 0;
     const int K = fs->K_now;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, B
 // by cell).  (A kernel of its own: a last-block ticket in k_finalize would
 // need a device-wide release in every block.)
 __global__ __launch_bounds__(1024) void k_grid(const Bufs *__restrict__ D, Batch G) {
-    const Bufs &B = D[G.idx[blockIdx.z]];
+    const Bufs B = D[G.idx[blockIdx.z]];
     __shared__ int wsum[16];
     const FrameState *fs = B.fs;
     if (fs->err) return;
@@ -737,14 +737,18 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     for (int a = 0; a < 6; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) g[a][b] = S.own[(ys + a) * 34 + cx + b];
-    // vertex sites of the thread (frame gaps >= 3): bit i for row ys + i
+    // vertex sites of the thread (frame gaps >= 3): bit i for row ys + i.
+    // (The map pointer and flag are read once: the stores could alias the
+    // slot table as far as the compiler knows.)
+    const bool keep_maps = B.keep_maps;
+    const auto orow = gmem(B.owner) + ((size_t)(y0 + ys) * lx + x0 + cx);
     unsigned vmask = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ys + i;
         if (cx >= tw || y >= th) continue;
         const int ckk = g[i + 1][1];
-        if (B.keep_maps) gmem(B.owner)[(size_t)(y0 + y) * lx + x0 + cx] = ckk;
+        if (keep_maps) orow[(size_t)i * lx] = ckk;
         if (ckk == DV_EMPTY) continue;
         int f[8];
 #pragma unroll
@@ -894,16 +898,16 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     if (t == 0) gmem(B.tpair_n)[tile] = min(S.nout, DV_TILE_PAIRS);
 }
 
-// Rows from the tiles' couple lists: 16 lanes per tile (a tile lists a few
+// Rows from the tiles' couple lists: ROW_LANES lanes per tile (a tile lists a few
 // couples), one lane per couple end.  Rows are sets: a couple found by
 // several tiles is stored once.
-#define ROW_LANES 16
+#define ROW_LANES 4
 __global__ __launch_bounds__(256) void k_rows(const Bufs *__restrict__ D, Batch G) {
     const int gt = blockIdx.x * (256 / ROW_LANES) + (threadIdx.x / ROW_LANES);
     const int lane = threadIdx.x % ROW_LANES;
     if (gt >= G.tiles) return;
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
-    const Bufs &B = D[G.idx[e]];
+    const Bufs B = D[G.idx[e]];
     const int tile = gt - G.tbase[e];
     FrameState *fs = B.fs;
     if (fs->err) return;
