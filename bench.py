@@ -530,6 +530,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads for the CPU baseline (0: 1 below 4096^2, else up to 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weighted", action="store_true",
+                    help="density-weighted centres (the centroid of Sec. 2 with the field as density)")
     ap.add_argument("--no-unbatched", action="store_true",
                     help="skip the one-frame-per-launch comparison run")
     ap.add_argument("--no-extras", action="store_true",
@@ -577,6 +579,7 @@ def main():
         copy_probe(args.copy_probe_mib)
     t0 = time.perf_counter()
     frames, spec, geom = make_frames(args.workload, args.frames)
+    geom["weighted"] = bool(args.weighted)
     spec["name"] = args.workload
     ly, lx = frames[0].shape
     N = lx * ly
@@ -688,7 +691,8 @@ def main():
                    "mode": "maps+flips" if maps else "flips-only",
                    "walls": "".join(a for a in ("x", "y") if geom[f"open_{a}"]) or "none",
                    "obstacle_sites": int(geom["obstacles"].sum()) if has_obst else 0,
-                   "max_batch": batch, "parallelism": "single-gpu"},
+                   "max_batch": batch, "centres": "weighted" if args.weighted else "unit weight",
+                   "parallelism": "single-gpu"},
         "delivered": {"frames": len(got), "flips": n_flips,
                       "note": "every frame's record and flips copied to the host inside the "
                               "timed region"},

@@ -70,6 +70,11 @@ extern "C" {
 #define DV_OPEN_Y 16u    /* walls across y instead of the periodic wrap          */
 #define DV_KEEP_RESULTS 32u /* keep every frame's record and flips until
                                 dv_get_results returns them (Sec. 3.2.4, Sec. 4) */
+#define DV_WEIGHTED 64u  /* centres are the centroids of Sec. 2 with the field as
+                            density instead of the unit-weight centres of mass of
+                            Sec. 3.1: site weight floor(256 rho + 1/2) clamped to
+                            [1, 65535], exact integer sums, Q.8 rounded half up;
+                            sizes stay member counts */
 
 /* dv_flip.flags bits (with DV_CLASSIFY; Sec. 3.2.4, extraction of events).
  * Active points are the ends of the flips.  BULK: both ends are connected to

@@ -244,6 +244,7 @@ dv_status flush(dv_ctx *c) {
     G.nty = H.nty;
     G.classify = H.classify;
     G.geom = (H.open_x | H.open_y | (H.obst != nullptr)) ? 1 : 0;
+    G.weighted = H.weighted;
     launch_label(G, c->pending, c->stream, c->prof);
     launch_voronoi(G, c->stream, c->prof);
     launch_compare(G, c->stream, c->prof);
@@ -305,7 +306,8 @@ dv_status check_cfg(const dv_config *cfg) {
     if (cfg->max_degree != 0 && (cfg->max_degree < 4 || cfg->max_degree > 64))
         return fail(nullptr, DV_ERR_ARG, "max_degree must be 0 or in [4, 64]");
     if (cfg->threshold != cfg->threshold) return fail(nullptr, DV_ERR_ARG, "threshold is NaN");
-    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y | DV_KEEP_RESULTS))
+    if (cfg->flags & ~(DV_KEEP_MAPS | DV_CLASSIFY | DV_OBSTACLES | DV_OPEN_X | DV_OPEN_Y | DV_KEEP_RESULTS |
+                       DV_WEIGHTED))
         return fail(nullptr, DV_ERR_ARG, "unknown flag bits");
     if (cfg->max_batch < 0 || cfg->max_batch > DV_MAX_BATCH)
         return fail(nullptr, DV_ERR_ARG, "max_batch must be 0 or in [1, 64]");
@@ -358,6 +360,7 @@ Bufs table_base(const dv_config &cfg) {
     B.classify = (cfg.flags & DV_CLASSIFY) ? 1 : 0;
     B.open_x = (cfg.flags & DV_OPEN_X) ? 1 : 0;
     B.open_y = (cfg.flags & DV_OPEN_Y) ? 1 : 0;
+    B.weighted = (cfg.flags & DV_WEIGHTED) ? 1 : 0;
     return B;
 }
 
@@ -376,6 +379,7 @@ void place_slot(Carve &cv, Bufs &b) {
     b.band_pre = cv.take<int32_t>(b.nty);
     b.acc_x = cv.take<long long>(K);
     b.acc_y = cv.take<long long>(K);
+    b.acc_w = cv.take<long long>(K);
     b.acc_n = cv.take<int32_t>(K);
     b.acc_amb = cv.take<int32_t>(K);
     b.acc_root = cv.take<int32_t>(K);
@@ -559,6 +563,7 @@ dv_status dv_create(const dv_config *cfg_in, void *hip_stream, dv_ctx **out) {
         const Bufs &b = c->h_tab[k];
         z = hipMemsetAsync(b.acc_x, 0, K * sizeof(long long), s0) == hipSuccess &&
             hipMemsetAsync(b.acc_y, 0, K * sizeof(long long), s0) == hipSuccess &&
+            hipMemsetAsync(b.acc_w, 0, K * sizeof(long long), s0) == hipSuccess &&
             hipMemsetAsync(b.acc_n, 0, K * sizeof(int), s0) == hipSuccess &&
             hipMemsetAsync(b.acc_amb, 0, K * sizeof(int), s0) == hipSuccess &&
             hipMemsetAsync(b.fs, 0, sizeof(FrameState), s0) == hipSuccess &&
@@ -990,6 +995,7 @@ dv_status dv_group_push_some(dv_group *g, const int32_t *members, const float *c
         G.nty = std::max(G.nty, b.nty);
         G.classify |= b.classify;
         G.geom |= (b.open_x | b.open_y | (b.obst != nullptr)) ? 1 : 0;
+        G.weighted |= b.weighted;
         alike = alike && b.ncells == g->h_tab[members[0]].ncells && b.nty == g->h_tab[members[0]].nty;
     }
     G.tiles = G.tbase[n];

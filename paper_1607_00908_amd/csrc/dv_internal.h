@@ -97,6 +97,7 @@ struct Bufs {
     int32_t keep_maps;     // write the label / owner maps
     int32_t classify;      // fill the flips' event flags
     int32_t open_x, open_y;  // 1: walls across that axis instead of wrapping
+    int32_t weighted;      // centres weighted by the quantised field (DV_WEIGHTED)
     const uint8_t *obst;   // [N] obstacle sites (nonzero), or null: none
     int32_t *parent;       // [N] union-find over piece roots (linear site indices)
     uint16_t *bpc;         // [tiles][DV_BORDER] tile-local piece root of every tile-border
@@ -116,7 +117,8 @@ struct Bufs {
     int32_t *band_sum;     // [nty] roots per band of 32 rows
     int32_t *band_pre;     // [nty] roots in the bands before each band
     // component accumulation (self-cleaning: finalize zeroes what it reads)
-    long long *acc_x, *acc_y;
+    long long *acc_x, *acc_y;   // sums of offsets from the root (weighted: of w * offset)
+    long long *acc_w;           // [K_max] sums of the site weights (weighted centres only)
     int32_t *acc_n, *acc_amb, *acc_root;
     // bucket grid of the frame's centres
     int32_t *cell_count;   // [ncells]
@@ -174,6 +176,7 @@ struct Batch {
     int kmax, nty;         // largest K_max and band count (launch shapes)
     int classify;          // some entry classifies events
     int geom;              // some entry has walls or obstacles (general kernels)
+    int weighted;          // some entry has weighted centres
     int idx[DV_MAX_ENTRIES];        // table row of each entry
     uint32_t pslot[DV_MAX_ENTRIES]; // results-page position of each entry (DV_PG_*)
     int tbase[DV_MAX_ENTRIES + 1];  // first flat tile of each entry

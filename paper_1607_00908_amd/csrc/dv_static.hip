@@ -42,7 +42,7 @@ dv_status scratch_on(int device, char **out) {
 }
 
 // Words to fill at the start of a call: ranges of 32-bit words.
-#define DV_FILLS 16
+#define DV_FILLS 18
 struct Fills {
     int *p[DV_FILLS];
     long long n[DV_FILLS];
@@ -165,6 +165,7 @@ extern "C" dv_status dv_compare_static(const dv_config *cfg_in, void *hip_stream
     for (int k = 0; k < 2; ++k) {
         add(tab[k].acc_x, 2 * K, 0);
         add(tab[k].acc_y, 2 * K, 0);
+        add(tab[k].acc_w, 2 * K, 0);
         add(tab[k].acc_n, K, 0);
         add(tab[k].acc_amb, K, 0);
         add(tab[k].fs, sizeof(FrameState) / 4, 0);
@@ -198,6 +199,7 @@ extern "C" dv_status dv_compare_static(const dv_config *cfg_in, void *hip_stream
     G.nty = B.nty;
     G.classify = B.classify;
     G.geom = (B.open_x | B.open_y) ? 1 : 0;
+    G.weighted = B.weighted;
     Fields F;
     std::memset(&F, 0, sizeof(F));
     F.p[0] = past_field;

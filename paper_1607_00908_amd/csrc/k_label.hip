@@ -547,8 +547,17 @@ __device__ __forceinline__ int wrap_off(int v, int L) {
     return v;
 }
 
-template <bool GEOM>
-__global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G) {
+// Site weight of the density-weighted centres (centroid equation of Sec. 2):
+// the field value quantised to 1/256, clamped to [1, 65535] (float64, exact).
+__device__ __forceinline__ int site_weight(float rho) {
+    const double v = floor(256.0 * (double)rho + 0.5);
+    return !(v >= 1.0) ? 1 : (v > 65535.0 ? 65535 : (int)v);
+}
+
+// WT: some entry of the launch has weighted centres (its runs read the field
+// again for the site weights; the other entries' sums are the unit-weight ones).
+template <bool GEOM, bool WT>
+__global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D, Batch G, Fields F) {
     const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
     const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
     // piece slot of every site (0xffff outside), as written by k_tile_ccl
@@ -558,6 +567,10 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     __shared__ int prank[DV_TILE_SITES / 2];
     __shared__ uint32_t pxy[DV_TILE_SITES / 2];
     __shared__ int psx[DV_TILE_SITES / 2], psy[DV_TILE_SITES / 2], pn[DV_TILE_SITES / 2];
+    // weighted sums per piece: w * dx, w * dy, w (64-bit)
+    __shared__ long long wsx[WT ? DV_TILE_SITES / 2 : 1], wsy[WT ? DV_TILE_SITES / 2 : 1],
+        wsw[WT ? DV_TILE_SITES / 2 : 1];
+    const bool wt = WT && B.weighted;
     __shared__ uint32_t rowm[DV_TILE];
     __shared__ uint16_t runs[DV_TILE_SITES / 2];   // (row << 5) | first column of each run
     __shared__ int nruns;
@@ -594,6 +607,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         psx[k] = 0;
         psy[k] = 0;
         pn[k] = 0;
+        if (WT) wsx[k] = wsy[k] = wsw[k] = 0;
     }
     __syncthreads();
 
@@ -657,9 +671,25 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
             sxr = 0;
             for (int j = 0; j < len; ++j) sxr += wrap_off(x0 + a + j - prx, wlx);
         }
-        atomicAdd(&psx[r], sxr);
-        atomicAdd(&psy[r], dy * len);
         atomicAdd(&pn[r], len);
+        if (wt) {
+            // the run's sites with their weights (the field row is read again)
+            const float *frow = F.p[e] + (size_t)(y0 + y) * lx + x0 + a;
+            long long swx = 0;
+            int sw = 0;
+            for (int j = 0; j < len; ++j) {
+                const int w = site_weight(frow[j]);
+                const int dxj = straight ? dx + j : wrap_off(x0 + a + j - prx, wlx);
+                swx += (long long)w * dxj;
+                sw += w;
+            }
+            atomicAdd((unsigned long long *)&wsx[r], (unsigned long long)swx);
+            atomicAdd((unsigned long long *)&wsy[r], (unsigned long long)((long long)dy * sw));
+            atomicAdd((unsigned long long *)&wsw[r], (unsigned long long)sw);
+        } else {
+            atomicAdd(&psx[r], sxr);
+            atomicAdd(&psy[r], dy * len);
+        }
         if (dy == hiy || !straight || (dx <= hix && hix <= dx_end)) {
             bool amb = false;
             const int gy = y0 + y;
@@ -689,8 +719,14 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     for (int k = t; k < np; k += DV_BLOCK) {
         const int rank = prank[k];
         if (rank >= B.kmax) continue;
-        atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)(long long)psx[k]);
-        atomicAdd((unsigned long long *)&B.acc_y[rank], (unsigned long long)(long long)psy[k]);
+        if (wt) {
+            atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)wsx[k]);
+            atomicAdd((unsigned long long *)&B.acc_y[rank], (unsigned long long)wsy[k]);
+            atomicAdd((unsigned long long *)&B.acc_w[rank], (unsigned long long)wsw[k]);
+        } else {
+            atomicAdd((unsigned long long *)&B.acc_x[rank], (unsigned long long)(long long)psx[k]);
+            atomicAdd((unsigned long long *)&B.acc_y[rank], (unsigned long long)(long long)psy[k]);
+        }
         atomicAdd(&B.acc_n[rank], pn[k]);
     }
 }
@@ -713,7 +749,12 @@ void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     hipLaunchKernelGGL(k_rank, dim3((G.tiles + 256 / RANK_LANES - 1) / (256 / RANK_LANES)), dim3(256), 0, s, G.D, G);
     P.end(ST_RESOLVE, s);
     P.begin(ST_RELABEL, s);
-    if (G.geom) hipLaunchKernelGGL(k_relabel<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
-    else hipLaunchKernelGGL(k_relabel<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G);
+    if (G.weighted) {
+        if (G.geom) hipLaunchKernelGGL((k_relabel<true, true>), dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+        else hipLaunchKernelGGL((k_relabel<false, true>), dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+    } else {
+        if (G.geom) hipLaunchKernelGGL((k_relabel<true, false>), dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+        else hipLaunchKernelGGL((k_relabel<false, false>), dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+    }
     P.end(ST_RELABEL, s);
 }

@@ -27,6 +27,14 @@ __device__ __forceinline__ long long pmod64(long long v, long long m) {
     return r < 0 ? r + m : r;
 }
 
+// floor(256 S / W + 1/2) for W > 0 without forming 512 S (a weighted sum can
+// use most of the 64 bits): with S = q W + r, 0 <= r < W, it is
+// 256 q + floor((512 r + W) / (2 W)), and 512 r stays far below 2^63.
+__device__ __forceinline__ long long q8_round(long long S, long long W) {
+    const long long q = floor_div(S, W), r = S - q * W;
+    return 256 * q + (512 * r + W) / (2 * W);
+}
+
 __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, Batch G) {
     const Bufs B = D[G.idx[blockIdx.z]];
     FrameState *fs = B.fs;
@@ -44,10 +52,16 @@ __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, B
             B.acc_y[k] = 0;
             B.acc_amb[k] = 0;
             const int rx = root % B.lx, ry = root / B.lx;
-            const int qx = (int)pmod64(256LL * rx + floor_div(512 * sx + n, 2 * n), 256LL * B.lx);
-            const int qy = (int)pmod64(256LL * ry + floor_div(512 * sy + n, 2 * n), 256LL * B.ly);
-            double fx = (double)rx + (double)sx / (double)n;
-            double fy = (double)ry + (double)sy / (double)n;
+            // weighted centres divide by the total weight, the others by n
+            long long W = n;
+            if (B.weighted) {
+                W = B.acc_w[k];
+                B.acc_w[k] = 0;
+            }
+            const int qx = (int)pmod64(256LL * rx + q8_round(sx, W), 256LL * B.lx);
+            const int qy = (int)pmod64(256LL * ry + q8_round(sy, W), 256LL * B.ly);
+            double fx = (double)rx + (double)sx / (double)W;
+            double fy = (double)ry + (double)sy / (double)W;
             if (fx < 0) fx += B.lx; else if (fx >= B.lx) fx -= B.lx;
             if (fy < 0) fy += B.ly; else if (fy >= B.ly) fy -= B.ly;
             C.qx[k] = qx;
@@ -74,6 +88,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const Bufs *__restrict__ D, B
             B.acc_x[k] = 0;
             B.acc_y[k] = 0;
             B.acc_amb[k] = 0;
+            if (B.weighted) B.acc_w[k] = 0;
         }
     }
 }

@@ -26,6 +26,7 @@ OBSTACLES = 4
 OPEN_X = 8
 OPEN_Y = 16
 KEEP_RESULTS = 32
+WEIGHTED = 64        # centres weighted by the quantised field (Sec. 2 centroid)
 FLIP_BULK, FLIP_BOUNDARY = 1, 2
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_STATE, ERR_INTERNAL = range(7)
@@ -162,10 +163,12 @@ def _frame_info(fi: DVFrameInfo) -> FrameInfo:
 
 
 def _config(lx, ly, threshold, phase, connectivity, max_components, max_degree, device, keep_maps,
-            max_batch, classify, open_x, open_y, with_obstacles, keep_results) -> DVConfig:
+            max_batch, classify, open_x, open_y, with_obstacles, keep_results,
+            weighted=False) -> DVConfig:
     flags = ((KEEP_MAPS if keep_maps else 0) | (CLASSIFY if classify else 0)
              | (OPEN_X if open_x else 0) | (OPEN_Y if open_y else 0)
-             | (KEEP_RESULTS if keep_results else 0) | (OBSTACLES if with_obstacles else 0))
+             | (KEEP_RESULTS if keep_results else 0) | (OBSTACLES if with_obstacles else 0)
+             | (WEIGHTED if weighted else 0))
     return DVConfig(ctypes.sizeof(DVConfig), int(lx), int(ly), float(threshold), int(phase),
                     int(connectivity), int(max_components), int(max_degree), int(device),
                     flags, int(max_batch))
@@ -175,12 +178,12 @@ def device_bytes(lx: int, ly: int, threshold: float = 0.5, phase: int = PHASE_AB
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
                  keep_maps: bool = True, max_batch: int = 0, classify: bool = False,
                  open_x: bool = False, open_y: bool = False, with_obstacles: bool = False,
-                 keep_results: bool = False) -> int:
+                 keep_results: bool = False, weighted: bool = False) -> int:
     """Device memory a Detector of this configuration allocates (the library's
     own layout; no device is touched)."""
     lib = load()
     cfg = _config(lx, ly, threshold, phase, connectivity, max_components, max_degree, 0, keep_maps,
-                  max_batch, classify, open_x, open_y, with_obstacles, keep_results)
+                  max_batch, classify, open_x, open_y, with_obstacles, keep_results, weighted)
     out = ctypes.c_uint64(0)
     st = lib.dv_device_bytes(ctypes.byref(cfg), ctypes.byref(out))
     if st != OK:
@@ -203,19 +206,23 @@ class Detector:
     axis instead of the periodic wrap.  ``obstacles``: a [ly, lx] mask
     (nonzero = obstacle; numpy array or device tensor) set at creation; it can
     be replaced later with ``set_obstacles`` (the context then holds a mask
-    even when this is None, with ``with_obstacles=True``).
+    even when this is None, with ``with_obstacles=True``).  ``weighted``: the
+    centres are the centroids of Sec. 2 with the field as density (site weight
+    floor(256 rho + 1/2) clamped to [1, 65535]) instead of the unit-weight
+    centres of mass.
     """
 
     def __init__(self, lx: int, ly: int, threshold: float, phase: int = PHASE_ABOVE,
                  connectivity: int = 8, max_components: int = 4096, max_degree: int = 0,
                  device: int = 0, keep_maps: bool = True, stream=None, max_batch: int = 0,
                  classify: bool = False, open_x: bool = False, open_y: bool = False,
-                 obstacles=None, with_obstacles: bool = False, keep_results: bool = False):
+                 obstacles=None, with_obstacles: bool = False, keep_results: bool = False,
+                 weighted: bool = False):
         self.lib = load()
         self.lx, self.ly = int(lx), int(ly)
         cfg = _config(self.lx, self.ly, threshold, phase, connectivity, max_components, max_degree,
                       device, keep_maps, max_batch, classify, open_x, open_y,
-                      with_obstacles or obstacles is not None, keep_results)
+                      with_obstacles or obstacles is not None, keep_results, weighted)
         import torch
         self._torch = torch
         self.device = torch.device("cuda", int(device))

@@ -47,7 +47,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(lx=2), dict(ly=0), dict(lx=70000), dict(lx=65536, ly=65536), dict(phase=2),
     dict(connectivity=6), dict(max_components=0), dict(max_components=(1 << 24) + 1),
-    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=64), dict(flags=0x80000000),
+    dict(max_degree=3), dict(max_degree=65), dict(threshold=float("nan")), dict(flags=128), dict(flags=0x80000000),
     dict(max_batch=-1), dict(max_batch=65)])
 def test_invalid_config_is_rejected_on_the_host(bad):
     lib = dv.load()

@@ -90,19 +90,21 @@ def check_results(res, refs, tag=""):
 
 
 def run_sequence(fields, thr, phase=0, conn=8, kmax=None, maps=True, max_degree=0, tag="",
-                 classify=False, open_x=False, open_y=False, obstacles=None):
+                 classify=False, open_x=False, open_y=False, obstacles=None, weighted=False,
+                 max_batch=0):
     ly, lx = fields[0].shape
     if kmax is None:
         kmax = lx * ly
     det = dv.Detector(lx, ly, thr, phase, conn, max_components=kmax, max_degree=max_degree,
                       keep_maps=maps, classify=classify, open_x=open_x, open_y=open_y,
-                      obstacles=obstacles, keep_results=True)
+                      obstacles=obstacles, keep_results=True, weighted=weighted,
+                      max_batch=max_batch)
     seq = oracle.Sequence(thr, phase, conn, NTHREADS, classify_events=classify,
-                          obstacles=obstacles, open_x=open_x, open_y=open_y)
+                          obstacles=obstacles, open_x=open_x, open_y=open_y, weighted=weighted)
     refs = []
     for i, f in enumerate(fields):
         say(f"  [{tag}] frame {i} {lx}x{ly} conn={conn} phase={phase} open={int(open_x)}{int(open_y)}"
-            f" obstacles={obstacles is not None}")
+            f" obstacles={obstacles is not None} weighted={weighted}")
         det.push(torch.from_numpy(np.ascontiguousarray(f)).to("cuda"))
         now, ref = seq.push(f)
         refs.append((now, ref))
@@ -921,3 +923,90 @@ def test_walled_sparse_cluster_exercises_candidate_overflow():
     for ox, oy in ((True, True), (True, False)):
         run_sequence([f, g], 0.5, kmax=2048, tag="wcluster", open_x=ox, open_y=oy,
                      obstacles=obst)
+
+
+# ------------------------------------------------------- density-weighted centres
+@pytest.mark.parametrize("seed", range(8))
+def test_weighted_centres_moving_disks(seed):
+    """Centres as the centroids of Sec. 2 with the field as density: disks with
+    smooth interfaces, so the weights vary inside every component and the
+    weighted centres differ from the unit-weight ones."""
+    rng = np.random.default_rng(9100 + seed)
+    lx, ly = int(rng.integers(40, 200)), int(rng.integers(40, 200))
+    sim = synth.DiskSim(lx, ly, int(rng.integers(3, 30)), 3.0, 7.0, 0.7, 3e-3, seed=9200 + seed)
+    fields = list(sim.frames(4))
+    conn = 8 if seed % 2 else 4
+    now = run_sequence(fields, 0.3, conn=conn, tag=f"weighted{seed}", weighted=True)
+    plain = oracle.frame(fields[-1], 0.3, conn=conn)
+    assert np.any(now.comps["qx"] != plain.comps["qx"]) or np.any(now.comps["qy"] != plain.comps["qy"])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_centres_random_fields_walls_and_obstacles(seed):
+    """Uniform-noise fields (weights 1..256 per site, bubbles clamped at one
+    unit), walls and obstacles in turn, both phases."""
+    rng = np.random.default_rng(9300 + seed)
+    lx, ly = int(rng.integers(3, 90)), int(rng.integers(3, 90))
+    conn = int(rng.choice([4, 8]))
+    phase = seed % 2
+    ox, oy = [(False, False), (True, False), (False, True), (True, True)][seed % 4]
+    obst = rng.random((ly, lx)) < 0.1 if seed % 3 == 0 else None
+    thr = 0.4 if phase == 1 else 0.6
+    fields = [synth.tiny_random_field(lx, ly, 9400 + 7 * seed + k) for k in range(3)]
+    run_sequence(fields, thr, phase, conn, tag=f"wrand{seed}", open_x=ox, open_y=oy,
+                 obstacles=obst, weighted=True)
+
+
+@pytest.mark.parametrize("depth", [4, 32])
+def test_weighted_centres_batched(depth):
+    """Batches of weighted frames: every frame's results against the oracle."""
+    lx, ly = 256, 192
+    sim = synth.DiskSim(lx, ly, 40, 4.0, 8.0, 0.6, 3e-3, seed=9500 + depth)
+    frames = list(sim.frames(2 * depth + 3))
+    det = dv.Detector(lx, ly, 0.3, max_components=256, max_batch=depth, keep_results=True,
+                      weighted=True)
+    seq = oracle.Sequence(0.3, 0, 8, NTHREADS, weighted=True)
+    refs = []
+    for f in frames:
+        refs.append(seq.push(f))
+        det.push(torch.from_numpy(f).cuda())
+    say(f"  [weighted batch{depth}] {len(frames)} frames")
+    check_frame(det, refs[-1][0], refs[-1][1], lx, ly)
+    check_results(det.results(), refs, f"weighted batch{depth}")
+    det.close()
+
+
+def test_group_of_weighted_and_unweighted_members():
+    """One launch per stage over members with and without weighted centres:
+    each member's frames equal its own oracle."""
+    sizes = [(96, 80), (128, 128), (70, 150), (200, 100)]
+    weighted = [True, False, True, False]
+    sims = [synth.DiskSim(lx, ly, max(3, lx * ly // 2000), 3.0, 7.0, 0.7, 3e-3, seed=9600 + i)
+            for i, (lx, ly) in enumerate(sizes)]
+    frames = [list(sm.frames(4)) for sm in sims]
+    stream = torch.cuda.Stream()
+    dets = [dv.Detector(lx, ly, 0.3, max_components=512, max_batch=2, stream=stream,
+                        keep_results=True, weighted=w) for (lx, ly), w in zip(sizes, weighted)]
+    grp = dv.Group(dets)
+    seqs = [oracle.Sequence(0.3, 0, 8, NTHREADS, weighted=w) for w in weighted]
+    refs = [[] for _ in sizes]
+    for k in range(4):
+        say(f"  [weighted group] frame {k}")
+        grp.push([torch.from_numpy(frames[i][k]).cuda() for i in range(len(sizes))])
+        for i, (lx, ly) in enumerate(sizes):
+            now, ref = seqs[i].push(frames[i][k])
+            refs[i].append((now, ref))
+            check_frame(dets[i], now, ref, lx, ly)
+    for i in range(len(sizes)):
+        check_results(dets[i].results(), refs[i], f"weighted group member {i}")
+    grp.close()
+    for d in dets:
+        d.close()
+
+
+def test_weighted_centres_grf1024():
+    """A 1024^2 random field (weights up to a few thousand units, components
+    across the seams) with weighted centres, in one batch of four."""
+    sim = synth.GRFSim(1024, 1024, 6.0, 0.98, seed=9700)
+    run_sequence(list(sim.frames(4)), 1.0, kmax=8192, tag="weighted grf1024", weighted=True,
+                 max_batch=4)

@@ -36,7 +36,7 @@ def _static(lib, cfg, past, now, cap, stream):
 
 def _context(lx, ly, kmax, past, now, flags=0):
     det = dv.Detector(lx, ly, 0.5, max_components=kmax, keep_maps=False,
-                      classify=bool(flags & dv.CLASSIFY))
+                      classify=bool(flags & dv.CLASSIFY), weighted=bool(flags & dv.WEIGHTED))
     det.push(past)
     det.push(now)
     fi, fl = det.info(), det.flips()
@@ -63,6 +63,22 @@ def test_static_entry_point_equals_the_context_path():
         got_fi2, got_fl2 = _static(lib, _cfg(lx, ly, 512), past, now, 1, stream)
         assert got_fi2.n_flips == want_fi.n_flips
         assert np.array_equal(got_fl2[:1], want_fl[:1])
+
+
+def test_static_entry_point_weighted_centres():
+    """The same with density-weighted centres (two calls, the second smaller)."""
+    lib = dv.load()
+    stream = torch.cuda.Stream()
+    for lx, ly, nd, seed in [(260, 220, 40, 5), (120, 100, 12, 6)]:
+        sim = synth.DiskSim(lx, ly, nd, 4.0, 7.0, 1.2, 4e-3, seed=500 + seed)
+        frames = list(sim.frames(6))
+        past = torch.from_numpy(frames[0]).cuda()
+        now = torch.from_numpy(frames[5]).cuda()
+        torch.cuda.synchronize()
+        want_fi, want_fl = _context(lx, ly, 512, past, now, dv.WEIGHTED)
+        got_fi, got_fl = _static(lib, _cfg(lx, ly, 512, dv.WEIGHTED), past, now, 4096, stream)
+        assert got_fi == want_fi, (lx, ly)
+        assert np.array_equal(got_fl[:got_fi.n_flips], want_fl), (lx, ly)
 
 
 def test_static_entry_point_rejects_what_does_not_fit():
