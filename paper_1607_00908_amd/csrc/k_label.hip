@@ -590,9 +590,11 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         u[i] = gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + (ok ? y * 32 + cx : 0)];
     }
     const int np = gmem(B.npieces)[tile];
-    // (slot t is read whether or not it is in use: the slots of a tile are
-    // all allocated)
-    const int2 pr0 = ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + t);
+    // the first wave reads the ranks of slots 0..63 at once, in use or not (a
+    // tile usually has a few pieces; the slots are allocated): 512 bytes per
+    // tile, and no load that waits for the piece count
+    int2 pr0 = make_int2(0, 0);
+    if (t < 64) pr0 = ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + t);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ry + 8 * i;
@@ -601,7 +603,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
     // each piece (thread t takes slot t; at most 512): rank and component
     // root as k_rank found them
     for (int k = t; k < np; k += DV_BLOCK) {
-        const int2 pr = k == t ? pr0 : ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + k);
+        const int2 pr = (k == t && t < 64) ? pr0 : ld_int2(B.prec, (size_t)tile * (DV_TILE_SITES / 2) + k);
         prank[k] = pr.x;
         pxy[k] = (uint32_t)pr.y;
         psx[k] = 0;
