@@ -146,57 +146,101 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
     return out ? 32 - __clz(out) : 0;
 }
 
-// Labels the inside sites of one tile with tile-local union-find.  On return
-// (after a barrier) L[L[s]] is the smallest tile-local index of the piece of
-// an inside site s (L[s] is that index for the first site of a run, else the
-// run's first site), and L[s] is -1 when s is outside or beyond the lattice.
-// rowm: LDS [32] row masks.
-//
-// Runs of a row are connected by construction (each site points to its run's
-// first site).  Runs of consecutive rows are united once per touching pair,
-// by one lane per row.
+// One wave per tile, four tiles per block (GEOM: some entry of the launch has
+// walls or obstacles; the periodic, unobstructed instance carries none of
+// their tests).  Lane l takes column l & 31 and the rows (l >> 5) + 2k,
+// k = 0..15, so that every wave load covers two whole rows.  A wave works on
+// its own tile from start to end: it waits for nothing but its own LDS
+// accesses, so the four tiles of a block overlap their latencies.
 template <bool GEOM>
-__device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int tw, int th, int *L,
-                         uint32_t *rowm) {
-    const int t = threadIdx.x, cx = t & 31, ry = t >> 5, lane = t & 63;
-    // the four loads are issued together (an out-of-tile lane reads the tile
-    // origin and ignores it)
-    float v[4];
-    uint8_t ob[4] = {0, 0, 0, 0};   // obstacle sites are never inside
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i;
-        const bool ok = cx < tw && y < th;
-        const size_t g = ok ? (size_t)(y0 + y) * B.lx + x0 + cx : (size_t)y0 * B.lx + x0;
-        v[i] = field[g];
-        if (GEOM && B.obst) ob[i] = gmem(B.obst)[g];
+__global__ __launch_bounds__(256, 8) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
+    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gt >= G.tiles) return;   // a whole wave; there is no block barrier below
+    const int e = entry_of(G.tbase, G.tpe, G.n, gt);
+    const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
+    // per wave: tile-local union-find (after the slots are assigned, a piece
+    // root's entry also holds its slot in bits 16..), row masks
+    __shared__ int Ls[4][DV_TILE_SITES];
+    __shared__ uint32_t rowms[4][DV_TILE];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int *L = Ls[w];
+    uint32_t *rowm = rowms[w];
+    const int tile = gt - G.tbase[e];
+    const int tx = tile % B.ntx, ty = tile / B.ntx;
+    const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
+    const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
+    FrameState *fs = B.fs;
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    // per-frame resets spread over the grid
+    if (tile == 0 && lane == 0) {
+        fs->K_now = 0;
+        fs->err = 0;
+        fs->n_amb = 0;
+        fs->E2_acc = 0;
+        fs->excl_acc = 0;
+        fs->nb_acc = 0;
+        fs->na_acc = 0;
     }
-    int rs[4];   // first column of each site's run (-1 outside)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i;
-        const bool in = cx < tw && y < th && !ob[i] && is_in(v[i], B.thr, B.phase);
-        const unsigned long long bal = __ballot(in);
-        const uint32_t m = (uint32_t)(lane < 32 ? bal : (bal >> 32));
-        if (cx == 0) rowm[y] = m;
-        rs[i] = in ? run_start(m, cx) : -1;
-        L[y * 32 + cx] = in ? y * 32 + rs[i] : -1;
+    if (lane == 0) B.cell_count[tile] = 0;
+    if (lane < th) gmem(B.seg_mask)[(size_t)(y0 + lane) * B.ntx + tx] = 0u;
+    {   // empty the rows this frame will fill
+        const size_t total = (size_t)fs->rows_dirty * B.maxdeg;
+        const size_t stride = (size_t)B.ncells * 64;
+        auto adj = gmem(B.cur.adj);
+        for (size_t i = (size_t)tile * 64 + lane; i < total; i += stride) adj[i] = DV_EMPTY;
     }
-    __syncthreads();
+
+    const int cx = lane & 31, h = lane >> 5;
+    // the field (and obstacle) values of the lane's sites, loads issued
+    // together; beyond a ragged tile's edge a lane reads the nearest site of
+    // the tile and ignores it
+    const float *field = F.p[e];
+    const size_t tbase = (size_t)y0 * B.lx + x0;
+    const int xc = min(cx, tw - 1);
+    // inside masks of the rows, each site pointing to its run's first site;
+    // in two halves of eight sites (fewer values live at once)
+    unsigned starts = 0;   // bit k: the lane's site k starts a run
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        float v[8];
+        uint8_t ob[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * half + j;
+            const size_t g = tbase + (size_t)(min(h + 2 * k, th - 1) * B.lx + xc);
+            v[j] = field[g];
+            ob[j] = (GEOM && B.obst) ? gmem(B.obst)[g] : (uint8_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * half + j, y = h + 2 * k;
+            const bool in = cx < tw && y < th && !ob[j] && (B.phase == 0 ? (v[j] > B.thr) : (v[j] < B.thr));
+            const unsigned long long bal = __ballot(in);
+            const uint32_t m = (uint32_t)(h == 0 ? bal : (bal >> 32));
+            if (cx == 0) rowm[y] = m;
+            const int rs = in ? run_start(m, cx) : -1;
+            L[y * 32 + cx] = in ? y * 32 + rs : -1;
+            starts |= (rs == cx) ? 1u << k : 0u;
+        }
+    }
+    wave_sync();
     // Unions of each run [a, b] with the runs of the row above that touch
     // it: columns a - 1 .. b + 1 (8-connectivity) or a .. b (4): the run
     // holding the lowest touching site of the row above, and every other
-    // run of that row starting inside the span.  Lane y of the first wave
-    // takes row y.
-    if (t < 32 && t >= 1 && t < th) {
-        const int y = t;
+    // run of that row starting inside the span.  Lane y takes row y.
+    if (lane >= 1 && lane < 32 && lane < th) {
+        const int y = lane;
         const uint32_t m = rowm[y], up = rowm[y - 1];
         if (m && up) {
             const uint32_t st_up = up & ~(up << 1);
-            uint32_t starts = m & ~(m << 1);
-            while (starts) {
-                const int a = __ffs(starts) - 1;
-                starts &= starts - 1;
+            uint32_t rst = m & ~(m << 1);
+            while (rst) {
+                const int a = __ffs(rst) - 1;
+                rst &= rst - 1;
                 const uint32_t rest = ~(m >> a);            // bit k clear: a + k inside
                 const int b = rest ? a + __ffs(rest) - 2 : 31;
                 const int lo = (B.conn == 8 && a > 0) ? a - 1 : a;
@@ -216,96 +260,66 @@ __device__ void tile_ccl(const Bufs &B, const float *field, int x0, int y0, int 
             }
         }
     }
-    __syncthreads();
-    // roots of the run starts.  The roots are stored only after a barrier: a
-    // find that is still shortening its path could otherwise overwrite a
-    // stored root with an intermediate ancestor.  Other inside sites keep
-    // pointing at their run start.
-    int root[4];
+    wave_sync();
+    // roots of the run starts, stored once every find has ended (a find that
+    // is still shortening its path could otherwise replace a stored root with
+    // an intermediate ancestor); other inside sites keep pointing at their
+    // run start
+    unsigned rootp[8];   // roots of sites 2j and 2j + 1 in the low / high half (0xffff: none)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
-        root[i] = (rs[i] == cx && L[s] < s) ? lfind(L, s) : -1;
+    for (int k = 0; k < 16; ++k) {
+        const int s = (h + 2 * k) * 32 + cx;
+        const unsigned r = ((starts >> k) & 1u) && L[s] < s ? (unsigned)lfind(L, s) : 0xffffu;
+        rootp[k >> 1] = (k & 1) ? (rootp[k >> 1] | (r << 16)) : r;
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (root[i] >= 0) L[(ry + 8 * i) * 32 + cx] = root[i];
-    __syncthreads();
-}
-
-// GEOM: some entry of the launch has walls or obstacles; the periodic,
-// unobstructed instance carries none of their tests.
-template <bool GEOM>
-__global__ __launch_bounds__(DV_BLOCK) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
-    const int e = entry_of(G.tbase, G.tpe, G.n, blockIdx.x);
-    const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
-    __shared__ int L[DV_TILE_SITES];
-    __shared__ uint32_t rowm[DV_TILE];
-    __shared__ uint16_t slot_of[DV_TILE_SITES];   // piece slot of each piece root
-    __shared__ int npc;
-    const int tile = blockIdx.x - G.tbase[e];
-    const int tx = tile % B.ntx, ty = tile / B.ntx;
-    const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
-    const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
-    const int t = threadIdx.x;
-    FrameState *fs = B.fs;
-
-    // per-frame resets spread over the grid
-    if (tile == 0 && t == 0) {
-        fs->K_now = 0;
-        fs->err = 0;
-        fs->n_amb = 0;
-        fs->E2_acc = 0;
-        fs->excl_acc = 0;
-        fs->nb_acc = 0;
-        fs->na_acc = 0;
+    for (int k = 0; k < 16; ++k) {
+        const unsigned r = (rootp[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+        if (r != 0xffffu) L[(h + 2 * k) * 32 + cx] = (int)r;
     }
-    if (t == 0) {
-        B.cell_count[tile] = 0;
-        npc = 0;
-    }
-    if (t < th) gmem(B.seg_mask)[(size_t)(y0 + t) * B.ntx + tx] = 0u;
-    {   // empty the rows this frame will fill
-        const size_t total = (size_t)fs->rows_dirty * B.maxdeg;
-        const size_t stride = (size_t)B.ncells * DV_BLOCK;
-        auto adj = gmem(B.cur.adj);
-        for (size_t i = (size_t)tile * DV_BLOCK + t; i < total; i += stride) adj[i] = DV_EMPTY;
-    }
-
-    tile_ccl<GEOM>(B, F.p[e], x0, y0, tw, th, L, rowm);
-
-    const int cx = t & 31, ry = t >> 5;
-    // piece roots take their slots in the tile's piece list
+    wave_sync();
+    // piece roots (L[s] == s) take consecutive slots in the tile's piece list
+    // (a wave prefix); the slot goes into bits 16.. of the root's entry
+    int npc = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
-        if (L[s] != s) continue;
-        const int slot = atomicAdd(&npc, 1);
-        slot_of[s] = (uint16_t)slot;
-        gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
-        const int g = (y0 + y) * B.lx + x0 + cx;
-        gmem(B.parent)[g] = g;
+    for (int k = 0; k < 16; ++k) {
+        const int y = h + 2 * k, s = y * 32 + cx;
+        const bool pr = L[s] == s;
+        const unsigned long long bal = __ballot(pr);
+        if (pr) {
+            const int slot = npc + __popcll(bal & below);
+            L[s] = s | (slot << 16);
+            gmem(B.pieces)[(size_t)tile * DV_TILE_SITES + slot] = (uint16_t)s;
+            const int g = (y0 + y) * B.lx + x0 + cx;
+            gmem(B.parent)[g] = g;
+        }
+        npc += __popcll(bal);
     }
-    __syncthreads();
+    wave_sync();
     // the 16-bit map holds each inside site's piece slot, the border array
     // each border site's piece root (an outside site is marked, so that
     // merging needs no field)
     auto bp = gmem(B.bpc) + (size_t)tile * DV_BORDER;
+    auto lab = gmem(B.lab16) + (size_t)tile * DV_TILE_SITES;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = ry + 8 * i, s = y * 32 + cx;
-        int r = L[s];
-        if (r >= 0) r = L[r];   // the run start's root
+    for (int k = 0; k < 16; ++k) {
+        const int y = h + 2 * k, s = y * 32 + cx;
+        int r = L[s], slot = 0xffff;
+        if (r >= 0) {
+            r = L[r & 0xffff] & 0xffff;   // the run start's root
+            slot = L[r] >> 16;
+        }
         if (cx >= tw || y >= th) continue;
-        gmem(B.lab16)[(size_t)tile * DV_TILE_SITES + y * 32 + cx] = r < 0 ? (uint16_t)0xffff : slot_of[r];
-        const uint16_t v = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
-        if (y == 0) bp[cx] = v;
-        if (y == th - 1) bp[DV_TILE + cx] = v;
-        if (cx == 0) bp[2 * DV_TILE + y] = v;
-        if (cx == tw - 1) bp[3 * DV_TILE + y] = v;
+        lab[y * 32 + cx] = (uint16_t)slot;
+        const uint16_t bv = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
+        if (y == 0) bp[cx] = bv;
+        if (y == th - 1) bp[DV_TILE + cx] = bv;
+        if (cx == 0) bp[2 * DV_TILE + y] = bv;
+        if (cx == tw - 1) bp[3 * DV_TILE + y] = bv;
     }
-    if (t == 0) B.npieces[tile] = npc;
+    if (lane == 0) B.npieces[tile] = npc;
 }
 
 // Unions between inside sites of neighbouring tiles (the border arrays hold
@@ -737,8 +751,8 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
 
 void launch_label(const Batch &G, const Fields &F, hipStream_t s, Prof &P) {
     P.begin(ST_TILE_CCL, s);
-    if (G.geom) hipLaunchKernelGGL(k_tile_ccl<true>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
-    else hipLaunchKernelGGL(k_tile_ccl<false>, dim3(G.tiles), dim3(DV_BLOCK), 0, s, G.D, G, F);
+    if (G.geom) hipLaunchKernelGGL(k_tile_ccl<true>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G, F);
+    else hipLaunchKernelGGL(k_tile_ccl<false>, dim3((G.tiles + 3) / 4), dim3(256), 0, s, G.D, G, F);
     P.end(ST_TILE_CCL, s);
     P.begin(ST_MERGE, s);
     const int merge_blocks = (G.tiles + 4 * MERGE_TILES - 1) / (4 * MERGE_TILES);
