@@ -33,7 +33,8 @@ MAXLINK = 0x77777777
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# (DV_ORACLE_LIB: another build of the oracle, for the mutation probe of the pins)
+_LIB = os.environ.get("DV_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _i32p = ctypes.POINTER(ctypes.c_int32)

@@ -131,6 +131,29 @@ def test_t_junction_links_all_three_cells():
     assert set(map(tuple, ab.tolist())) == {(0, 1), (0, 2), (1, 2)}
 
 
+def test_first_neighbour_rule_needs_its_long_diagonal():
+    """Worked example of the first-neighbour rule of Sec. 3.2.2 (reading 9):
+    a vertex site v of colour A links to its neighbour spx only when the
+    long diagonal spy / smypx is split.  Background C; A = v = (5, 5), its
+    left neighbour and the site below it; B = the single site right of v.
+    v's frame, cyclic from spx: B, C, C, C, A, C, A, C (six gaps, a vertex);
+    spx = B, but spy = smypx = C, so v does not link A to B (a rule checking
+    spy against smy, or no diagonal at all, would).  The other vertex sites
+    of colour A or B cannot link them either: the site below v has B at
+    spxpy, but its inner point (5.5, 4.5) is nearest to the centre placed
+    there for C, so the second-neighbour rule does not fire; the other A
+    site and the B site see two gaps only.  A and C are linked (spy of v)."""
+    L = 12
+    m = np.full((L, L), 2, np.int32)          # C
+    m[5, 5] = m[5, 4] = m[4, 5] = 0          # A: v, its left neighbour, the site below
+    m[5, 6] = 1                              # B: right of v
+    qx = np.array([256 * 4 + 128, 256 * 6, 256 * 5 + 128], np.int32)
+    qy = np.array([256 * 5, 256 * 5, 256 * 4 + 128], np.int32)
+    ab = set(map(tuple, oracle.edges(L, L, qx, qy, m).tolist()))
+    assert (0, 1) not in ab
+    assert (0, 2) in ab
+
+
 def test_short_diagonal_condition_blocks_link_across_thin_band():
     """Colours by (x + y) mod 24: 0 | one-site diagonal band 1 | 2 | band 3.
     Cells 0 and 2 are diagonal lattice neighbours across band 1; the fourth
