@@ -154,7 +154,9 @@ __device__ __forceinline__ int run_start(uint32_t m, int x) {
 // accesses, so the four tiles of a block overlap their latencies.
 template <bool GEOM>
 __global__ __launch_bounds__(256, 8) void k_tile_ccl(const Bufs *__restrict__ D, Batch G, Fields F) {
-    const int gt = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // (the same for every lane of the wave: read once, so that the slot's
+    // fields are loaded into scalar registers)
+    const int gt = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (gt >= G.tiles) return;   // a whole wave; there is no block barrier below
     const int e = entry_of(G.tbase, G.tpe, G.n, gt);
     const Bufs B = D[G.idx[e]];   // (a copy: the loads are not repeated after stores)
@@ -425,7 +427,7 @@ __device__ __forceinline__ void border_pairs(const Bufs &B, int tile, int lane, 
 #define MERGE_TILES 2
 template <bool GEOM>
 __global__ __launch_bounds__(256) void k_merge(const Bufs *__restrict__ D, Batch G) {
-    const int gt0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MERGE_TILES;
+    const int gt0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * MERGE_TILES);
     if (gt0 >= G.tiles) return;
     const int lane = threadIdx.x & 63;
     int ps[MERGE_TILES], pu[MERGE_TILES][3];
