@@ -26,6 +26,58 @@ __device__ __forceinline__ void st_int2(int2 *p, size_t i, int a, int b) {
         (unsigned long long)(unsigned)a | ((unsigned long long)(unsigned)b << 32);
 }
 
+// ---- wave-wide operations through DPP lane moves --------------------------
+// (every lane of the wave must be active).  Lane moves within rows of 16
+// lanes (row_shr), then the last lane of a row broadcast into the rows above
+// it (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3); lanes
+// without a source take the identity.  The control codes are those of the
+// GFX9 data-parallel primitives.
+#define DPP_ROW_SHR(n) (0x110 + (n))
+#define DPP_WAVE_SHR1 0x138
+#define DPP_ROW_BCAST15 0x142
+#define DPP_ROW_BCAST31 0x143
+
+// inclusive prefix sum over the lanes of the wave
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR(1), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR(2), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR(4), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR(8), 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST31, 0xc, 0xf, false);
+    return x;
+}
+
+// value of the last lane (a scalar)
+__device__ __forceinline__ int wave_last(int x) { return __builtin_amdgcn_readlane(x, 63); }
+
+// one step of wave_min_u64: the minimum with the value CTRL moves in
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long min_step_u64(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(-1, (int)(unsigned)v, CTRL, ROWS, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(-1, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, false);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    return o < v ? o : v;
+}
+
+// minimum over the lanes of the wave, in every lane (unsigned 64-bit)
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+    v = min_step_u64<DPP_ROW_SHR(1), 0xf>(v);
+    v = min_step_u64<DPP_ROW_SHR(2), 0xf>(v);
+    v = min_step_u64<DPP_ROW_SHR(4), 0xf>(v);
+    v = min_step_u64<DPP_ROW_SHR(8), 0xf>(v);
+    v = min_step_u64<DPP_ROW_BCAST15, 0xa>(v);
+    v = min_step_u64<DPP_ROW_BCAST31, 0xc>(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// value of the previous lane of the wave (lane 0: `first`)
+__device__ __forceinline__ int wave_prev(int x, int first) {
+    return __builtin_amdgcn_update_dpp(first, x, DPP_WAVE_SHR1, 0xf, 0xf, false);
+}
+
 // v in (-M, M) -> signed minimum image in [-M/2, M/2 - 1]  (M = 256 L, even)
 __device__ __forceinline__ int wrap_q(int v, int M) {
     const int h = M >> 1;
@@ -228,11 +280,7 @@ __device__ int block_exclusive_scan(const int *in, int *out, int n, int *wsum /*
     for (int c0 = 0; c0 < n; c0 += blockDim.x) {
         const int i = c0 + t;
         const int v = i < n ? in[i] : 0;
-        int x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = wave_incl_sum(v);
         __syncthreads();
         if (lane == 63) wsum[wid] = x;
         __syncthreads();
@@ -266,11 +314,7 @@ __device__ int block_exclusive_scan_wide(const int *in, int *out, int n, int *ws
             v[k] = b + k < e ? in[b + k] : 0;
             sum += v[k];
         }
-        int x = sum;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = wave_incl_sum(sum);
         __syncthreads();
         if (lane == 63) wsum[wid] = x;
         __syncthreads();

@@ -344,12 +344,13 @@ __device__ __forceinline__ void merge_line(gint *P, int ps, const int pu[3], boo
         a[k] = use ? ps : -1;
         b[k] = use ? pu[k] : -1;
     }
-    // the previous thread's pairs (lanes 0 and 32 start a line)
+    // the previous thread's pairs (lanes 0 and 32 start a line: what they
+    // receive is not used)
     int pa[3], pb[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        pa[k] = __shfl_up(a[k], 1, 32);
-        pb[k] = __shfl_up(b[k], 1, 32);
+        pa[k] = wave_prev(a[k], -1);
+        pb[k] = wave_prev(b[k], -1);
     }
     const bool first = (lane & 31) == 0;
 #pragma unroll
@@ -492,11 +493,7 @@ __global__ __launch_bounds__(1024) void k_resolve(const Bufs *__restrict__ D, Ba
     for (int c0 = 0; c0 < n; c0 += blockDim.x) {
         const int i = c0 + t;
         const int v = i < n ? __popc(B.seg_mask[base + i]) : 0;
-        int x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const int x = wave_incl_sum(v);
         __syncthreads();
         if (lane == 63) wsum[wid] = x;
         __syncthreads();
@@ -654,11 +651,7 @@ __global__ __launch_bounds__(DV_BLOCK) void k_relabel(const Bufs *__restrict__ D
         const uint32_t m = t < 32 ? rowm[t] : 0u;
         uint32_t st = m & ~(m << 1);
         const int c = __popc(st);
-        int x = c;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(x, o, 64);
-            if (lane >= o) x += v;
-        }
+        const int x = wave_incl_sum(c);
         for (int k = x - c; st; ++k) {
             runs[k] = (uint16_t)((t << 5) | (__ffs(st) - 1));
             st &= st - 1;

@@ -242,11 +242,7 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
         // exclusive scan of the counts (nrng <= RCAP / 2 * 2 <= blockDim)
         {
             const int lane = t & 63, wid = t >> 6;
-            int x = cnt;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
+            const int x = wave_incl_sum(cnt);
             if (lane == 63) S.wsum[wid] = x;
             __syncthreads();
             int before = 0;
@@ -567,12 +563,8 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 e0 = cs[celly * B.ntx + sx0.lo(c)];
                 cnt = cs[celly * B.ntx + sx0.hi(c) + 1] - e0;
             }
-            int inc = cnt;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(inc, o, 64);
-                if (t >= o) inc += y;
-            }
-            const int total = __shfl(inc, 63, 64);
+            const int inc = wave_incl_sum(cnt);
+            const int total = wave_last(inc);
             const int pre = inc - cnt;
             unsigned long long dmin = ~0ull;
             // the lane's item of the first 64 stays in registers; later ones
@@ -584,7 +576,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 const int f = f0 + t;
                 // range of item f: the last one whose exclusive prefix is <= f
                 int r = 0;
-                for (int k = 1; k < nrng; ++k) r = __shfl(pre, k, 64) <= f ? k : r;
+                for (int k = 1; k < nrng; ++k) r = __builtin_amdgcn_readlane(pre, k) <= f ? k : r;
                 const int e = __shfl(e0, r, 64) + f - __shfl(pre, r, 64);
                 if (f < total) {
                     const int2 q = ld_int2(B.cell_q, e);
@@ -602,10 +594,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                     }
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                const unsigned long long other = __shfl_xor(dmin, o, 64);
-                dmin = other < dmin ? other : dmin;
-            }
+            dmin = wave_min_u64(dmin);
             // the bound covers the candidates' radius: the list is built here
             bool fast = dmin != ~0ull && total <= TMP_CAP;
             double rq2 = 0.0;
@@ -639,11 +628,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                         image_masks(rx, ry, mxk, myk);
                     }
                     const int c = __popc(mxk) * __popc(myk);
-                    int x = c;
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const int y = __shfl_up(x, o, 64);
-                        if (t >= o) x += y;
-                    }
+                    const int x = wave_incl_sum(c);
                     int slot = nc + x - c;
                     for (unsigned a = mxk; a; a &= a - 1) {
                         const int cx = rx + (__ffs(a) - 2) * MX;
@@ -656,7 +641,7 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                             ++slot;
                         }
                     }
-                    nc += __shfl(x, 63, 64);
+                    nc += wave_last(x);
                 }
                 if (t == 0) S.ncand = nc;
             }
@@ -784,15 +769,13 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     // second-neighbour rules of frame direction r (spx, spy, smx, smy rotated
     // by quarter turns).  A second-neighbour candidate goes to the mask of
     // the thread owning the site (bit 4i + r), read back below.
-    S.pendw[t] = 0u;
-    {
-        const int cnt = __popc(vmask);
-        int inc = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += v;
-        }
-        const int total = __shfl(inc, 63, 64);
+    // (a wave without vertex sites, the usual case, skips both steps)
+    const int vcnt = __popc(vmask);
+    const int vinc = wave_incl_sum(vcnt);
+    const int vtotal = wave_last(vinc);
+    if (vtotal > 0) {
+        S.pendw[t] = 0u;
+        const int cnt = vcnt, inc = vinc, total = vtotal;
         for (int p0 = 0; p0 < total; p0 += 16) {
             const int item = min(p0 + (lane >> 2), total - 1), r = lane & 3;
             // lane holding the item: the first one whose inclusive count exceeds it
@@ -815,21 +798,16 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                     atomicOr(&S.pendw[tl], 1u << (4 * i + r));
             }
         }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const unsigned pend = S.pendw[t];   // bit 4i + r: site i needs the colour of inner-frame point r
-    // Inner-frame queries, which are few: numbered within the wave (a wave
-    // prefix of the per-lane counts) and answered one per lane, 64 at a time.
-    {
-        const int cnt = __popc(pend);
-        int inc = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += v;
-        }
-        const int total = __shfl(inc, 63, 64);
-        for (int p0 = 0; p0 < total; p0 += 64) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const unsigned pend = S.pendw[t];   // bit 4i + r: site i needs the colour of inner-frame point r
+        // Inner-frame queries, which are few: numbered within the wave (a wave
+        // prefix of the per-lane counts) and answered one per lane, 64 at a time.
+        const int qcnt = __popc(pend);
+        const int qinc = wave_incl_sum(qcnt);
+        const int qtotal = wave_last(qinc);
+        for (int p0 = 0; p0 < qtotal; p0 += 64) {
+            const int cnt = qcnt, inc = qinc, total = qtotal;
             const int item = min(p0 + lane, total - 1);
             // lane holding the item: the first one whose inclusive count exceeds it
             int L = 0;
