@@ -299,15 +299,26 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     // window sites of this thread: exact tile-relative Q.8 coordinates
     // (best value, owner) of the thread's window sites w = t + 256 i; the
     // site coordinates are rebuilt where needed (w / W by a multiply: w <
-    // 1280 and W <= 34, so the 16-bit reciprocal is exact)
+    // 1280 and W <= 34, so the 16-bit reciprocal is exact).  The float64
+    // values are set by the first evaluation that uses them.
     double be[WSITES];
     int bl[WSITES];
     const int wmagic = (65536 + W - 1) / W;
 #pragma unroll
-    for (int i = 0; i < WSITES; ++i) {
-        be[i] = 1.0e300;
-        bl[i] = DV_EMPTY;
-    }
+    for (int i = 0; i < WSITES; ++i) bl[i] = DV_EMPTY;
+    // the same sites as packed pairs wx | wy << 16: the first by the
+    // reciprocal, each next one by adding 256 = wq W + wr (with a carry into
+    // the row when wx reaches W)
+    const int wq = DV_BLOCK / W, wr = DV_BLOCK - wq * W;
+    auto site_pairs = [&](int P[WSITES]) {
+        const int wy0 = (t * wmagic) >> 16;
+        P[0] = (t - wy0 * W) | (wy0 << 16);
+#pragma unroll
+        for (int i = 1; i < WSITES; ++i) {
+            const int q = P[i - 1] + (wr | (wq << 16));
+            P[i] = (q & 0xffff) >= W ? q + (1 << 16) - W : q;
+        }
+    };
     if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; S.nkeep = 0; S.imode = 0; }
     __syncthreads();
 
@@ -407,14 +418,8 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         }
         __syncthreads();
         const bool im = last && S.nchunks == 0 && !S.far;
-        for (int c = t; c < nc; c += DV_BLOCK) {
-            if (!S.keep[c]) continue;
-            const int lab = S.lab[c];
-            int r = 0;
-            for (int j = 0; j < nc; ++j) {
-                const int l2 = S.lab[j];
-                r += (S.keep[j] && (l2 < lab || (l2 == lab && j < c))) ? 1 : 0;
-            }
+        // kept candidate c with label lab goes to position r of the ordered list
+        auto place = [&](int c, int r, int lab) {
             const int ix = S.cx[c], iy = S.cy[c];
             if (im) {
                 S.ixy[r] = (int)(((unsigned)iy << 16) | ((unsigned)ix & 0xffffu));
@@ -426,6 +431,33 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
                 S.sk[r] = x * x + y * y;
             }
             S.sl[r] = lab;
+        };
+        if (nc <= 64) {
+            // the first wave, lane c holding candidate c: its position counts
+            // the kept candidates before it by (label, index), visited one
+            // kept candidate at a time
+            if (t < 64) {
+                const bool kc = t < nc && S.keep[t];
+                const int lab = t < nc ? S.lab[t] : 0;
+                int r = 0;
+                for (unsigned long long m = __ballot(kc); m; m &= m - 1) {
+                    const int j = (int)__builtin_ctzll(m);
+                    const int l2 = __builtin_amdgcn_readlane(lab, j);
+                    r += (l2 < lab || (l2 == lab && j < t)) ? 1 : 0;
+                }
+                if (kc) place(t, r, lab);
+            }
+        } else {
+            for (int c = t; c < nc; c += DV_BLOCK) {
+                if (!S.keep[c]) continue;
+                const int lab = S.lab[c];
+                int r = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const int l2 = S.lab[j];
+                    r += (S.keep[j] && (l2 < lab || (l2 == lab && j < c))) ? 1 : 0;
+                }
+                place(c, r, lab);
+            }
         }
         if (t == 0) S.imode = im ? 1 : 0;
         __syncthreads();
@@ -437,12 +469,15 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
             // with exact 32-bit accumulation
             sh2 m2[WSITES];
             int bi[WSITES];
+            {
+                int P[WSITES];
+                site_pairs(P);
 #pragma unroll
-            for (int i = 0; i < WSITES; ++i) {
-                const int w = t + i * DV_BLOCK;
-                const int wy = (w * wmagic) >> 16, wx = w - wy * W;
-                m2[i] = sh2{(short)(-512 * (wx - 1)), (short)(-512 * (wy - 1))};
-                bi[i] = INT_MAX;
+                for (int i = 0; i < WSITES; ++i) {
+                    // (-512 (wx - 1), -512 (wy - 1)) = ((1, 1) - (wx, wy)) * 512
+                    m2[i] = (sh2{1, 1} - __builtin_bit_cast(sh2, P[i])) * (short)512;
+                    bi[i] = INT_MAX;
+                }
             }
             // candidates in order, two per step (the compiler does not unroll
             // a loop around inline assembly)
@@ -475,6 +510,8 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
             m2y[i] = -512.0 * (wy - 1);
         }
         if (S.nchunks == 0) {
+#pragma unroll
+            for (int i = 0; i < WSITES; ++i) be[i] = 1.0e300;
             for (int c = 0; c < nk; ++c) {
                 const double cx = S.sx[c], cy = S.sy[c], kk = S.sk[c];
                 const int lab = S.sl[c];
@@ -695,7 +732,13 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         }
         eval_owners(true, done);
     }
-    // window sites with no colour: beyond a wall, and obstacles
+    // window sites with no colour: beyond a wall, and obstacles.  (Without
+    // either, a window 34 sites wide is stored as it is numbered.)
+    if (!GEOM && W == 34) {
+#pragma unroll
+        for (int i = 0; i < WSITES; ++i)
+            if (t + i * DV_BLOCK < W * H) S.own[t + i * DV_BLOCK] = bl[i];
+    } else
 #pragma unroll
     for (int i = 0; i < WSITES; ++i) {
         const int w = t + i * DV_BLOCK;
