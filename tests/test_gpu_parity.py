@@ -162,6 +162,23 @@ def test_wrapping_strip_and_checkerboard():
     run_sequence([strip, cb, strip], 0.5, 0, 8, tag="strip/cb8")
 
 
+def test_tiles_with_hundreds_of_pieces():
+    """Tiles holding 253, 254, 255 and 256 pieces (isolated sites two apart),
+    then a 4-connected checkerboard (512 pieces a tile, the most a tile can
+    hold) below them: piece slots and ranks beyond one byte and beyond the
+    first 64 slots of a tile."""
+    lx, ly = 128, 64
+    f = np.zeros((ly, lx), np.float32)
+    for tile, n in enumerate((253, 254, 255, 256)):
+        idx = np.arange(n)
+        f[2 * (idx // 16), 32 * tile + 2 * (idx % 16)] = 1.0
+    yy, xx = np.mgrid[0:32, 0:lx]
+    cb = f.copy()
+    cb[32:, :] = ((xx + yy) % 2).astype(np.float32)
+    run_sequence([f, cb, f], 0.5, 0, 4, tag="slots4")
+    run_sequence([f, cb, f], 0.5, 0, 8, tag="slots8")
+
+
 def test_threshold_equality_and_nan_are_outside():
     rng = np.random.default_rng(9)
     f = rng.random((48, 40)).astype(np.float32)
