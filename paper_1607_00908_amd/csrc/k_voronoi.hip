@@ -786,6 +786,29 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     const bool keep_maps = B.keep_maps;
     const auto orow = gmem(B.owner) + ((size_t)(y0 + ys) * lx + x0 + cx);
     unsigned vmask = 0;
+    if (!GEOM) {
+        // The frame of the site in row ys + i is the border of rows i .. i + 2
+        // of the block: its gaps are the changes along rows i and i + 2 and
+        // down columns 0 and 2 (rows i to i + 1 and i + 1 to i + 2), each
+        // change counted once for the thread's four sites.  (Without walls
+        // and obstacles no frame point is MAXLINK once the site has a colour:
+        // there is a centre, so every point has one.)
+        int hr[6], vc[5];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) hr[a] = (g[a][0] != g[a][1] ? 1 : 0) + (g[a][1] != g[a][2] ? 1 : 0);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) vc[a] = (g[a][0] != g[a + 1][0] ? 1 : 0) + (g[a][2] != g[a + 1][2] ? 1 : 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = ys + i;
+            if (cx >= tw || y >= th) continue;
+            const int ckk = g[i + 1][1];
+            if (keep_maps) orow[(size_t)i * lx] = ckk;
+            // (with no centre every colour is MAXLINK and there are no gaps)
+            const int gaps = hr[i] + hr[i + 2] + vc[i] + vc[i + 1];
+            vmask |= gaps >= 3 ? 1u << i : 0u;
+        }
+    } else
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int y = ys + i;
@@ -796,13 +819,12 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         int f[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) f[k] = g[i + 1 + fry(k)][1 + frx(k)];
-        // (without walls and obstacles no frame point is MAXLINK once the site
-        // has a colour: there is a centre, so every point has one)
+        // (a change next to a point without colour is no gap)
         int gaps = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int a = f[k], b = f[(k + 1) & 7];
-            gaps += (a != b && (!GEOM || (a != DV_EMPTY && b != DV_EMPTY))) ? 1 : 0;
+            gaps += (a != b && a != DV_EMPTY && b != DV_EMPTY) ? 1 : 0;
         }
         vmask |= gaps >= 3 ? 1u << i : 0u;
     }
