@@ -305,21 +305,36 @@ __global__ __launch_bounds__(256, 8) void k_tile_ccl(const Bufs *__restrict__ D,
     // merging needs no field)
     auto bp = gmem(B.bpc) + (size_t)tile * DV_BORDER;
     auto lab = gmem(B.lab16) + (size_t)tile * DV_TILE_SITES;
+    // site -> its run start -> the start's root -> the root's slot, without
+    // branches (an outside site follows itself), so that the reads of the
+    // sixteen sites are in flight together
+    unsigned rootq[8];   // piece roots of sites 2j and 2j + 1 in the low / high half (0xffff: outside)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int y = h + 2 * k, s = y * 32 + cx;
-        int r = L[s], slot = 0xffff;
-        if (r >= 0) {
-            r = L[r & 0xffff] & 0xffff;   // the run start's root
-            slot = L[r] >> 16;
-        }
-        if (cx >= tw || y >= th) continue;
-        lab[y * 32 + cx] = (uint16_t)slot;
-        const uint16_t bv = r < 0 ? (uint16_t)0xffff : (uint16_t)r;
-        if (y == 0) bp[cx] = bv;
-        if (y == th - 1) bp[DV_TILE + cx] = bv;
-        if (cx == 0) bp[2 * DV_TILE + y] = bv;
-        if (cx == tw - 1) bp[3 * DV_TILE + y] = bv;
+        const int v0 = L[s];
+        const bool in = v0 >= 0;
+        const int i1 = in ? (v0 & 0xffff) : s;
+        const int i2 = in ? (L[i1] & 0xffff) : s;
+        const int v2 = L[i2];
+        const unsigned r = in ? (unsigned)i2 : 0xffffu;
+        rootq[k >> 1] = (k & 1) ? (rootq[k >> 1] | (r << 16)) : r;
+        if (cx < tw && y < th) lab[y * 32 + cx] = in ? (uint16_t)((unsigned)v2 >> 16) : (uint16_t)0xffff;
+    }
+    wave_sync();
+    // every site's piece root into the table (0xffff outside, also beyond a
+    // ragged tile's edge), then the border array as two whole lines per
+    // lane: top and bottom row, left and right column
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        L[(h + 2 * k) * 32 + cx] = (int)((rootq[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+    wave_sync();
+    {
+        const int c = lane & 31;
+        const int a = h == 0 ? L[c] : L[(th - 1) * 32 + c];
+        const int b = h == 0 ? L[c * 32] : L[c * 32 + tw - 1];
+        bp[lane] = (uint16_t)a;
+        bp[2 * DV_TILE + lane] = (uint16_t)b;
     }
     if (lane == 0) B.npieces[tile] = npc;
 }
