@@ -281,18 +281,36 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
     const Bufs &B = D[G.idx[e]];
     const int tile = blockIdx.x - G.tbase[e];
     __shared__ OwnerLds S;
-    FrameState *fs = B.fs;
-    if (fs->err) return;
-    const int K = fs->K_now;
-    gint *adj = gmem(B.cur.adj);
     const int tx = tile % B.ntx, ty = tile / B.ntx;
+    const bool ox = GEOM && B.open_x, oy = GEOM && B.open_y;
+    // The usual candidate search reads the centres of the 7 x 7 cells around
+    // the tile: first the bounds of their cell ranges (each row of cells of a
+    // column span is one contiguous range of the cell-ordered arrays, at
+    // most 7 x 2 ranges, a lane each in the first wave), then the centres.
+    // The bounds are requested before anything else, so that their round
+    // trip overlaps the frame header's.
+    const int R0 = 3;
+    const Span sx0 = span_cells(tx, R0, B.ntx, ox), sy0 = span_cells(ty, R0, B.nty, oy);
+    const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
+    const int nrng = ncy * sx0.n;
+    int rb0 = 0, rb1 = 0;
+    if ((int)threadIdx.x < nrng) {
+        const int iy = threadIdx.x / sx0.n, c = threadIdx.x - iy * sx0.n;
+        const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
+        const auto cs = gmem(B.cell_start);
+        rb0 = cs[celly * B.ntx + sx0.lo(c)];
+        rb1 = cs[celly * B.ntx + sx0.hi(c) + 1];
+    }
+    FrameState *fs = B.fs;
+    if (*gmem(&fs->err)) return;
+    const int K = *gmem(&fs->K_now);
+    gint *adj = gmem(B.cur.adj);
     const int x0 = tx * DV_TILE, y0 = ty * DV_TILE;
     const int tw = min(DV_TILE, B.lx - x0), th = min(DV_TILE, B.ly - y0);
     const int W = tw + 2, H = th + 2;
     const int t = threadIdx.x, lx = B.lx, ly = B.ly;
     // wrap periods (Q.8): the lattice period of a periodic axis; on a walled
     // axis a period that no distance reaches (images are not used there)
-    const bool ox = GEOM && B.open_x, oy = GEOM && B.open_y;
     const int MX = qperiod(lx, ox), MY = qperiod(ly, oy);
     const int OX = 256 * x0, OY = 256 * y0;   // tile origin (Q.8); coordinates below are relative
 
@@ -319,8 +337,9 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
             P[i] = (q & 0xffff) >= W ? q + (1 << 16) - W : q;
         }
     };
+    // (the first wave reads these in program order, the others only after a
+    // later barrier)
     if (t == 0) { S.ncand = 0; S.nchunks = 0; S.best = ~0ull; S.npair = 0; S.ntmp = 0; S.nout = 0; S.nkeep = 0; S.imode = 0; }
-    __syncthreads();
 
     // tile centre (absolute Q.8) and the window's relative x / y extent
     const int tcx = OX + 128 * (tw - 1), tcy = OY + 128 * (th - 1);
@@ -582,24 +601,11 @@ __global__ __launch_bounds__(DV_BLOCK, 8) void k_owner_edges(const Bufs *__restr
         // tile give a bound (nearest centre seen) and, when they cover the
         // radius it implies, every candidate as well; the other waves wait at
         // the barrier
-        const int R0 = 3;
-        const Span sx0 = span_cells(tx, R0, B.ntx, ox), sy0 = span_cells(ty, R0, B.nty, oy);
         if (t < 64) {
-            // the centres of the square's cells, lane-parallel: each row of
-            // cells of a column span is one contiguous range of the cell-ordered
-            // arrays, so the lanes load the (at most 7 x 2) range bounds, then
-            // one centre per lane over the concatenated ranges (two dependent
-            // load rounds); the bound is one wave minimum
-            const int n0y = sy0.hi0 - sy0.lo0 + 1, ncy = n0y + (sy0.n == 2 ? sy0.hi1 - sy0.lo1 + 1 : 0);
-            const int nrng = ncy * sx0.n;
-            int e0 = 0, cnt = 0;
-            if (t < nrng) {
-                const int iy = t / sx0.n, c = t - iy * sx0.n;
-                const int celly = iy < n0y ? sy0.lo0 + iy : sy0.lo1 + (iy - n0y);
-                const auto cs = gmem(B.cell_start);
-                e0 = cs[celly * B.ntx + sx0.lo(c)];
-                cnt = cs[celly * B.ntx + sx0.hi(c) + 1] - e0;
-            }
+            // the centres of the square's cells, lane-parallel: one centre per
+            // lane over the concatenated ranges whose bounds were requested
+            // at the start; the bound is one wave minimum
+            const int e0 = rb0, cnt = rb1 - rb0;
             const int inc = wave_incl_sum(cnt);
             const int total = wave_last(inc);
             const int pre = inc - cnt;
