@@ -305,8 +305,10 @@ __device__ __forceinline__ void copy_words(const int2 *__restrict__ src, int2 *_
     for (; j < n; ++j) d[j] = s[j];
 }
 
+// rows per thread of k_place's one-pass form (K up to 16 x 1024 rows)
+#define PLACE_PER 16
 __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Batch G) {
-    __shared__ int wsum[16];
+    __shared__ int wsum[16], wsb2[16];
     __shared__ int s_before[2];
     const int i = blockIdx.z;
     const Bufs &B = Dt[G.idx[i]];
@@ -358,22 +360,68 @@ __global__ __launch_bounds__(1024) void k_place(const Bufs *__restrict__ Dt, Bat
         const int KN = fs->K_now;
         const PastOf PO = past_of(Dt, G, i, accepted_entries(Dt, G, B.seq));
         const int D = B.maxdeg;
-        const int nbk = block_exclusive_scan_wide<16>(B.nb, B.ob, KN, wsum);
-        __syncthreads();
-        const int nar = block_exclusive_scan_wide<16>(B.na, B.oa, KN, wsum);
-        __syncthreads();
-        for (int n = t; n < KN; n += blockDim.x) {
-            const int cb = B.nb[n], ca = B.na[n];
-            if (cb == 0 && ca == 0) continue;
+        // row n's staged flips to their places in the frame's list; records
+        // are 24 bytes, copied as 8-byte words with the loads issued together
+        auto place_row = [&](int n, int cb, int ca, int offb, int offa) {
             const int *stg = B.stage + (size_t)n * (2 * D) * 6;
-            int *fb = flips + (size_t)6 * B.ob[n];
-            int *fa = flips + (size_t)6 * (nbk + B.oa[n]);
-            // records are 24 bytes: copied as 8-byte words, loads issued together
+            int *fb = flips + (size_t)6 * offb;
+            int *fa = flips + (size_t)6 * offa;
             copy_words(reinterpret_cast<const int2 *>(stg), reinterpret_cast<int2 *>(fb), 3 * cb);
             copy_words(reinterpret_cast<const int2 *>(stg + 6 * D), reinterpret_cast<int2 *>(fa), 3 * ca);
             if (B.classify) {
                 for (int j = 0; j < cb; ++j) fb[6 * j + 5] = event_flags(B, fb[6 * j], fb[6 * j + 1], -1);
                 for (int j = 0; j < ca; ++j) fa[6 * j + 5] = event_flags(B, fa[6 * j], fa[6 * j + 1], 1);
+            }
+        };
+        int nbk, nar;
+        if (KN <= PLACE_PER * (int)blockDim.x) {
+            // one pass: thread t holds the counts of a contiguous run of rows
+            // (their loads issued together), both prefix sums are one block
+            // scan, and the copies start from the registers
+            const int per = (KN + blockDim.x - 1) / blockDim.x;
+            const int b0 = t * per, e0 = min(b0 + per, KN);
+            int vb[PLACE_PER], va[PLACE_PER];
+            int sb = 0, sa = 0;
+#pragma unroll
+            for (int k = 0; k < PLACE_PER; ++k) {
+                vb[k] = b0 + k < e0 ? gmem(B.nb)[b0 + k] : 0;
+                va[k] = b0 + k < e0 ? gmem(B.na)[b0 + k] : 0;
+                sb += vb[k];
+                sa += va[k];
+            }
+            const int lane = t & 63, wid = t >> 6, nw = blockDim.x >> 6;
+            const int xb = wave_incl_sum(sb), xa = wave_incl_sum(sa);
+            if (lane == 63) {
+                wsum[wid] = xb;
+                wsb2[wid] = xa;
+            }
+            __syncthreads();
+            int offb = xb - sb, offa = xa - sa;
+            nbk = 0;
+            nar = 0;
+            for (int w = 0; w < nw; ++w) {
+                const int pb = wsum[w], pa = wsb2[w];
+                offb += w < wid ? pb : 0;
+                offa += w < wid ? pa : 0;
+                nbk += pb;
+                nar += pa;
+            }
+            offa += nbk;   // arising flips follow every breaking one
+#pragma unroll
+            for (int k = 0; k < PLACE_PER; ++k) {
+                if ((vb[k] | va[k]) != 0) place_row(b0 + k, vb[k], va[k], offb, offa);
+                offb += vb[k];
+                offa += va[k];
+            }
+        } else {
+            nbk = block_exclusive_scan_wide<16>(B.nb, B.ob, KN, wsum);
+            __syncthreads();
+            nar = block_exclusive_scan_wide<16>(B.na, B.oa, KN, wsum);
+            __syncthreads();
+            for (int n = t; n < KN; n += blockDim.x) {
+                const int cb = B.nb[n], ca = B.na[n];
+                if (cb == 0 && ca == 0) continue;
+                place_row(n, cb, ca, B.ob[n], nbk + B.oa[n]);
             }
         }
         if (t == 0) {

@@ -103,7 +103,9 @@ __global__ __launch_bounds__(1024) void k_grid(const Bufs *__restrict__ D, Batch
     if (fs->err) return;
     const int K = fs->K_now, t = threadIdx.x;
     const CompBuf C = B.cur;
-    const int total = block_exclusive_scan(B.cell_count, B.cell_start, B.ncells, wsum);
+    // (contiguous runs of up to 16 counts per thread: one pass for up to
+    // 16384 cells)
+    const int total = block_exclusive_scan_wide<16>(B.cell_count, B.cell_start, B.ncells, wsum);
     if (t == 0) B.cell_start[B.ncells] = total;
     __syncthreads();
 #pragma unroll 4
