@@ -27,10 +27,6 @@
 
 namespace {
 
-__device__ __forceinline__ bool is_in(float v, float thr, int phase) {
-    return phase == 0 ? (v > thr) : (v < thr);
-}
-
 // ---- union-find in LDS over tile-local indices -----------------------------
 // Every parent is a smaller index than its child, so walks end at a root.
 // Finds shorten the path they walk with plain stores (path splitting: a node

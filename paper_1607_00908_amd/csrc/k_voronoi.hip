@@ -250,7 +250,7 @@ __device__ void visit_items(const Bufs &B, OwnerLds &S, const Span &sx, const Sp
             int before = 0;
             for (int w = 0; w < wid; ++w) before += S.wsum[w];
             if (t < RCAP) S.r_pre[t] = before + x - cnt;
-            if (t == blockDim.x - 1) S.r_pre[RCAP] = before + x;
+            if (t == (int)blockDim.x - 1) S.r_pre[RCAP] = before + x;
             __syncthreads();
         }
         const int total = S.r_pre[RCAP];
